@@ -1,0 +1,460 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: values the
+paper prints, closed forms, an independent construction of the same quantity
+(Pauli matrices, numerical Fourier integrals), exact diagonalisation, or a
+textbook linear solve.  None of these tests touches the GPU path.
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+from conftest import golden
+
+HB2M = 41.47
+MIN = dict(VR=200.0, kR=1.487, VT=178.0, kT=0.639, VS=-91.85, kS=0.465)
+
+
+# --------------------------------------------------------------------------
+# model space
+# --------------------------------------------------------------------------
+
+def test_state_counts_match_paper(orc):
+    """Magic numbers of Table tab:table1 and the basis sizes quoted in the
+    text (342, 1598, 610, 502 states)."""
+    big = orc.PNM(2, 33, 0.08).states()
+    shell = (big[:, :3] ** 2).sum(axis=1)
+    for nmax2, count, *_ in golden("basis_counts.txt"):
+        nmax2, count = int(nmax2), int(count)
+        # cumulative count inside a larger basis, and a basis built at that cutoff
+        assert int((shell <= nmax2).sum()) == count
+        if nmax2 >= 1:
+            # N = 2 closes the first shell for every cutoff
+            assert orc.PNM(2, nmax2, 0.08).ns == count, nmax2
+
+
+def test_shell_contents_match_table1(orc):
+    rows = golden("table1_momenta.txt")
+    want = {}
+    for n2, x, y, z in rows:
+        want.setdefault(int(n2), set()).add((int(x), int(y), int(z)))
+    st = orc.PNM(2, 3, 0.08).states()
+    got = {}
+    for x, y, z, s in st:
+        got.setdefault(int(x * x + y * y + z * z), []).append((int(x), int(y), int(z), int(s)))
+    for n2, moms in want.items():
+        assert {m[:3] for m in got[n2]} == moms
+        # every momentum appears with both spin projections
+        assert sorted(got[n2]) == sorted([m + (s,) for m in moms for s in (-1, 1)])
+
+
+def test_state_order_is_shell_then_lexicographic_then_spin(orc):
+    st = orc.PNM(14, 6, 0.08).states()
+    keys = [(x * x + y * y + z * z, x, y, z, s) for x, y, z, s in st]
+    assert keys == sorted(keys)
+
+
+@pytest.mark.parametrize("n", [3, 10, 20, 67])
+def test_non_closed_shell_rejected(orc, n):
+    with pytest.raises(ValueError):
+        orc.PNM(n, 8, 0.08)
+
+
+def test_kinetic_energy_closed_form(orc):
+    """T = hbar^2/2m (2 pi / L)^2 sum_i |n_i|^2 with L = (N/rho)^(1/3)
+    (sec. "Single-particle basis for infinite matter"); sum |n|^2 = 12 for
+    N = 14 and 156 for N = 66."""
+    for N, s, rho in [(14, 12, 0.08), (66, 156, 0.16), (66, 156, 0.02)]:
+        p = orc.PNM(N, 20, rho)
+        L = (N / rho) ** (1.0 / 3.0)
+        assert p.L == pytest.approx(L, rel=1e-15)
+        T = p.kinetic()[:N].sum()
+        assert T == pytest.approx(HB2M / 2 * (2 * math.pi / L) ** 2 * s, rel=1e-13)
+
+
+def test_kinetic_energy_approaches_infinite_matter(orc):
+    """Loose check against T_inf/N = 3 hbar^2 k_F^2 / 10 m (sec. on twist
+    averaging), k_F from rho = k_F^3 / 3 pi^2 (g = 2)."""
+    rho = 0.16
+    p = orc.PNM(66, 20, rho)
+    kf = (3 * math.pi ** 2 * rho) ** (1 / 3)
+    tinf = 3 * HB2M * kf ** 2 / 10
+    assert abs(p.kinetic()[:66].sum() / 66 - tinf) / tinf < 0.05
+
+
+# --------------------------------------------------------------------------
+# Minnesota interaction
+# --------------------------------------------------------------------------
+
+def _pauli_spin_operators():
+    """Spin operators of the three Minnesota channels built from Pauli matrices:
+    P_sigma = (1 + sigma_1 . sigma_2)/2, P_tau = +1 between neutrons."""
+    sx = np.array([[0, 1], [1, 0]], dtype=complex)
+    sy = np.array([[0, -1j], [1j, 0]], dtype=complex)
+    sz = np.array([[1, 0], [0, -1]], dtype=complex)
+    one = np.eye(4)
+    Ps = 0.5 * (one + sum(np.kron(s, s) for s in (sx, sy, sz))).real
+    ex = one - Ps  # 1 - P_sigma P_tau
+    return {"R": 0.5 * ex, "T": 0.25 * (one + Ps) @ ex, "S": 0.25 * (one - Ps) @ ex}
+
+
+def _ft_numeric(V, kappa, q):
+    """int d^3r exp(-i q.r) V exp(-kappa r^2), by radial quadrature."""
+    if q == 0.0:
+        f = lambda r: 4 * math.pi * r * r * V * math.exp(-kappa * r * r)
+    else:
+        f = lambda r: 4 * math.pi * r * r * V * math.exp(-kappa * r * r) * math.sin(q * r) / (q * r)
+    val, _ = integrate.quad(f, 0.0, 40.0, limit=400, epsabs=1e-13, epsrel=1e-13)
+    return val
+
+
+def test_minnesota_element_independent_construction(orc):
+    """<pq||rs> = <pq|v|rs> - <pq|v|sr> with the spatial part a numerical
+    Fourier integral of V_a exp(-kappa_a r^2) divided by L^3, at momentum
+    transfer q = (k_p - k_q - k_r + k_s)/2, and the spin part from Pauli
+    matrices (sec. "Two-body interaction")."""
+    p = orc.PNM(14, 4, 0.08)
+    st = p.states()
+    L = p.L
+    ops = _pauli_spin_operators()
+    pars = {"R": (MIN["VR"], MIN["kR"]), "T": (MIN["VT"], MIN["kT"]), "S": (MIN["VS"], MIN["kS"])}
+    sidx = lambda s1, s2: 2 * (s1 < 0) + (s2 < 0)  # kron order: index 0 = spin up
+
+    def vdir(a, b, c, d):
+        na, nb, nc, nd = (st[x, :3] for x in (a, b, c, d))
+        if np.any(na + nb != nc + nd):
+            return 0.0
+        q = 0.5 * (2 * math.pi / L) * (na - nb - nc + nd)
+        qn = float(np.sqrt(q @ q))
+        tot = 0.0
+        for ch, (V, k) in pars.items():
+            spin = ops[ch][sidx(st[a, 3], st[b, 3]), sidx(st[c, 3], st[d, 3])]
+            if spin != 0.0:
+                tot += _ft_numeric(V, k, qn) / L ** 3 * spin
+        return tot
+
+    rng = np.random.default_rng(7)
+    n = p.ns
+    checked = 0
+    while checked < 40:
+        a, b, c = rng.integers(0, n, 3)
+        target = st[a, :3] + st[b, :3] - st[c, :3]
+        cands = [d for d in range(n) if np.all(st[d, :3] == target)]
+        if not cands:
+            continue
+        d = cands[rng.integers(len(cands))]
+        want = vdir(a, b, c, d) - vdir(a, b, d, c)
+        got = p.v(a, b, c, d)
+        assert got == pytest.approx(want, rel=1e-9, abs=1e-12), (a, b, c, d)
+        checked += 1
+
+
+def test_minnesota_symmetries(orc):
+    p = orc.PNM(14, 4, 0.12)
+    st = p.states()
+    n = p.ns
+    rng = np.random.default_rng(3)
+    for _ in range(400):
+        a, b, c = (int(x) for x in rng.integers(0, n, 3))
+        target = st[a, :3] + st[b, :3] - st[c, :3]
+        ds = [d for d in range(n) if np.all(st[d, :3] == target)]
+        for d in ds:
+            v = p.v(a, b, c, d)
+            assert p.v(b, a, c, d) == pytest.approx(-v, abs=1e-15)
+            assert p.v(a, b, d, c) == pytest.approx(-v, abs=1e-15)
+            assert p.v(c, d, a, b) == pytest.approx(v, abs=1e-15)
+            assert p.v_fast(a, b, c, d) == pytest.approx(v, rel=1e-13, abs=1e-16)
+            if st[a, 3] == st[b, 3]:
+                # two neutrons with equal spin projection do not interact
+                assert v == 0.0
+        # momentum non-conserving elements vanish
+        e = int(rng.integers(0, n))
+        if not np.all(st[e, :3] == target):
+            assert p.v(a, b, c, e) == 0.0
+
+
+def _W(m, L):
+    """Spin-singlet strength W(m) = sum_{a=R,S} V_a/L^3 (pi/kappa_a)^{3/2}
+    exp(-(2 pi/L)^2 m / 4 kappa_a)."""
+    out = 0.0
+    for V, k in ((MIN["VR"], MIN["kR"]), (MIN["VS"], MIN["kS"])):
+        out += V / L ** 3 * (math.pi / k) ** 1.5 * math.exp(-(2 * math.pi / L) ** 2 * m / (4 * k))
+    return out
+
+
+@pytest.mark.parametrize("N,nmax2,rho", [(14, 4, 0.08), (66, 20, 0.16), (38, 12, 0.05)])
+def test_reference_and_fock_energies_closed_form(orc, N, nmax2, rho):
+    """Between two neutrons only the spin singlet interacts, so
+    E_ref = T + N^2/8 W(0) + 1/2 sum_{k,k' in FS} W(|k-k'|^2) and
+    eps_p = t_p + N/4 W(0) + 1/2 sum_{k in FS} W(|n_p-k|^2), where FS is the
+    set of N/2 occupied momenta."""
+    p = orc.PNM(N, nmax2, rho)
+    st = p.states()
+    L = p.L
+    fs = np.unique(st[:N, :3], axis=0)
+    assert len(fs) == N // 2
+    T = p.kinetic()[:N].sum()
+    acc = sum(_W(int(((k1 - k2) ** 2).sum()), L) for k1 in fs for k2 in fs)
+    eref = T + N * N / 8 * _W(0, L) + 0.5 * acc
+    assert p.eref() == pytest.approx(eref, rel=1e-12)
+    eps = p.fock()
+    tk = p.kinetic()
+    for q in list(range(0, p.ns, max(1, p.ns // 40))):
+        want = tk[q] + N / 4 * _W(0, L) + 0.5 * sum(_W(int(((st[q, :3] - k) ** 2).sum()), L) for k in fs)
+        assert eps[q] == pytest.approx(want, rel=1e-12, abs=1e-12)
+
+
+# --------------------------------------------------------------------------
+# integer structure pinned by the paper's profiles and memory estimate
+# --------------------------------------------------------------------------
+
+def test_profile_call_counts(orc):
+    """gprof call counts for 1598 states and N = 54: the block-sparse MBPT2
+    code evaluates one element per (ordered hh pair, ordered pp pair) of each
+    momentum/spin channel plus one per Fock term (p, i != p); the channel index
+    is computed twice per ordered pair; the brute-force code's 32-bit counter
+    wrapped."""
+    want = {k: int(v) for k, v in golden("profile_counts.txt")}
+    p = orc.PNM(54, 33, 0.08)
+    assert p.ns == 1598
+    o3 = orc.O3(p)
+    n_pairs = o3_count = orc.lib().orc_o3_count(o3.o)  # sum over channels n_hh * n_pp
+    assert n_pairs + (1598 * 54 - 54) == want["V_Minnesota_V02"]
+    nh, npart = 54, 1598 - 54
+    assert 2 * (nh * (nh - 1) + npart * (npart - 1)) == want["Chan_2bInd_V02"]
+    assert (nh * (nh - 1) * npart * (npart - 1)) % 2 ** 32 + (1598 * 54 - 54) == want["V_Minnesota_V06"]
+    del o3_count
+
+
+def test_block_diagonal_memory_502_states(orc):
+    """502 states stored block-diagonally by (total momentum, S_z): about
+    0.23 GB of FP64 two-body elements; naive storage of 500^4 doubles = 500 GB."""
+    st = orc.PNM(2, 14, 0.08).states()
+    assert len(st) == 502
+    count = {}
+    for a in range(502):
+        for b in range(502):
+            if a != b:
+                key = tuple(st[a, :3] + st[b, :3]) + (int(st[a, 3] + st[b, 3]),)
+                count[key] = count.get(key, 0) + 1
+    gib = sum(c * c for c in count.values()) * 8 / 2 ** 30
+    assert round(gib, 2) == 0.23
+    assert 500 ** 4 * 8 / 1e9 == 500.0
+
+
+# --------------------------------------------------------------------------
+# pairing model (sec. "Developing a CCD code for infinite matter")
+# --------------------------------------------------------------------------
+
+def _run_o1(o, alpha, tol=1e-12, max_iter=2000, mask=127):
+    e = o.ecorr
+    for _ in range(max_iter):
+        en = o.sweep(alpha, mask)
+        if abs(en - e) < tol:
+            return en
+        e = en
+    raise AssertionError("no convergence")
+
+
+@pytest.mark.parametrize("row", golden("pairing_table.txt"))
+def test_pairing_model_table(orc, row):
+    g, eref, emp2, eccd = (float(x) for x in row)
+    h, v = orc.pairing_model(g)
+    o = orc.O1(h, v, 4)
+    assert o.eref == pytest.approx(eref, abs=1e-12)
+    assert o.emp2 == pytest.approx(emp2, abs=5e-6)
+    closed = -g * g / 4 * (1 / (4 + g) + 1 / (6 + g) + 1 / (2 + g) + 1 / (4 + g))
+    assert o.emp2 == pytest.approx(closed, abs=1e-14)
+    # single-particle energies of Table tab:pairingmodelsp
+    assert np.allclose(o.eps(), [-g / 2, -g / 2, 1 - g / 2, 1 - g / 2, 2, 2, 3, 3], atol=1e-15)
+    alpha = 0.5 if g == -1.0 else 1.0
+    assert _run_o1(o, alpha) == pytest.approx(eccd, abs=5e-6)
+
+
+def test_pairing_g_minus_one_needs_mixing(orc):
+    """Without mixing the g = -1 iteration does not settle (sec. after the
+    pairing table)."""
+    h, v = orc.pairing_model(-1.0)
+    o = orc.O1(h, v, 4)
+    hist = [o.sweep(1.0) for _ in range(200)]
+    assert not all(math.isfinite(x) for x in hist) or abs(hist[-1] - hist[-2]) > 1e-6 \
+        or abs(hist[-1] - (-0.21895)) > 1e-3
+
+
+def test_pairing_fci_matrix_and_first_iteration(orc):
+    """The paper's 6x6 FCI matrix has E_ref as its first diagonal element and
+    the first CCD iteration gives MBPT2."""
+    g = 0.5
+    H = np.array([
+        [2 - g, -g / 2, -g / 2, -g / 2, -g / 2, 0],
+        [-g / 2, 4 - g, -g / 2, -g / 2, 0, -g / 2],
+        [-g / 2, -g / 2, 6 - g, 0, -g / 2, -g / 2],
+        [-g / 2, -g / 2, 0, 6 - g, -g / 2, -g / 2],
+        [-g / 2, 0, -g / 2, -g / 2, 8 - g, -g / 2],
+        [0, -g / 2, -g / 2, -g / 2, -g / 2, 10 - g]])
+    h, v = orc.pairing_model(g)
+    o = orc.O1(h, v, 4)
+    assert H[0, 0] == pytest.approx(o.eref)
+    eccd = _run_o1(o, 1.0)
+    exact = np.linalg.eigvalsh(H)[0] - H[0, 0]
+    # CCD is close to, not equal to, the exact answer for four particles
+    assert abs(eccd - exact) < 0.01 * abs(exact)
+
+
+# --------------------------------------------------------------------------
+# exact results: two neutrons
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("nmax2,rho", [(1, 0.08), (2, 0.16), (4, 0.05)])
+def test_two_neutrons_ccd_is_exact(orc, nmax2, rho):
+    """For two particles T2^2|Phi> = 0 and T1 vanishes by momentum
+    conservation, so converged CCD equals exact diagonalisation in the
+    K = 0, S_z = 0 two-body sector."""
+    p = orc.PNM(2, nmax2, rho)
+    st = p.states()
+    tk = p.kinetic()
+    pairs = [(a, b) for a in range(p.ns) for b in range(a + 1, p.ns)
+             if np.all(st[a, :3] + st[b, :3] == 0) and st[a, 3] + st[b, 3] == 0]
+    H = np.zeros((len(pairs), len(pairs)))
+    for x, (a, b) in enumerate(pairs):
+        for y, (c, d) in enumerate(pairs):
+            H[x, y] = p.v(a, b, c, d) + (tk[a] + tk[b] if x == y else 0.0)
+    exact = np.linalg.eigvalsh(H)[0] - p.eref()
+    o3 = orc.O3(p)
+    hist = o3.solve(0.7, 1e-13, 3000)
+    assert hist[-1] == pytest.approx(exact, rel=1e-9)
+    if p.ns <= 66:
+        o1 = orc.O1(tk, p.dense_v(), 2)
+        assert _run_o1(o1, 0.7, tol=1e-13, max_iter=3000) == pytest.approx(exact, rel=1e-9)
+
+
+# --------------------------------------------------------------------------
+# perturbation theory identities
+# --------------------------------------------------------------------------
+
+def _dense_setup(orc, N, nmax2, rho):
+    p = orc.PNM(N, nmax2, rho)
+    v = p.dense_v()
+    eps = p.fock()
+    return p, v, eps
+
+
+def test_first_iteration_energy_is_mbpt2(orc):
+    """E(t^(0)) = 1/4 sum <ij||ab><ab||ij>/eps_ij^ab (eq. ccdGuess and the
+    energy after it), brute force over all index quadruples."""
+    p, v, eps = _dense_setup(orc, 14, 2, 0.1)
+    N, n = 14, p.ns
+    h, pp = slice(0, N), slice(N, n)
+    D = eps[h, None, None, None] + eps[None, h, None, None] - eps[None, None, pp, None] - eps[None, None, None, pp]
+    vv = v[h, h, pp, pp]
+    e2 = 0.25 * np.sum(vv * vv / D)
+    assert orc.O3(p).emp2 == pytest.approx(e2, rel=1e-12)
+    assert orc.O1(p.kinetic(), v, N).emp2 == pytest.approx(e2, rel=1e-12)
+
+
+@pytest.mark.parametrize("mask_name", ["PP", "HH", "RING", "LINEAR"])
+def test_linear_terms_reproduce_third_order_diagrams(orc, mask_name):
+    """One sweep from t^(0) with only linear terms adds the third-order
+    diagrams: pp ladder (4), hh ladder (5) and ring (3), eqs. diag3-diag5.
+    Diagram (3) is read with <bk|v|jc> in place of the printed <bk|v|ic>."""
+    p, v, eps = _dense_setup(orc, 14, 2, 0.12)
+    N, n = 14, p.ns
+    H, P = range(N), range(N, n)
+    D2 = lambda i, j, a, b: eps[i] + eps[j] - eps[a] - eps[b]
+    vh = v  # dense <pq||rs>
+    d4 = d5 = d3 = 0.0
+    for i, j in itertools.product(H, H):
+        for a, b in itertools.product(P, P):
+            x = vh[i, j, a, b]
+            if x == 0.0:
+                continue
+            dij = D2(i, j, a, b)
+            for c, d in itertools.product(P, P):
+                y = vh[c, d, a, b]
+                if y != 0.0:
+                    d4 += vh[i, j, c, d] * y * x / (D2(i, j, c, d) * dij)
+            for k, l in itertools.product(H, H):
+                y = vh[k, l, i, j]
+                if y != 0.0:
+                    d5 += vh[a, b, k, l] * y * x / (dij * D2(k, l, a, b))
+            for k in H:
+                for c in P:
+                    y = vh[b, k, j, c]
+                    if y != 0.0:
+                        d3 += x * y * vh[a, c, i, k] / (dij * D2(i, k, a, c))
+    d4 /= 8.0
+    d5 /= 8.0
+    T = {"PP": (orc.T_PP, d4), "HH": (orc.T_HH, d5), "RING": (orc.T_RING, d3),
+         "LINEAR": (orc.T_LINEAR, d3 + d4 + d5)}
+    mask, want = T[mask_name]
+    assert abs(want) > 1e-6
+    o3 = orc.O3(p)
+    got = o3.sweep(1.0, mask) - o3.emp2
+    assert got == pytest.approx(want, rel=1e-10)
+    o1 = orc.O1(p.kinetic(), v, N)
+    got1 = o1.sweep(1.0, mask) - o1.emp2
+    assert got1 == pytest.approx(want, rel=1e-10)
+
+
+def test_ladder_only_equation_is_a_linear_solve(orc):
+    """Eq. ccd1 (pp ladder only) converged equals, for every hole pair (ij), the
+    dense solve (eps_ij^ab delta - <ab||cd>) t_ij^cd = <ab||ij> over a < b,
+    c < d in its channel (the matrix-inversion form after eq. ccd1)."""
+    p = orc.PNM(14, 4, 0.08)
+    st = p.states()
+    N, n = 14, p.ns
+    eps = p.fock()
+    o3 = orc.O3(p)
+    hist = o3.solve(1.0, 1e-14, 500, mask=orc.T_PP)
+    assert abs(hist[-1] - hist[-2]) < 1e-14
+    checked = 0
+    for i in range(N):
+        for j in range(i + 1, N):
+            K = st[i, :3] + st[j, :3]
+            S = st[i, 3] + st[j, 3]
+            ab = [(a, b) for a in range(N, n) for b in range(a + 1, n)
+                  if np.all(st[a, :3] + st[b, :3] == K) and st[a, 3] + st[b, 3] == S]
+            if not ab:
+                continue
+            A = np.array([[(eps[i] + eps[j] - eps[a] - eps[b] if x == y else 0.0) - p.v(a, b, c, d)
+                           for y, (c, d) in enumerate(ab)] for x, (a, b) in enumerate(ab)])
+            rhs = np.array([p.v(a, b, i, j) for a, b in ab])
+            sol = np.linalg.solve(A, rhs)
+            got = np.array([o3.t(a, b, i, j) for a, b in ab])
+            assert np.allclose(got, sol, rtol=1e-9, atol=1e-13)
+            checked += 1
+    assert checked > 20
+
+
+# --------------------------------------------------------------------------
+# the two oracle forms agree term by term
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("mask", [1, 2, 4, 8, 16, 32, 64, 127])
+def test_o1_and_o3_agree_per_term(orc, mask):
+    p = orc.PNM(14, 2, 0.1)
+    o1 = orc.O1(p.kinetic(), p.dense_v(), 14)
+    o3 = orc.O3(p)
+    assert o1.emp2 == pytest.approx(o3.emp2, rel=1e-13)
+    for _ in range(3):
+        e1 = o1.sweep(0.8, mask)
+        e3 = o3.sweep(0.8, mask)
+        assert e1 == pytest.approx(e3, rel=1e-12)
+    ijab, tv = o3.export()
+    for (i, j, a, b), t in zip(ijab[::7], tv[::7]):
+        assert o1.t(a, b, i, j) == pytest.approx(t, rel=1e-10, abs=1e-15)
+
+
+def test_amplitudes_antisymmetric(orc):
+    p = orc.PNM(14, 4, 0.08)
+    o3 = orc.O3(p)
+    for _ in range(3):
+        o3.sweep(1.0)
+    ijab, tv = o3.export()
+    for (i, j, a, b), t in zip(ijab[::11], tv[::11]):
+        assert o3.t(b, a, i, j) == pytest.approx(-t, abs=1e-15)
+        assert o3.t(a, b, j, i) == pytest.approx(-t, abs=1e-15)
+        assert o3.t(b, a, j, i) == pytest.approx(t, abs=1e-15)
