@@ -1,0 +1,201 @@
+/*
+ * ccd.h -- C ABI of the MI355X (gfx950) coupled-cluster doubles (CCD) library
+ * for pure neutron matter (PNM) in a periodic box with the Minnesota
+ * interaction, after Lietz, Novario, Jansen, Hagen and Hjorth-Jensen,
+ * "Computational Nuclear Physics and Post Hartree-Fock Methods"
+ * (arXiv:1611.06765).
+ *
+ * The problem stated by the paper (sec. "Developing a CCD code for infinite
+ * matter"): for N neutrons (a closed shell of the plane-wave basis) at density
+ * rho, in a basis of plane waves k = 2 pi n / L with n_x^2+n_y^2+n_z^2 <= nmax2
+ * and both spin projections, find the reference energy E_ref, the MBPT2
+ * correlation energy and the CCD correlation energy of eq. ccdcorr, by the
+ * iteration of eq. ccd3 (in its intermediates form) started from the MBPT2
+ * amplitudes of eq. ccdGuess, with linear mixing, until the correlation energy
+ * changes by less than a tolerance.
+ *
+ * Conventions
+ *  - Energies are box totals in MeV (divide by N for E/N).
+ *  - Plain C types only.  "Host" pointers are ordinary CPU memory owned by the
+ *    caller; "device" pointers are GPU memory owned by the caller.
+ *  - Every call returns a ccd_status; nothing aborts.  On failure the message
+ *    of ccd_last_error() (thread-local) says why.
+ *  - A context is used by one host thread at a time.  All device work of a
+ *    context is ordered on the HIP stream given at creation (NULL = the default
+ *    stream); calls that return numbers to the host synchronise that stream.
+ *  - Amplitude layout ("canonical"): the direct channels of a problem in the
+ *    order of ccd_export_maps(CCD_MAP_CHANNELS); each channel holds a row-major
+ *    block [n_pp][n_hh] of t_ij^ab with (a<b) particle pairs as rows and (i<j)
+ *    hole pairs as columns, pairs in the order of CCD_MAP_PP / CCD_MAP_HH.
+ *    Only channels that hold at least one hole pair and one particle pair are
+ *    present.  The other orderings follow from t_ij^ab = -t_ji^ab = -t_ij^ba.
+ */
+#ifndef CCD_H
+#define CCD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CCD_OK = 0,
+    CCD_NOT_CONVERGED = 1, /* max_iter sweeps done, some problem not converged */
+    CCD_DIVERGED = 2,      /* a correlation energy became non-finite */
+    CCD_EINVAL = -1,       /* bad argument (message in ccd_last_error) */
+    CCD_ENOTMAGIC = -2,    /* N does not close a shell, or no particle states */
+    CCD_ENOMEM = -3,       /* host allocation failed or workspace too small */
+    CCD_EHIP = -4,         /* a HIP runtime call failed */
+    CCD_ESTATE = -5        /* call out of order (e.g. iterate before a workspace is bound) */
+} ccd_status;
+
+/* One PNM problem (sec. "Single-particle basis for infinite matter" and
+ * sec. "Two-body interaction").  The Minnesota triplet channel does not act
+ * between two neutrons, so only its R and S channels are parameters. */
+typedef struct {
+    int32_t n_particles;  /* N: closed shell of the basis (2, 14, 38, 54, 66, 114, ...) */
+    int32_t nmax2;        /* keep states with n_x^2+n_y^2+n_z^2 <= nmax2 */
+    double density;       /* rho in fm^-3; box side L = (N/rho)^(1/3) */
+    double hbar2_over_m;  /* MeV fm^2, e.g. 41.47 */
+    double V_R, kappa_R;  /* repulsive Gaussian, e.g. 200 MeV, 1.487 fm^-2 */
+    double V_S, kappa_S;  /* singlet Gaussian, e.g. -91.85 MeV, 0.465 fm^-2 */
+} ccd_problem;
+
+/* Term bits of eq. ccd3 (all set = full CCD) */
+#define CCD_T_PP     1u  /* 1/2 sum_cd <ab|v|cd> t_ij^cd                       */
+#define CCD_T_HH     2u  /* 1/2 sum_kl <kl|v|ij> t_kl^ab                       */
+#define CCD_T_RING   4u  /* P(ij|ab) sum_kc <kb|v|cj> t_ik^ac                  */
+#define CCD_T_QHH    8u  /* 1/4 sum_klcd <kl|v|cd> t_ij^cd t_kl^ab             */
+#define CCD_T_QRING 16u  /* P(ij) sum_klcd <kl|v|cd> t_ik^ac t_jl^bd           */
+#define CCD_T_QHOLE 32u  /* -1/2 P(ij) sum_klcd <kl|v|cd> t_ik^dc t_lj^ab      */
+#define CCD_T_QPART 64u  /* -1/2 P(ab) sum_klcd <kl|v|cd> t_lk^ac t_ij^db      */
+#define CCD_T_ALL  127u
+
+/* Precision of the channel contractions (ladders and ring).  Denominators,
+ * the amplitude update, mixing and the energy are FP64 in every mode. */
+#define CCD_PREC_FP64 0
+#define CCD_PREC_FP32 1 /* FP32 operands, FP32 accumulation on MFMA */
+#define CCD_PREC_BF16 2 /* BF16 operands, FP32 accumulation on MFMA */
+
+typedef struct {
+    double mixing;         /* alpha in (0, 1]: t <- alpha t_new + (1-alpha) t_old */
+    double tol;            /* stop when |dE_n - dE_(n-1)| < tol (MeV, box total);
+                              tol <= 0 runs exactly max_iter sweeps */
+    int32_t max_iter;      /* sweeps in this call (>= 1) */
+    int32_t precision;     /* CCD_PREC_* for the sweeps of this call */
+    int32_t refine_sweeps; /* after a mixed-precision run converges, this many
+                              more FP64 sweeps, then FP64 iteration to tol */
+    uint32_t terms;        /* CCD_T_* mask; CCD_T_ALL for CCD */
+} ccd_solver_opts;
+
+typedef struct ccd_ctx ccd_ctx; /* opaque */
+
+typedef struct {
+    int32_t n_states, n_holes, n_particles_states;
+    int32_t n_channels;      /* direct channels (K, S_z) in the amplitude layout */
+    int32_t n_channels_sz0;  /* of which S_z = 0 (the only ones with nonzero <ab|v|ij>) */
+    int32_t n_ph_channels;   /* particle-hole cross channels (Q, sigma) */
+    int32_t max_hh, max_pp, max_ph;  /* largest block dimensions */
+    int64_t n_amplitudes;    /* elements of the canonical amplitude vector */
+    int32_t lut_size;        /* entries of the interaction table W(m), m = |dn|^2 */
+    double box_L;            /* fm */
+    double flops_pp;         /* FP64 flops of one sweep's pp ladder (executed) */
+    double flops_hh;         /* hh ladder + chi_klij contraction */
+    double flops_ring;       /* both ring contractions */
+    double flops_ordered;    /* the same three with ordered pairs, the paper's
+                                unrestricted-index form */
+} ccd_info;
+
+/* Build the host plan of n_problems independent problems: model space and
+ * hole filling (model-space loop of sec. "Developing a CCD code for infinite
+ * matter"), Minnesota table W(m) and Fock energies (sec. "Two-body
+ * interaction", normal-ordering section), direct channels T (quantum numbers
+ * added) and particle-hole cross channels X (subtracted) with their pair lists
+ * (channel discussion after the intermediates).  No GPU work and no device
+ * memory: the GPU is first touched by ccd_bind_workspace.
+ *   probs       host array of n_problems problems (n_problems >= 1)
+ *   hip_stream  hipStream_t for all later device work (NULL = default stream)
+ *   out         receives the new context; free with ccd_destroy.
+ * Errors: CCD_EINVAL (bad sizes / parameters, blocks beyond the kernels'
+ * limits), CCD_ENOTMAGIC, CCD_ENOMEM. */
+ccd_status ccd_build_channels(const ccd_problem* probs, int32_t n_problems, void* hip_stream,
+                              ccd_ctx** out);
+
+/* Device bytes the context needs (all amplitudes, intermediates, tables). */
+ccd_status ccd_workspace_size(const ccd_ctx* ctx, size_t* bytes);
+
+/* Hand the context device memory of at least ccd_workspace_size bytes, owned
+ * by the caller (e.g. a torch uint8 tensor) and kept alive until ccd_destroy.
+ * Uploads the tables, then on the device builds <ab||ij>, the MBPT2 amplitudes
+ * t0 = <ab||ij>/eps_ij^ab and the MBPT2 energy (eq. ccdGuess).  The library
+ * itself allocates no device memory.  Errors: CCD_EINVAL (NULL / too small /
+ * misaligned: 256-byte alignment required), CCD_EHIP, CCD_ESTATE (bound twice). */
+ccd_status ccd_bind_workspace(ccd_ctx* ctx, void* device_ptr, size_t bytes);
+
+/* Jacobi sweeps of eq. ccd3 in the intermediates form on the GPU (every term
+ * from t^(n), linear mixing, energy of the mixed amplitudes), for all
+ * problems of the context.  A problem whose |dE_n - dE_(n-1)| < tol stops
+ * changing; the call returns when all problems have converged or after
+ * max_iter sweeps.
+ *   sweeps_done  host, n_problems entries (nullable): sweeps each problem ran in this call
+ *   e_hist       host, n_problems * max_iter entries (nullable): correlation energy
+ *                of problem p after sweep s at e_hist[p*max_iter + s] (NaN after
+ *                the problem stopped).  Requesting it synchronises every sweep.
+ * Returns CCD_OK, CCD_NOT_CONVERGED (tol > 0 and a problem is still moving;
+ * with tol <= 0 always CCD_OK), CCD_DIVERGED, CCD_EINVAL, CCD_ESTATE, CCD_EHIP. */
+ccd_status ccd_iterate(ccd_ctx* ctx, const ccd_solver_opts* opts, int32_t* sweeps_done,
+                       double* e_hist);
+
+/* Energies of problem `problem` (MeV, box totals): E_ref, the MBPT2
+ * correlation energy and the current correlation energy 1/4 sum <ij||ab> t
+ * (eq. ccdcorr).  Synchronises the stream.  Any pointer may be NULL. */
+ccd_status ccd_energy(const ccd_ctx* ctx, int32_t problem, double* e_ref, double* e_mbpt2,
+                      double* e_corr);
+
+/* Sizes and operation counts of problem `problem`. */
+ccd_status ccd_problem_info(const ccd_ctx* ctx, int32_t problem, ccd_info* info);
+
+/* Copy the canonical amplitude vector of a problem to / from host memory
+ * (n = ccd_info.n_amplitudes doubles).  set also recomputes the energy and
+ * makes the set amplitudes the current iterate (warm start, checkpoint
+ * restore).  reset returns every problem to its MBPT2 amplitudes. */
+ccd_status ccd_get_amplitudes(const ccd_ctx* ctx, int32_t problem, double* host_dst, size_t n);
+ccd_status ccd_set_amplitudes(ccd_ctx* ctx, int32_t problem, const double* host_src, size_t n);
+ccd_status ccd_reset_amplitudes(ccd_ctx* ctx);
+
+/* Host copies of the plan's integer maps of a problem, for bit-exact tests.
+ * Works without a GPU.  If dst is NULL or n is too small, only *n_needed is
+ * written (and CCD_OK returned when dst is NULL, CCD_EINVAL otherwise). */
+#define CCD_MAP_STATES   0 /* 4 per state: n_x, n_y, n_z, 2 s_z                         */
+#define CCD_MAP_CHANNELS 1 /* 6 per direct channel: K_x, K_y, K_z, 2 S_z, n_hh, n_pp      */
+#define CCD_MAP_HH       2 /* 2 per hole pair (i, j), channel after channel                */
+#define CCD_MAP_PP       3 /* 2 per particle pair (a, b), channel after channel            */
+#define CCD_MAP_PH_CHANNELS 4 /* 6 per cross channel: Q_x, Q_y, Q_z, 2 sigma, n, partner     */
+#define CCD_MAP_PH       5 /* 2 per particle-hole pair (p, h), channel after channel       */
+ccd_status ccd_export_maps(const ccd_ctx* ctx, int32_t problem, int32_t which, int32_t* dst,
+                           size_t n, size_t* n_needed);
+
+/* Host copies of a problem's single-particle tables: kinetic energies,
+ * Fock energies (n_states each) and the interaction table W(m) (lut_size). */
+ccd_status ccd_export_tables(const ccd_ctx* ctx, int32_t problem, double* tkin, double* eps,
+                             double* w_table);
+
+/* Per-kernel GPU timing with HIP events recorded on the context's stream.
+ * While enabled every launch is bracketed by two events; ccd_kernel_times
+ * returns, per kernel family, the summed milliseconds and launch counts since
+ * the last reset (families: see ccd_kernel_name).  Synchronises the stream. */
+ccd_status ccd_set_timing(ccd_ctx* ctx, int32_t enabled);
+int32_t ccd_kernel_families(void);
+const char* ccd_kernel_name(int32_t family);
+ccd_status ccd_kernel_times(ccd_ctx* ctx, double* ms, int64_t* launches, int32_t reset);
+
+const char* ccd_last_error(void);
+const char* ccd_version(void);
+void ccd_destroy(ccd_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CCD_H */

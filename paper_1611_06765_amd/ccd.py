@@ -1,0 +1,243 @@
+"""ctypes binding of libccd.so (include/ccd.h): argument marshalling only.
+
+Every step of the CCD sweep runs in the library's HIP kernels.  PyTorch is used
+for device memory (the workspace tensor) and for the stream the library works
+on.  If the shared library is missing this module raises at import time: there
+is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libccd.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built: run `python -m paper_1611_06765_amd.build_lib`")
+
+# torch brings its own HIP runtime (same soname, libamdhip64.so.7).  Loading it
+# first makes the library bind to that runtime instead of a second copy from
+# /opt/rocm: two HIP runtimes in one process do not share the device.
+import torch  # noqa: E402,F401
+
+_lib = C.CDLL(LIB_PATH)
+
+CCD_OK, CCD_NOT_CONVERGED, CCD_DIVERGED = 0, 1, 2
+CCD_EINVAL, CCD_ENOTMAGIC, CCD_ENOMEM, CCD_EHIP, CCD_ESTATE = -1, -2, -3, -4, -5
+STATUS_NAMES = {0: "CCD_OK", 1: "CCD_NOT_CONVERGED", 2: "CCD_DIVERGED", -1: "CCD_EINVAL",
+                -2: "CCD_ENOTMAGIC", -3: "CCD_ENOMEM", -4: "CCD_EHIP", -5: "CCD_ESTATE"}
+
+CCD_T_PP, CCD_T_HH, CCD_T_RING, CCD_T_QHH = 1, 2, 4, 8
+CCD_T_QRING, CCD_T_QHOLE, CCD_T_QPART, CCD_T_ALL = 16, 32, 64, 127
+CCD_PREC_FP64, CCD_PREC_FP32, CCD_PREC_BF16 = 0, 1, 2
+CCD_MAP_STATES, CCD_MAP_CHANNELS, CCD_MAP_HH, CCD_MAP_PP, CCD_MAP_PH_CHANNELS, CCD_MAP_PH = range(6)
+
+
+class ccd_problem(C.Structure):
+    _fields_ = [("n_particles", C.c_int32), ("nmax2", C.c_int32), ("density", C.c_double),
+                ("hbar2_over_m", C.c_double), ("V_R", C.c_double), ("kappa_R", C.c_double),
+                ("V_S", C.c_double), ("kappa_S", C.c_double)]
+
+
+class ccd_solver_opts(C.Structure):
+    _fields_ = [("mixing", C.c_double), ("tol", C.c_double), ("max_iter", C.c_int32),
+                ("precision", C.c_int32), ("refine_sweeps", C.c_int32), ("terms", C.c_uint32)]
+
+
+class ccd_info(C.Structure):
+    _fields_ = [("n_states", C.c_int32), ("n_holes", C.c_int32), ("n_particles_states", C.c_int32),
+                ("n_channels", C.c_int32), ("n_channels_sz0", C.c_int32), ("n_ph_channels", C.c_int32),
+                ("max_hh", C.c_int32), ("max_pp", C.c_int32), ("max_ph", C.c_int32),
+                ("n_amplitudes", C.c_int64), ("lut_size", C.c_int32), ("box_L", C.c_double),
+                ("flops_pp", C.c_double), ("flops_hh", C.c_double), ("flops_ring", C.c_double),
+                ("flops_ordered", C.c_double)]
+
+
+_vp, _i32, _sz = C.c_void_p, C.c_int32, C.c_size_t
+_dp, _ip = C.POINTER(C.c_double), C.POINTER(C.c_int32)
+_SIGS = {
+    "ccd_build_channels": (_i32, [C.POINTER(ccd_problem), _i32, _vp, C.POINTER(_vp)]),
+    "ccd_workspace_size": (_i32, [_vp, C.POINTER(_sz)]),
+    "ccd_bind_workspace": (_i32, [_vp, _vp, _sz]),
+    "ccd_iterate": (_i32, [_vp, C.POINTER(ccd_solver_opts), _ip, _dp]),
+    "ccd_energy": (_i32, [_vp, _i32, _dp, _dp, _dp]),
+    "ccd_problem_info": (_i32, [_vp, _i32, C.POINTER(ccd_info)]),
+    "ccd_get_amplitudes": (_i32, [_vp, _i32, _dp, _sz]),
+    "ccd_set_amplitudes": (_i32, [_vp, _i32, _dp, _sz]),
+    "ccd_reset_amplitudes": (_i32, [_vp]),
+    "ccd_export_maps": (_i32, [_vp, _i32, _i32, _ip, _sz, C.POINTER(_sz)]),
+    "ccd_export_tables": (_i32, [_vp, _i32, _dp, _dp, _dp]),
+    "ccd_set_timing": (_i32, [_vp, _i32]),
+    "ccd_kernel_families": (_i32, []),
+    "ccd_kernel_name": (C.c_char_p, [_i32]),
+    "ccd_kernel_times": (_i32, [_vp, _dp, C.POINTER(C.c_int64), _i32]),
+    "ccd_last_error": (C.c_char_p, []),
+    "ccd_version": (C.c_char_p, []),
+    "ccd_destroy": (None, [_vp]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+EXPORTED = tuple(_SIGS)
+
+
+class CCDError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        msg = _lib.ccd_last_error().decode()
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {msg}")
+
+
+def _check(status, where, ok=(CCD_OK,)):
+    if status not in ok:
+        raise CCDError(status, where)
+    return status
+
+
+MINNESOTA = dict(V_R=200.0, kappa_R=1.487, V_S=-91.85, kappa_S=0.465)
+HBAR2_OVER_M = 41.47
+
+
+def problem(n_particles, nmax2, density, hbar2_over_m=HBAR2_OVER_M, **pot):
+    p = dict(MINNESOTA)
+    p.update(pot)
+    return ccd_problem(n_particles, nmax2, density, hbar2_over_m,
+                       p["V_R"], p["kappa_R"], p["V_S"], p["kappa_S"])
+
+
+def _dptr(a):
+    return a.ctypes.data_as(_dp)
+
+
+class Context:
+    """One ccd_ctx: a batch of independent problems sharing one stream."""
+
+    def __init__(self, problems, stream=None):
+        probs = (ccd_problem * len(problems))(*problems)
+        self._h = _vp()
+        sp = None if stream is None else _vp(stream)
+        _check(_lib.ccd_build_channels(probs, len(problems), sp, C.byref(self._h)), "ccd_build_channels")
+        self.n = len(problems)
+        self.workspace = None
+
+    def __del__(self):
+        self.close()
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _lib.ccd_destroy(self._h)
+            self._h = _vp()
+
+    # ---- host-side plan (no GPU) ------------------------------------------
+    def workspace_size(self):
+        n = _sz()
+        _check(_lib.ccd_workspace_size(self._h, C.byref(n)), "ccd_workspace_size")
+        return n.value
+
+    def info(self, p=0):
+        i = ccd_info()
+        _check(_lib.ccd_problem_info(self._h, p, C.byref(i)), "ccd_problem_info")
+        return {k: getattr(i, k) for k, _ in ccd_info._fields_}
+
+    def export_map(self, which, p=0):
+        need = _sz()
+        _check(_lib.ccd_export_maps(self._h, p, which, None, 0, C.byref(need)), "ccd_export_maps")
+        out = np.zeros(need.value, dtype=np.int32)
+        _check(_lib.ccd_export_maps(self._h, p, which, out.ctypes.data_as(_ip), out.size, None),
+               "ccd_export_maps")
+        return out
+
+    def export_tables(self, p=0):
+        inf = self.info(p)
+        tk = np.zeros(inf["n_states"])
+        eps = np.zeros(inf["n_states"])
+        w = np.zeros(inf["lut_size"])
+        _check(_lib.ccd_export_tables(self._h, p, _dptr(tk), _dptr(eps), _dptr(w)), "ccd_export_tables")
+        return tk, eps, w
+
+    # ---- device -------------------------------------------------------------
+    def bind(self, device="cuda"):
+        """Allocate the workspace as a torch uint8 tensor and bind it."""
+        import torch
+        nbytes = self.workspace_size()
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        ptr = self.workspace.data_ptr()
+        ptr = (ptr + 255) & ~255
+        _check(_lib.ccd_bind_workspace(self._h, _vp(ptr), nbytes), "ccd_bind_workspace")
+        return self
+
+    def iterate(self, mixing=1.0, tol=0.0, max_iter=1, precision=CCD_PREC_FP64, refine_sweeps=0,
+                terms=CCD_T_ALL, history=False):
+        o = ccd_solver_opts(mixing, tol, max_iter, precision, refine_sweeps, terms)
+        sweeps = np.zeros(self.n, dtype=np.int32)
+        hist = np.zeros(self.n * max_iter) if history else None
+        st = _lib.ccd_iterate(self._h, C.byref(o), sweeps.ctypes.data_as(_ip),
+                              _dptr(hist) if history else None)
+        _check(st, "ccd_iterate", ok=(CCD_OK, CCD_NOT_CONVERGED))
+        res = {"status": st, "sweeps": sweeps}
+        if history:
+            res["history"] = hist.reshape(self.n, max_iter)
+        return res
+
+    def energy(self, p=0):
+        a, b, c = C.c_double(), C.c_double(), C.c_double()
+        _check(_lib.ccd_energy(self._h, p, C.byref(a), C.byref(b), C.byref(c)), "ccd_energy")
+        return a.value, b.value, c.value
+
+    def eref(self, p=0):
+        """Reference energy (host plan; no GPU needed)."""
+        a = C.c_double()
+        _check(_lib.ccd_energy(self._h, p, C.byref(a), None, None), "ccd_energy")
+        return a.value
+
+    def get_amplitudes(self, p=0):
+        n = self.info(p)["n_amplitudes"]
+        out = np.zeros(n)
+        _check(_lib.ccd_get_amplitudes(self._h, p, _dptr(out), n), "ccd_get_amplitudes")
+        return out
+
+    def set_amplitudes(self, t, p=0):
+        t = np.ascontiguousarray(t, dtype=np.float64)
+        _check(_lib.ccd_set_amplitudes(self._h, p, _dptr(t), t.size), "ccd_set_amplitudes")
+
+    def reset_amplitudes(self):
+        _check(_lib.ccd_reset_amplitudes(self._h), "ccd_reset_amplitudes")
+
+    def set_timing(self, on=True):
+        _check(_lib.ccd_set_timing(self._h, int(on)), "ccd_set_timing")
+
+    def kernel_times(self, reset=False):
+        nf = _lib.ccd_kernel_families()
+        ms = np.zeros(nf)
+        cnt = np.zeros(nf, dtype=np.int64)
+        _check(_lib.ccd_kernel_times(self._h, _dptr(ms), cnt.ctypes.data_as(C.POINTER(C.c_int64)),
+                                     int(reset)), "ccd_kernel_times")
+        return {_lib.ccd_kernel_name(f).decode(): (float(ms[f]), int(cnt[f])) for f in range(nf)}
+
+
+def canonical_index(ctx: Context, p=0):
+    """(i, j, a, b) state indices of every element of the canonical amplitude
+    vector of problem p, from the exported maps."""
+    ch = ctx.export_map(CCD_MAP_CHANNELS, p).reshape(-1, 6)
+    hh = ctx.export_map(CCD_MAP_HH, p).reshape(-1, 2)
+    pp = ctx.export_map(CCD_MAP_PP, p).reshape(-1, 2)
+    out = []
+    ho = po = 0
+    for kx, ky, kz, sz, nhh, npp in ch:
+        H = hh[ho:ho + nhh]
+        Pp = pp[po:po + npp]
+        ii = np.repeat(Pp, nhh, axis=0)
+        jj = np.tile(H, (npp, 1))
+        out.append(np.concatenate([jj, ii], axis=1))
+        ho += nhh
+        po += npp
+    return np.concatenate(out, axis=0) if out else np.zeros((0, 4), dtype=np.int32)
+
+
+def version():
+    return _lib.ccd_version().decode()

@@ -1,0 +1,210 @@
+// ccd_plan.cpp -- host side of the CCD library: model space, Minnesota table,
+// Fock energies, direct and particle-hole channels, and operation counts.
+//
+// Model space: plane waves k = 2 pi n / L in a periodic box of side
+// L = (N/rho)^(1/3), n_x^2+n_y^2+n_z^2 <= nmax2, two spin projections, ordered
+// by shell, then n_x, n_y, n_z, then s_z = -1/2 before +1/2; the first N
+// states are holes (sec. "Single-particle basis for infinite matter" and the
+// model-space loop of sec. "Developing a CCD code for infinite matter").
+//
+// Interaction: between two neutrons the isospin exchange is +1, so the
+// Minnesota operator 1/2 (V_R + 1/2(1+P_s)V_T + 1/2(1-P_s)V_S)(1 - P_s P_t)
+// (sec. "Two-body interaction") reduces to 1/2 (V_R(r) + V_S(r)) (1 - P_s):
+// only spin singlets interact.  With the Gaussian Fourier transform
+// V_a/L^3 (pi/kappa_a)^{3/2} exp(-q^2/4 kappa_a) and q = k_p - k_r under
+// momentum conservation, the antisymmetrised element is
+//   <pq||rs> = 1/2 [d(s_p,s_r) d(s_q,s_s) - d(s_p,s_s) d(s_q,s_r)]
+//              * (W(|n_p-n_r|^2) + W(|n_p-n_s|^2)),
+//   W(m) = sum_{a=R,S} V_a/L^3 (pi/kappa_a)^{3/2} exp(-(2 pi/L)^2 m / 4 kappa_a),
+// for n_p+n_q = n_r+n_s and zero otherwise.  The table W(m), m = 0 .. 4 nmax2,
+// is all the device needs to generate any element.
+//
+// Channels (channel discussion after the intermediates): direct channels
+// T = (K = n_p + n_q, S_z) hold the hole pairs (i<j) and particle pairs (a<b);
+// particle-hole cross channels X = (Q = n_p - n_h, sigma = s_p - s_h) hold
+// (particle, hole) pairs; the ring contraction of cross channel (Q, sigma)
+// pairs it with (-Q, -sigma).
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <map>
+#include <tuple>
+
+#include "ccd_internal.h"
+
+namespace ccd {
+
+static double minnesota_W(const ccd_problem& p, double L, int m) {
+    const double pi = 3.14159265358979323846;
+    double dk = 2.0 * pi / L;
+    double L3 = L * L * L;
+    double w = 0.0;
+    w += p.V_R / L3 * std::pow(pi / p.kappa_R, 1.5) * std::exp(-dk * dk * (double)m / (4.0 * p.kappa_R));
+    w += p.V_S / L3 * std::pow(pi / p.kappa_S, 1.5) * std::exp(-dk * dk * (double)m / (4.0 * p.kappa_S));
+    return w;
+}
+
+ccd_status build_problem(const ccd_problem& par, HostProblem& P, std::string& err) {
+    P = HostProblem();
+    P.par = par;
+    if (par.nmax2 < 1 || par.nmax2 > 300) { err = "nmax2 must be in [1, 300]"; return CCD_EINVAL; }
+    if (par.n_particles < 2) { err = "n_particles must be >= 2"; return CCD_EINVAL; }
+    if (!(par.density > 0.0) || !std::isfinite(par.density)) { err = "density must be > 0"; return CCD_EINVAL; }
+    if (!(par.hbar2_over_m > 0.0)) { err = "hbar2_over_m must be > 0"; return CCD_EINVAL; }
+    if (!(par.kappa_R > 0.0) || !(par.kappa_S > 0.0)) { err = "Gaussian ranges must be > 0"; return CCD_EINVAL; }
+
+    // ---- model space ------------------------------------------------------
+    int R = 0;
+    while ((R + 1) * (R + 1) <= par.nmax2) R++;
+    P.R = R;
+    std::vector<std::array<int, 4>> mom;  // (n^2, nx, ny, nz)
+    for (int x = -R; x <= R; x++)
+        for (int y = -R; y <= R; y++)
+            for (int z = -R; z <= R; z++) {
+                int n2 = x * x + y * y + z * z;
+                if (n2 <= par.nmax2) mom.push_back({n2, x, y, z});
+            }
+    std::sort(mom.begin(), mom.end());
+    for (auto& m : mom)
+        for (int s : {-1, 1}) {
+            P.nx.push_back(m[1]); P.ny.push_back(m[2]); P.nz.push_back(m[3]); P.sz.push_back(s);
+        }
+    P.ns = (int)P.nx.size();
+    P.nh = par.n_particles;
+    if (P.nh >= P.ns) { err = "no particle states: raise nmax2"; return CCD_ENOTMAGIC; }
+    auto shell = [&](int p) { return P.nx[p] * P.nx[p] + P.ny[p] * P.ny[p] + P.nz[p] * P.nz[p]; };
+    if (shell(P.nh - 1) == shell(P.nh)) {
+        err = "n_particles does not close a shell of the plane-wave basis";
+        return CCD_ENOTMAGIC;
+    }
+    if (P.ns > 65535) { err = "basis too large"; return CCD_EINVAL; }
+    P.np = P.ns - P.nh;
+    P.L = std::cbrt((double)par.n_particles / par.density);
+
+    // ---- energies and interaction table -------------------------------------
+    const double pi = 3.14159265358979323846;
+    double dk = 2.0 * pi / P.L;
+    P.tkin.resize(P.ns);
+    for (int p = 0; p < P.ns; p++) P.tkin[p] = 0.5 * par.hbar2_over_m * dk * dk * (double)shell(p);
+    int nlut = 4 * par.nmax2 + 1;
+    P.W.resize(nlut);
+    for (int m = 0; m < nlut; m++) P.W[m] = minnesota_W(par, P.L, m);
+    auto d2 = [&](int p, int q) {
+        int x = P.nx[p] - P.nx[q], y = P.ny[p] - P.ny[q], z = P.nz[p] - P.nz[q];
+        return x * x + y * y + z * z;
+    };
+    // <pi||pi> = 1/2 (1 - d(s_p, s_i)) (W(0) + W(|n_p - n_i|^2))
+    P.eps.resize(P.ns);
+    for (int p = 0; p < P.ns; p++) {
+        double f = 0.0;
+        for (int i = 0; i < P.nh; i++)
+            if (P.sz[i] != P.sz[p]) f += 0.5 * (P.W[0] + P.W[d2(p, i)]);
+        P.eps[p] = P.tkin[p] + f;
+    }
+    {
+        double t = 0.0, v = 0.0;
+        for (int i = 0; i < P.nh; i++) t += P.tkin[i];
+        for (int i = 0; i < P.nh; i++)
+            for (int j = 0; j < P.nh; j++)
+                if (P.sz[i] != P.sz[j]) v += 0.5 * (P.W[0] + P.W[d2(i, j)]);
+        P.eref = t + 0.5 * v;
+    }
+
+    // ---- direct channels ----------------------------------------------------
+    // key = (S_z, K_x, K_y, K_z): canonical channel order is by S_z, then K.
+    using Key = std::tuple<int, int, int, int>;
+    std::map<Key, std::pair<std::vector<int32_t>, std::vector<int32_t>>> chmap;
+    for (int i = 0; i < P.nh; i++)
+        for (int j = i + 1; j < P.nh; j++) {
+            Key k{P.sz[i] + P.sz[j], P.nx[i] + P.nx[j], P.ny[i] + P.ny[j], P.nz[i] + P.nz[j]};
+            auto& e = chmap[k].first;
+            e.push_back(i); e.push_back(j);
+        }
+    for (int a = P.nh; a < P.ns; a++)
+        for (int b = a + 1; b < P.ns; b++) {
+            Key k{P.sz[a] + P.sz[b], P.nx[a] + P.nx[b], P.ny[a] + P.ny[b], P.nz[a] + P.nz[b]};
+            auto it = chmap.find(k);
+            if (it == chmap.end()) continue;  // no hole pair: carries no amplitude
+            it->second.second.push_back(a); it->second.second.push_back(b);
+        }
+    int64_t toff = 0;
+    for (auto& kv : chmap) {
+        int nhh = (int)kv.second.first.size() / 2, npp = (int)kv.second.second.size() / 2;
+        if (nhh == 0 || npp == 0) continue;
+        Chan c;
+        c.Sz = std::get<0>(kv.first); c.Kx = std::get<1>(kv.first);
+        c.Ky = std::get<2>(kv.first); c.Kz = std::get<3>(kv.first);
+        c.nhh = nhh; c.npp = npp;
+        c.t_off = toff;
+        c.hh_off = (int)P.hh.size() / 2;
+        c.pp_off = (int)P.pp.size() / 2;
+        P.hh.insert(P.hh.end(), kv.second.first.begin(), kv.second.first.end());
+        P.pp.insert(P.pp.end(), kv.second.second.begin(), kv.second.second.end());
+        toff += (int64_t)nhh * npp;
+        P.chans.push_back(c);
+        P.max_hh = std::max(P.max_hh, nhh);
+        P.max_pp = std::max(P.max_pp, npp);
+        if (c.Sz == 0) {
+            P.n_sz0++;
+            double M = npp, Nn = nhh;
+            P.flops_pp += 2.0 * M * M * Nn;
+            P.flops_hh += 2.0 * M * Nn * Nn + 2.0 * Nn * Nn * M;  // hh ladder + chi_klij
+            P.flops_ordered += 8.0 * (2.0 * M * M * Nn + 4.0 * M * Nn * Nn);
+        }
+    }
+    P.n_amp = toff;
+    if (P.max_hh > kMaxHH) {
+        err = "a direct channel has more than 64 hole pairs (N too large for this library)";
+        return CCD_EINVAL;
+    }
+
+    // ---- particle-hole cross channels -------------------------------------
+    std::map<Key, std::vector<int32_t>> phmap;  // key (sigma, Qx, Qy, Qz)
+    for (int p = P.nh; p < P.ns; p++)
+        for (int h = 0; h < P.nh; h++) {
+            Key k{P.sz[p] - P.sz[h], P.nx[p] - P.nx[h], P.ny[p] - P.ny[h], P.nz[p] - P.nz[h]};
+            auto& e = phmap[k];
+            e.push_back(p); e.push_back(h);
+        }
+    std::map<Key, int> phid;
+    for (auto& kv : phmap) {
+        PhChan c;
+        c.sig = std::get<0>(kv.first); c.Qx = std::get<1>(kv.first);
+        c.Qy = std::get<2>(kv.first); c.Qz = std::get<3>(kv.first);
+        c.n = (int)kv.second.size() / 2;
+        c.mem_off = (int)P.phmem.size() / 2;
+        c.partner = -1;
+        c.z_off = P.nz_ph;
+        P.nz_ph += (int64_t)c.n * c.n;
+        phid[kv.first] = (int)P.ph.size();
+        P.phmem.insert(P.phmem.end(), kv.second.begin(), kv.second.end());
+        P.ph.push_back(c);
+        P.max_ph = std::max(P.max_ph, c.n);
+        P.flops_ring += 4.0 * (double)c.n * c.n * c.n;
+    }
+    P.flops_ordered += P.flops_ring;
+    P.phq.assign((size_t)P.np * P.nh, -1);
+    P.phpos.assign((size_t)P.np * P.nh, -1);
+    for (size_t q = 0; q < P.ph.size(); q++) {
+        PhChan& c = P.ph[q];
+        Key partner{-c.sig, -c.Qx, -c.Qy, -c.Qz};
+        auto it = phid.find(partner);
+        if (it == phid.end() || P.ph[it->second].n != c.n) {
+            err = "internal: particle-hole channel without a partner of equal size";
+            return CCD_EINVAL;
+        }
+        c.partner = it->second;
+        for (int u = 0; u < c.n; u++) {
+            int p = P.phmem[2 * (c.mem_off + u)], h = P.phmem[2 * (c.mem_off + u) + 1];
+            P.phq[(size_t)(p - P.nh) * P.nh + h] = (int)q;
+            P.phpos[(size_t)(p - P.nh) * P.nh + h] = u;
+        }
+    }
+    if (P.max_ph > kMaxPH) {
+        err = "a particle-hole channel has more than 90 pairs (N too large for this library)";
+        return CCD_EINVAL;
+    }
+    return CCD_OK;
+}
+
+}  // namespace ccd
