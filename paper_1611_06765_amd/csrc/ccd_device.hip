@@ -1,30 +1,34 @@
 // ccd_device.hip -- gfx950 kernels of the CCD sweep and the C ABI around them.
 //
-// One Jacobi sweep (eq. ccd3 in the intermediates form of sec. "Developing a
-// CCD code for infinite matter"), all terms from the current amplitudes t:
-//   k_rowcol   row and column sums of t <ab||ij> over S_z = 0 blocks
-//   k_dchi     one-body intermediates, diagonal by momentum conservation:
-//              chi_bb - f_bb = -1/2 sum_kld t_kl^bd <kl||bd>,
-//              chi_jj - f_jj = +1/2 sum_cdl <jl||cd> t_jl^cd
-//   k_chh      chi_klij = <kl||ij> + 1/2 sum_cd <kl||cd> t_ij^cd per S_z = 0 block
-//   k_scatter  t -> particle-hole layout T~_Q[(a,i),(c,k)] = t_ik^ac
-//   k_ring     per cross channel Q: chi~ = V_ph + 1/2 Vbar T~_Q (chi_kbcj),
-//              Z_Q = T~_Q chi~ (sum_kc t_ik^ac chi_kbcj)
-//   k_ladder   per S_z = 0 block and 64-row tile: pp ladder sum_{c<d} <ab||cd> t_ij^cd
-//              with <ab||cd> generated on the fly from W(m), hh ladder
-//              sum_{k<l} t_kl^ab chi_klij, the ring P(ij)P(ab) gather from Z,
-//              the one-body terms, t_new = R / eps_ij^ab, linear mixing and the
-//              energy partial sums
-//   k_update   the same update for the S_z = +-1 blocks (no ladders: <ab||cd> = 0)
-//   k_energy   deterministic per-problem energy, convergence flag
-// Reductions use fixed-order trees (no floating-point atomics), so energies are
-// bit-identical from run to run.
+// One Jacobi sweep of eq. ccd3 in the intermediates form (sec. "Developing a
+// CCD code for infinite matter"), every term from the current amplitudes t:
+//   k_direct  per S_z = 0 block: chi_klij = <kl||ij> + 1/2 sum_cd <kl||cd> t_ij^cd
+//             (FP64 MFMA), and the row / column sums of t <ab||ij> that make the
+//             one-body intermediates
+//   k_dchi    one-body intermediates, diagonal by momentum conservation:
+//             chi_bb - f_bb = -1/2 sum_kld t_kl^bd <kl||bd>,
+//             chi_jj - f_jj = +1/2 sum_cdl <jl||cd> t_jl^cd
+//   k_ring    per cross channel Q: gather T~_Q[(a,i),(c,k)] = t_ik^ac, then
+//             chi~ = <kb||cj> + 1/2 Vbar T~_Q (chi_kbcj) and Z_Q = T~_Q chi~
+//             (sum_kc t_ik^ac chi_kbcj), both on FP64 MFMA in LDS; Z is written
+//             with its P(ij)P(ab) sign into four slots per canonical amplitude
+//   k_ladder  per S_z = 0 block and 64-row tile: pp ladder sum_{c<d} <ab||cd> t_ij^cd
+//             on FP64 MFMA with <ab||cd> generated in registers from W(m), hh
+//             ladder sum_{k<l} t_kl^ab chi_klij, ring slots, one-body terms,
+//             t_new = R / eps_ij^ab, linear mixing, energy partial sums
+//   k_update  the same update for the S_z = +-1 blocks (no ladders there)
+//   k_energy  deterministic per-problem energy and convergence flag
+// Problems with the same (N, nmax2) share the integer tables; every work item
+// serves all problems of its group, so index arithmetic is done once for all
+// densities.  Reductions are fixed-order trees (no floating-point atomics):
+// energies are bit-identical from run to run.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -46,37 +50,57 @@ void set_error(const std::string& m) { g_err = m; }
         }                                                                               \
     } while (0)
 
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// D = A B + C for 16x16x4 FP64 tiles.  Lane l supplies A[l%16][l/16] and
+// B[l/16][l%16]; it receives D[l/16 + 4r][l%16], r = 0..3.
+__device__ __forceinline__ d4 mfma64(double a, double b, d4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+
 // --------------------------------------------------------------------------
 // device pointers, passed by value to every kernel
 // --------------------------------------------------------------------------
 struct DevPtrs {
-    const int32_t* st;     // packed states
-    const double* eps;     // Fock energies
-    const double* lut;     // W(m) / 2
-    const DevProb* probs;
+    const int32_t* st;       // packed states (per group structure)
+    const double* eps;       // Fock energies (per problem)
+    const double* lut;       // W(m)/2 (per problem)
+    const DevGroup* groups;
     const DevChan* chans;
     const DevPh* ph;
-    const int32_t* hh;     // packed pairs
+    const int32_t* hh;       // packed pairs (per structure)
     const int32_t* pp;
     const int32_t* phmem;
-    const int32_t* phq;
-    const int32_t* phpos;
-    const int32_t* dchi_ptr;
-    const int32_t* dchi_idx;
-    const Item* it_elem;   // elementwise items, all channels
-    const Item* it_nsz0;   // elementwise items, S_z != 0 channels
-    const Item* it_ladder; // ladder items (S_z = 0)
-    const int32_t* it_sz0; // S_z = 0 channel ids
+    const int32_t* phmap;
+    const int32_t* csr_ptr;
+    const int32_t* csr_idx;
+    const int32_t* zidx;     // per amplitude: the two ring entries (shared by a group)
+    const double* rowE;      // per particle-pair row: eps_a + eps_b (per problem)
+    const double* colE;      // per hole-pair column: eps_i + eps_j (per problem)
+    const int32_t* pgrp;     // per problem: group
+    const int32_t* pgi;      // per problem: index inside the group
+    const Item* it_elem;     // elementwise items, all channels
+    const Item* it_nsz0;     // elementwise items, S_z != 0 channels
+    const Item* it_ladder;   // ladder items (S_z = 0)
+    const int32_t* it_sz0;   // S_z = 0 channel ids
+    const Item* it_dchi;     // (group, first state)
+    const Item* it_direct;   // (S_z = 0 channel, problem in group)
+    const Item* it_ring_s;   // (primary cross channel with n <= 16, problem in group)
+    const Item* it_ring_b;   // (primary cross channel with n > 16, problem in group)
+    const Item* it_lg;       // (ladder item, problem in group)
+    const Item* it_ng;       // (S_z != 0 elementwise item, problem in group)
     double* t[2];
-    double* vt;            // <ab||ij>
+    double* vt;              // <ab||ij>
     double* chh;
     double* rowsum;
     double* colsum;
     double* dchi;
-    double* tt;            // particle-hole layout of t
-    double* z;             // ring result
-    double* epart;         // energy partials (ladder items)
-    double* epart_elem;    // energy partials (elementwise items)
+    double* zp;              // ring result per pair block {Q, -Q}
+    double* rowX;            // per row: one-body intermediates of a and b
+    double* colX;            // per column: one-body intermediates of i and j
+    double* epart;
+    double* epart_elem;
     double* ecorr;
     double* eprev;
     int32_t* active;
@@ -108,9 +132,14 @@ __device__ __forceinline__ double vas(const double* __restrict__ lut, int32_t p,
     return f > 0 ? w : -w;
 }
 
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
 // deterministic sum over a 256-thread block; result valid in thread 0
 __device__ __forceinline__ double block_sum256(double v, double* sh) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    v = wave_sum(v);
     int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     __syncthreads();
     if (lane == 0) sh[w] = v;
@@ -120,390 +149,626 @@ __device__ __forceinline__ double block_sum256(double v, double* sh) {
     return r;
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
-
-// index of Z[(p,h),(p2,h2)] in the particle-hole layout
-__device__ __forceinline__ int64_t zidx(const DevPtrs& d, const DevProb& P, int p, int h, int p2, int h2) {
-    int u = P.ph_off + (p - P.nh) * P.nh + h;
-    int v = P.ph_off + (p2 - P.nh) * P.nh + h2;
-    const DevPh q = d.ph[d.phq[u]];
-    return q.z_off + (int64_t)d.phpos[u] * q.n + d.phpos[v];
-}
-
-// P(ij)P(ab) sum_kc t_ik^ac chi_kbcj from the ring result Z
-__device__ __forceinline__ double ring_gather(const DevPtrs& d, const DevProb& P, int a, int b, int i, int j) {
-    return d.z[zidx(d, P, a, i, b, j)] - d.z[zidx(d, P, a, j, b, i)] - d.z[zidx(d, P, b, i, a, j)] +
-           d.z[zidx(d, P, b, j, a, i)];
-}
-
 // --------------------------------------------------------------------------
-// kernels
+// set-up kernels
 // --------------------------------------------------------------------------
 
-// <ab||ij>, t0 = <ab||ij> / eps_ij^ab (eq. ccdGuess); energy partial per item
+// <ab||ij>, t0 = <ab||ij> / eps_ij^ab (eq. ccdGuess), energy partials
 __global__ void __launch_bounds__(256) k_init(DevPtrs d, int cur) {
     __shared__ double sh[4];
-    const Item it = d.it_elem[blockIdx.x];
+    const int item = blockIdx.x;
+    const Item it = d.it_elem[item];
     const DevChan c = d.chans[it.chan];
-    const DevProb P = d.probs[c.prob];
+    const DevGroup G = d.groups[c.group];
     const int nel = c.nhh * c.npp;
-    double es = 0.0;
-    for (int k = 0; k < kElemChunk / 256; k++) {
-        int e = it.start + threadIdx.x + 256 * k;
-        if (e < nel && e < it.start + kElemChunk) {
-            int r = e / c.nhh, col = e - r * c.nhh;
-            int32_t ab = d.pp[c.pp_off + r], ij = d.hh[c.hh_off + col];
-            int a = pa(ab), b = pb(ab), i = pa(ij), j = pb(ij);
-            const int32_t* st = d.st + P.st_off;
-            const double* eps = d.eps + P.st_off;
-            double v = vas(d.lut + P.lut_off, st[a], st[b], st[i], st[j]);
-            double den = eps[i] + eps[j] - eps[a] - eps[b];
-            double t0 = v / den;
-            d.vt[c.t_off + e] = v;
-            d.t[cur][c.t_off + e] = t0;
-            es += v * t0;
+    const int32_t* st = d.st + G.st_off;
+    for (int g = 0; g < G.G; g++) {
+        const double* eps = d.eps + G.eps_base + g * G.ns;
+        const double* lut = d.lut + G.lut_base + g * G.nlut;
+        const int64_t E0 = G.t_base + g * G.n_amp + c.t_off;
+        double es = 0.0;
+        for (int k = 0; k < kElemChunk / 256; k++) {
+            int e = it.start + threadIdx.x + 256 * k;
+            if (e < nel && e < it.start + kElemChunk) {
+                int r = e / c.nhh, col = e - r * c.nhh;
+                int32_t ab = d.pp[c.pp_off + r], ij = d.hh[c.hh_off + col];
+                int a = pa(ab), b = pb(ab), i = pa(ij), j = pb(ij);
+                double v = vas(lut, st[a], st[b], st[i], st[j]);
+                double t0 = v / (eps[i] + eps[j] - eps[a] - eps[b]);
+                d.vt[E0 + e] = v;
+                d.t[cur][E0 + e] = t0;
+                es += v * t0;
+            }
         }
+        double s = block_sum256(es, sh);
+        if (threadIdx.x == 0) d.epart_elem[G.eelem_base + g * (G.elem_hi - G.elem_lo) + (item - G.elem_lo)] = s;
     }
-    double s = block_sum256(es, sh);
-    if (threadIdx.x == 0) d.epart_elem[blockIdx.x] = s;
 }
 
-// energy partial sums sum v t of the current amplitudes per elementwise item
+// energy partials sum v t of the current amplitudes per elementwise item
 __global__ void __launch_bounds__(256) k_dot(DevPtrs d, int cur) {
     __shared__ double sh[4];
-    const Item it = d.it_elem[blockIdx.x];
+    const int item = blockIdx.x;
+    const Item it = d.it_elem[item];
     const DevChan c = d.chans[it.chan];
+    const DevGroup G = d.groups[c.group];
     const int nel = c.nhh * c.npp;
-    double es = 0.0;
-    for (int k = 0; k < kElemChunk / 256; k++) {
-        int e = it.start + threadIdx.x + 256 * k;
-        if (e < nel && e < it.start + kElemChunk) es += d.vt[c.t_off + e] * d.t[cur][c.t_off + e];
+    for (int g = 0; g < G.G; g++) {
+        const int64_t E0 = G.t_base + g * G.n_amp + c.t_off;
+        double es = 0.0;
+        for (int k = 0; k < kElemChunk / 256; k++) {
+            int e = it.start + threadIdx.x + 256 * k;
+            if (e < nel && e < it.start + kElemChunk) es += d.vt[E0 + e] * d.t[cur][E0 + e];
+        }
+        double s = block_sum256(es, sh);
+        if (threadIdx.x == 0) d.epart_elem[G.eelem_base + g * (G.elem_hi - G.elem_lo) + (item - G.elem_lo)] = s;
     }
-    double s = block_sum256(es, sh);
-    if (threadIdx.x == 0) d.epart_elem[blockIdx.x] = s;
 }
 
 // per-problem energy from the elementwise partials; sets ecorr = eprev
 __global__ void __launch_bounds__(256) k_energy_elem(DevPtrs d) {
     __shared__ double sh[4];
-    const DevProb P = d.probs[blockIdx.x];
+    const int p = blockIdx.x;
+    const DevGroup G = d.groups[d.pgrp[p]];
+    const int g = d.pgi[p], n = G.elem_hi - G.elem_lo;
+    const double* part = d.epart_elem + G.eelem_base + g * n;
     double s = 0.0;
-    for (int x = P.elem_lo + threadIdx.x; x < P.elem_hi; x += 256) s += d.epart_elem[x];
+    for (int x = threadIdx.x; x < n; x += 256) s += part[x];
     double e = block_sum256(s, sh);
-    if (threadIdx.x == 0) { d.ecorr[blockIdx.x] = e; d.eprev[blockIdx.x] = e; }
+    if (threadIdx.x == 0) { d.ecorr[p] = e; d.eprev[p] = e; }
 }
 
-// row and column sums of t <ab||ij> for the S_z = 0 blocks (one block per channel)
-__global__ void __launch_bounds__(256) k_rowcol(DevPtrs d, int cur) {
-    __shared__ double sh[4][64];
-    const DevChan c = d.chans[d.it_sz0[blockIdx.x]];
-    if (!d.active[c.prob]) return;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const double* t = d.t[cur] + c.t_off;
-    const double* vt = d.vt + c.t_off;
-    for (int r = w; r < c.npp; r += 4) {
-        double v = lane < c.nhh ? t[(int64_t)r * c.nhh + lane] * vt[(int64_t)r * c.nhh + lane] : 0.0;
-        v = wave_sum(v);
-        if (lane == 0) d.rowsum[c.row_off + r] = v;
-    }
-    double s = 0.0;
-    if (lane < c.nhh)
-        for (int r = w; r < c.npp; r += 4) s += t[(int64_t)r * c.nhh + lane] * vt[(int64_t)r * c.nhh + lane];
-    sh[w][lane] = s;
-    __syncthreads();
-    if (w == 0 && lane < c.nhh) d.colsum[c.col_off + lane] = (sh[0][lane] + sh[1][lane]) + (sh[2][lane] + sh[3][lane]);
-}
+// --------------------------------------------------------------------------
+// sweep kernels
+// --------------------------------------------------------------------------
 
-// one-body intermediates per state from the row/column sums (fixed CSR order):
-// entry x >= 0: + colsum[x] (holes); x < 0: - rowsum[-x-1] (particles)
-__global__ void __launch_bounds__(256) k_dchi(DevPtrs d, int n_states, uint32_t mask) {
-    int s = blockIdx.x * 256 + threadIdx.x;
-    if (s >= n_states) return;
-    double acc = 0.0;
-    for (int x = d.dchi_ptr[s]; x < d.dchi_ptr[s + 1]; x++) {
-        int idx = d.dchi_idx[x];
-        if (idx >= 0) {
-            if (mask & CCD_T_QHOLE) acc += d.colsum[idx];
-        } else {
-            if (mask & CCD_T_QPART) acc -= d.rowsum[-idx - 1];
-        }
-    }
-    d.dchi[s] = acc;
-}
-
-// chi_klij = [HH] <kl||ij> + [QHH] sum_{c<d} <kl||cd> t_ij^cd (one block per S_z = 0 channel)
-__global__ void __launch_bounds__(256) k_chh(DevPtrs d, int cur, uint32_t mask) {
-    __shared__ double sv[32][kMaxHH];
-    __shared__ double stt[32][kMaxHH];
-    const DevChan c = d.chans[d.it_sz0[blockIdx.x]];
-    if (!d.active[c.prob]) return;
-    const DevProb P = d.probs[c.prob];
-    const int nhh = c.nhh, npp = c.npp, n2 = nhh * nhh;
-    double acc[kMaxHH * kMaxHH / 256];
-#pragma unroll
-    for (int k = 0; k < kMaxHH * kMaxHH / 256; k++) acc[k] = 0.0;
-    if (mask & CCD_T_QHH) {
-        const double* t = d.t[cur] + c.t_off;
-        const double* vt = d.vt + c.t_off;
-        for (int r0 = 0; r0 < npp; r0 += 32) {
-            int rc = min(32, npp - r0);
-            for (int e = threadIdx.x; e < 32 * nhh; e += 256) {
-                int r = e / nhh, col = e - r * nhh;
-                bool ok = r < rc;
-                sv[r][col] = ok ? vt[(int64_t)(r0 + r) * nhh + col] : 0.0;
-                stt[r][col] = ok ? t[(int64_t)(r0 + r) * nhh + col] : 0.0;
-            }
-            __syncthreads();
-#pragma unroll
-            for (int k = 0; k < kMaxHH * kMaxHH / 256; k++) {
-                int o = threadIdx.x + 256 * k;
-                if (o < n2) {
-                    int kl = o / nhh, ij = o - kl * nhh;
-                    double s = 0.0;
-                    for (int r = 0; r < rc; r++) s += sv[r][kl] * stt[r][ij];
-                    acc[k] += s;
-                }
-            }
-            __syncthreads();
-        }
-    }
-    const int32_t* st = d.st + P.st_off;
-#pragma unroll
-    for (int k = 0; k < kMaxHH * kMaxHH / 256; k++) {
-        int o = threadIdx.x + 256 * k;
-        if (o < n2) {
-            int kl = o / nhh, ij = o - kl * nhh;
-            double v = 0.0;
-            if (mask & CCD_T_HH) {
-                int32_t p1 = d.hh[c.hh_off + kl], p2 = d.hh[c.hh_off + ij];
-                v = vas(d.lut + P.lut_off, st[pa(p1)], st[pb(p1)], st[pa(p2)], st[pb(p2)]);
-            }
-            d.chh[c.chh_off + o] = v + acc[k];
-        }
-    }
-}
-
-// t -> particle-hole layout: each canonical amplitude lands at four places
-__global__ void __launch_bounds__(256) k_scatter(DevPtrs d, int cur) {
-    const Item it = d.it_elem[blockIdx.x];
+// per (S_z = 0 channel, problem): row sums of t v, chi_klij (its quadratic
+// part on FP64 MFMA over LDS-staged row chunks) and the column sums, which are
+// the diagonal of that product.  Wave w owns output tiles w, w+4, ...
+constexpr int kDirRows = 32;
+__global__ void __launch_bounds__(256) k_direct(DevPtrs d, int cur, uint32_t mask) {
+    __shared__ double vs[kDirRows][kMaxHH + 1];
+    __shared__ double ts[kDirRows][kMaxHH + 1];
+    const Item it = d.it_direct[blockIdx.x];
+    if (it.chan < 0) return;
     const DevChan c = d.chans[it.chan];
-    if (!d.active[c.prob]) return;
-    const DevProb P = d.probs[c.prob];
-    const int nel = c.nhh * c.npp;
-    for (int k = 0; k < kElemChunk / 256; k++) {
-        int e = it.start + threadIdx.x + 256 * k;
-        if (e < nel && e < it.start + kElemChunk) {
-            int r = e / c.nhh, col = e - r * c.nhh;
-            int32_t ab = d.pp[c.pp_off + r], ij = d.hh[c.hh_off + col];
-            int a = pa(ab), b = pb(ab), i = pa(ij), j = pb(ij);
-            double tv = d.t[cur][c.t_off + e];
-            d.tt[zidx(d, P, a, i, b, j)] = tv;
-            d.tt[zidx(d, P, a, j, b, i)] = -tv;
-            d.tt[zidx(d, P, b, i, a, j)] = -tv;
-            d.tt[zidx(d, P, b, j, a, i)] = tv;
-        }
-    }
-}
-
-// ring per cross channel Q (one block; 2 n^2 doubles of dynamic LDS):
-//   B[x][m] = <kl||cd>, (c,k) in -Q, (d,l) in Q;   A = T~_Q
-//   chi[x][y] = [RING] <kb||cj> + [QRING] 1/2 sum_m B[x][m] A[m][y]
-//   Z_Q[u][y] = sum_x A[u][x] chi[x][y]
-constexpr int kRingPer = (kMaxPH * kMaxPH + 255) / 256;
-__global__ void __launch_bounds__(256) k_ring(DevPtrs d, uint32_t mask) {
-    extern __shared__ double lds[];
-    const DevPh q = d.ph[blockIdx.x];
-    if (!d.active[q.prob]) return;
-    const DevPh pq = d.ph[q.partner];
-    const DevProb P = d.probs[q.prob];
-    const int n = q.n, n2 = n * n;
-    double* A = lds;
-    double* B = lds + n2;
-    const int32_t* st = d.st + P.st_off;
-    const double* lut = d.lut + P.lut_off;
-    for (int e = threadIdx.x; e < n2; e += 256) {
-        A[e] = d.tt[q.z_off + e];
-        double v = 0.0;
-        if (mask & CCD_T_QRING) {
-            int x = e / n, m = e - x * n;
-            int32_t ck = d.phmem[pq.mem_off + x], dl = d.phmem[q.mem_off + m];
-            v = vas(lut, st[pb(ck)], st[pb(dl)], st[pa(ck)], st[pa(dl)]);
-        }
-        B[e] = v;
-    }
-    __syncthreads();
-    double acc[kRingPer];
-#pragma unroll
-    for (int k = 0; k < kRingPer; k++) {
-        int e = threadIdx.x + 256 * k;
-        double s = 0.0;
-        if (e < n2) {
-            int x = e / n, y = e - x * n;
-            if (mask & CCD_T_QRING) {
-                for (int m = 0; m < n; m++) s += B[x * n + m] * A[m * n + y];
-                s *= 0.5;
-            }
-            if (mask & CCD_T_RING) {
-                int32_t ck = d.phmem[pq.mem_off + x], bj = d.phmem[pq.mem_off + y];
-                s += vas(lut, st[pb(ck)], st[pa(bj)], st[pa(ck)], st[pb(bj)]);
-            }
-        }
-        acc[k] = s;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < kRingPer; k++) {
-        int e = threadIdx.x + 256 * k;
-        if (e < n2) B[e] = acc[k];
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < n2; e += 256) {
-        int u = e / n, y = e - u * n;
-        double s = 0.0;
-        for (int x = 0; x < n; x++) s += A[u * n + x] * B[x * n + y];
-        d.z[q.z_off + e] = s;
-    }
-}
-
-// fused S_z = 0 update: ladders, ring gather, one-body terms, division, mixing, energy
-constexpr int kKC = 32;
-__global__ void __launch_bounds__(256) k_ladder(DevPtrs d, int cur, double alpha, uint32_t mask) {
-    // the K-loop tiles and the chi_klij block share the same LDS
-    static_assert(kKC * kMaxHH + kKC * kLadderRows >= kMaxHH * kMaxHH, "LDS union too small");
-    __shared__ double smem[kKC * kMaxHH + kKC * kLadderRows];
-    __shared__ int32_t pcs[kKC][2];
-    __shared__ double sh[4];
-    double (*Ts)[kMaxHH] = reinterpret_cast<double (*)[kMaxHH]>(smem);
-    double (*Vs)[kLadderRows] = reinterpret_cast<double (*)[kLadderRows]>(smem + kKC * kMaxHH);
-    double* chi = smem;
-    const Item it = d.it_ladder[blockIdx.x];
-    const DevChan c = d.chans[it.chan];
-    const DevProb P = d.probs[c.prob];
+    const DevGroup G = d.groups[c.group];
+    const int g = it.start;
+    if (!d.active[G.p0 + g]) return;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int nhh = c.nhh, npp = c.npp;
-    const int row = it.start + lane;
-    const bool rv = row < npp;
-    const int32_t* st = d.st + P.st_off;
-    const double* eps = d.eps + P.st_off;
-    const double* lut = d.lut + P.lut_off;
-    const double* t = d.t[cur] + c.t_off;
-    double* tn = d.t[cur ^ 1] + c.t_off;
-    const double* vt = d.vt + c.t_off;
-    const bool act = d.active[c.prob] != 0;
-    const double al = act ? alpha : 0.0;
-
-    int a = 0, b = 0;
-    int32_t sa = 0, sb = 0;
-    if (rv) {
-        int32_t ab = d.pp[c.pp_off + row];
-        a = pa(ab); b = pb(ab);
-        sa = st[a]; sb = st[b];
-    }
-    constexpr int NC = kMaxHH / 4;
-    double acc[NC];
+    const int nhh = c.nhh, npp = c.npp, nt = (nhh + 15) >> 4;
+    const int64_t E0 = G.t_base + g * G.n_amp + c.t_off;
+    const double* t = d.t[cur] + E0;
+    const double* vt = d.vt + E0;
+    const bool quad = (mask & (CCD_T_QHH | CCD_T_QHOLE)) != 0;
+    double* rows = d.rowsum + G.rows_base + g * G.n_rows + c.row_off;
+    d4 acc[4];
 #pragma unroll
-    for (int k = 0; k < NC; k++) acc[k] = 0.0;
-
-    if (act && (mask & CCD_T_PP)) {
-        for (int c0 = 0; c0 < npp; c0 += kKC) {
-            const int kc = min(kKC, npp - c0);
-            for (int e = threadIdx.x; e < kKC * nhh; e += 256) {
-                int rr = e / nhh, cc = e - rr * nhh;
-                Ts[rr][cc] = rr < kc ? t[(int64_t)(c0 + rr) * nhh + cc] : 0.0;
-            }
-            if (threadIdx.x < kKC) {
-                int32_t cd = threadIdx.x < kc ? d.pp[c.pp_off + c0 + threadIdx.x] : 0;
-                pcs[threadIdx.x][0] = threadIdx.x < kc ? st[pa(cd)] : 0;
-                pcs[threadIdx.x][1] = threadIdx.x < kc ? st[pb(cd)] : 0;
-            }
-            __syncthreads();
-#pragma unroll
-            for (int k = 0; k < kKC / 4; k++) {
-                int cl = w + 4 * k;
-                double v = 0.0;
-                if (rv && cl < kc) v = vas(lut, sa, sb, pcs[cl][0], pcs[cl][1]);
-                Vs[cl][lane] = v;
-            }
-            __syncthreads();
-            for (int cl = 0; cl < kc; cl++) {
-                double v = Vs[cl][lane];
-#pragma unroll
-                for (int k = 0; k < NC; k++) {
-                    int col = w + 4 * k;
-                    if (col < nhh) acc[k] += v * Ts[cl][col];
-                }
-            }
-            __syncthreads();
-        }
-    }
-    const bool hh_on = act && (mask & (CCD_T_HH | CCD_T_QHH));
-    if (hh_on) {
-        for (int e = threadIdx.x; e < nhh * nhh; e += 256) chi[e] = d.chh[c.chh_off + e];
+    for (int k = 0; k < 4; k++) acc[k] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int r0 = 0; r0 < npp; r0 += kDirRows) {
+        const int rc = min(kDirRows, npp - r0);
         __syncthreads();
-    }
-    const bool ring_on = act && (mask & (CCD_T_RING | CCD_T_QRING));
-    double es = 0.0;
-    if (rv) {
+        for (int e = threadIdx.x; e < kDirRows * nhh; e += 256) {
+            int r = e / nhh, j = e - r * nhh;
+            bool ok = r < rc;
+            vs[r][j] = ok ? vt[(int64_t)r0 * nhh + e] : 0.0;
+            ts[r][j] = ok ? t[(int64_t)r0 * nhh + e] : 0.0;
+        }
+        // zero the padding columns of the last tile
+        for (int e = threadIdx.x; e < kDirRows * (nt * 16 - nhh); e += 256) {
+            int r = e / (nt * 16 - nhh), j = nhh + e % (nt * 16 - nhh);
+            vs[r][j] = 0.0;
+            ts[r][j] = 0.0;
+        }
+        __syncthreads();
+        if ((mask & CCD_T_QPART) && threadIdx.x < rc) {
+            double sum = 0.0;
+            for (int j = 0; j < nhh; j++) sum += ts[threadIdx.x][j] * vs[threadIdx.x][j];
+            rows[r0 + threadIdx.x] = sum;
+        }
+        if (quad) {
 #pragma unroll
-        for (int k = 0; k < NC; k++) {
-            int col = w + 4 * k;
-            if (col < nhh) {
-                int64_t e = (int64_t)row * nhh + col;
-                double tc = t[e], v = vt[e];
+            for (int k = 0; k < 4; k++) {
+                const int tile = w + 4 * k;
+                if (tile < nt * nt) {
+                    const int ti = tile / nt, tj = tile - ti * nt;
+                    for (int kk = 0; kk < kDirRows; kk += 4) {
+                        double av = vs[kk + (lane >> 4)][ti * 16 + (lane & 15)];
+                        double bv = ts[kk + (lane >> 4)][tj * 16 + (lane & 15)];
+                        acc[k] = mfma64(av, bv, acc[k]);
+                    }
+                }
+            }
+        }
+    }
+    double* chh = d.chh + G.chh_base + g * G.n_chh + c.chh_off;
+    double* cols = d.colsum + G.cols_base + g * G.n_cols + c.col_off;
+    const double* lut = d.lut + G.lut_base + g * G.nlut;
+    const int32_t* st = d.st + G.st_off;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        const int tile = w + 4 * k;
+        if (tile < nt * nt) {
+            const int ti = tile / nt, tj = tile - ti * nt;
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                int kl = ti * 16 + (lane >> 4) + 4 * q, ij = tj * 16 + (lane & 15);
+                if (kl < nhh && ij < nhh) {
+                    double qv = acc[k][q];
+                    if (kl == ij) cols[kl] = qv;
+                    double v = 0.0;
+                    if (mask & CCD_T_HH) {
+                        int32_t p1 = d.hh[c.hh_off + kl], p2 = d.hh[c.hh_off + ij];
+                        v = vas(lut, st[pa(p1)], st[pb(p1)], st[pa(p2)], st[pb(p2)]);
+                    }
+                    chh[kl * nhh + ij] = v + ((mask & CCD_T_QHH) ? qv : 0.0);
+                }
+            }
+        }
+    }
+}
+
+// one-body intermediates: one wave per (state, problem); CSR entries x >= 0
+// name a column sum (holes, +), x < 0 the row sum -x-1 (particles, -)
+__global__ void __launch_bounds__(256) k_dchi(DevPtrs d, uint32_t mask) {
+    const Item it = d.it_dchi[blockIdx.x];
+    const DevGroup G = d.groups[it.chan];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int s = it.start + w;
+    if (s >= G.ns) return;
+    const int x0 = d.csr_ptr[G.csr_off + s], x1 = d.csr_ptr[G.csr_off + s + 1];
+    for (int g = 0; g < G.G; g++) {
+        if (!d.active[G.p0 + g]) continue;
+        const double* rows = d.rowsum + G.rows_base + g * G.n_rows;
+        const double* cols = d.colsum + G.cols_base + g * G.n_cols;
+        double acc = 0.0;
+        for (int x = x0 + lane; x < x1; x += 64) {
+            int idx = d.csr_idx[x];
+            if (idx >= 0) {
+                if (mask & CCD_T_QHOLE) acc += cols[idx];
+            } else {
+                if (mask & CCD_T_QPART) acc -= rows[-idx - 1];
+            }
+        }
+        acc = wave_sum(acc);
+        if (lane == 0) d.dchi[G.eps_base + g * G.ns + s] = acc;
+    }
+}
+
+// ring per pair {Q, P = -Q} of cross channels and problem.  With
+//   A[u][x] = T~_Q  = t_ik^ac,  (a,i) = member u of Q, (c,k) = member x of P
+//   B[x][m] = <kl||cd>,         (c,k) = member x of P, (d,l) = member m of Q
+// the partner's blocks are the transposes (T~_P = A^T, its Vbar = B^T), so
+//   chi_P = <kb||cj>_P + 1/2 B A      (chi_kbcj for the ring of Q)
+//   M_Q   = <kb||cj>_Q + 1/2 A B      (the transpose of chi_kbcj for the ring of P)
+//   Out   = A chi_P + M_Q A  =  Z_Q[u][y] + Z_P[y][u]
+// i.e. the sum of the two P(ij)P(ab) ring terms (with their common sign) that
+// land on one canonical amplitude.  Out is written in the pair block's own
+// order (coalesced); the amplitude update reads it back through the
+// (p, h) -> (channel, position) tables.  All four products run on FP64 MFMA
+// from LDS (matrices padded to n16, row stride n16 + 1).
+struct PairCtx {
+    const int32_t* map;    // position map of Q
+    const double* t;       // amplitudes of the problem
+    double* zp;            // pair block of the problem
+    int n;
+    bool self;             // Q is its own partner
+};
+
+__device__ __forceinline__ bool pair_ctx(const DevPtrs& d, const Item it, int cur, PairCtx& r,
+                                         int32_t& memQ, int32_t& memP, int32_t& lut_off) {
+    const DevPh q = d.ph[it.chan];
+    const DevGroup G = d.groups[q.group];
+    const int g = it.start;
+    r.map = d.phmap + q.map_off;
+    r.t = d.t[cur] + G.t_base + g * G.n_amp;
+    r.zp = d.zp + G.zp_base + g * G.n_zp + q.zp_off;
+    r.n = q.n;
+    r.self = q.partner == it.chan;
+    memQ = q.mem_off;
+    memP = d.ph[q.partner].mem_off;
+    lut_off = G.lut_base + g * G.nlut;
+    return d.active[G.p0 + g] != 0;
+}
+
+// stage (p, h) states of both member lists and the problem's W/2 table
+__device__ __forceinline__ void pair_stage(const DevPtrs& d, const Item it, int memQ, int memP, int lut_off,
+                                           int n, int32_t* qs, int32_t* ps, double* lutS, int t0, int stride) {
+    const DevGroup G = d.groups[d.ph[it.chan].group];
+    const int32_t* st = d.st + G.st_off;
+    for (int e = t0; e < n; e += stride) {
+        int32_t m = d.phmem[memQ + e], o = d.phmem[memP + e];
+        qs[2 * e] = st[pa(m)]; qs[2 * e + 1] = st[pb(m)];
+        ps[2 * e] = st[pa(o)]; ps[2 * e + 1] = st[pb(o)];
+    }
+    for (int e = t0; e < G.nlut; e += stride) lutS[e] = d.lut[lut_off + e];
+}
+
+// A = gathered T~_Q (signed), B = Vbar, zero padded; gathers issued 8 at a time
+template <int n16, int lda, int stride>
+__device__ __forceinline__ void pair_fill(const PairCtx& r, const int32_t* qs, const int32_t* ps,
+                                          const double* lutS, double* A, double* B, int t0, bool qring) {
+    const int n = r.n;
+    constexpr int tot = n16 * n16;
+    for (int base = t0; base < tot; base += 8 * stride) {
+        int m[8];
+        double tv[8];
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+            int e = base + j * stride;
+            int u = e / n16, x = e - u * n16;
+            m[j] = (e < tot && u < n && x < n) ? r.map[u * n + x] : -1;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; j++) tv[j] = m[j] >= 0 ? r.t[m[j] >> 3] : 0.0;
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+            int e = base + j * stride;
+            if (e < tot) {
+                int u = e / n16, x = e - u * n16;
+                double b = 0.0;
+                if (qring && u < n && x < n)  // <kl||cd>: (c,k) = P member u, (d,l) = Q member x
+                    b = vas(lutS, ps[2 * u + 1], qs[2 * x + 1], ps[2 * u], qs[2 * x]);
+                A[u * lda + x] = (m[j] & 1) ? -tv[j] : tv[j];
+                B[u * lda + x] = b;
+            }
+        }
+    }
+}
+
+// <kb||cj> between members x, y of one list (states interleaved (p, h))
+__device__ __forceinline__ double pair_vph(const int32_t* s2, const double* lutS, int x, int y) {
+    return vas(lutS, s2[2 * x + 1], s2[2 * y], s2[2 * x], s2[2 * y + 1]);
+}
+
+__device__ __forceinline__ void pair_store(const PairCtx& r, d4 acc, int tu, int ty, int lane) {
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        int u = tu * 16 + (lane >> 4) + 4 * q, y = ty * 16 + (lane & 15);
+        if (u < r.n && y < r.n) {
+            int m = r.map[u * r.n + y];
+            // a self pair holds both orders of one amplitude: keep the p < p' one
+            if (m >= 0 && !(r.self && ((m >> 2) & 1))) r.zp[u * r.n + y] = (m & 1) ? -acc[q] : acc[q];
+        }
+    }
+}
+
+// pairs with n <= 16: one wave per item, four items per block
+__global__ void __launch_bounds__(256) k_ringp_small(DevPtrs d, int cur, uint32_t mask, int n_items) {
+    constexpr int L = 17, M = 16 * 17;
+    __shared__ double mat[4][3 * M];
+    __shared__ double lutS[4][kMaxLut];
+    __shared__ int32_t qs[4][32], ps[4][32];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int idx = (int)blockIdx.x * 4 + w;
+    const Item it = d.it_ring_s[min(idx, n_items - 1)];
+    PairCtx r;
+    int32_t memQ = 0, memP = 0, lo = 0;
+    bool live = idx < n_items && it.chan >= 0;
+    if (live) live = pair_ctx(d, it, cur, r, memQ, memP, lo);
+    const bool qring = (mask & CCD_T_QRING) != 0, ring = (mask & CCD_T_RING) != 0;
+    double* A = mat[w];
+    double* B = mat[w] + M;
+    double* C = mat[w] + 2 * M;
+    if (live) pair_stage(d, it, memQ, memP, lo, r.n, qs[w], ps[w], lutS[w], lane, 64);
+    __syncthreads();
+    if (live) pair_fill<16, L, 64>(r, qs[w], ps[w], lutS[w], A, B, lane, qring);
+    __syncthreads();
+    d4 x1 = {0.0, 0.0, 0.0, 0.0}, x2 = {0.0, 0.0, 0.0, 0.0};
+    if (live) {
+        if (qring)
+            for (int m0 = 0; m0 < 16; m0 += 4) {
+                const int ra = (lane & 15) * L + m0 + (lane >> 4), rb = (m0 + (lane >> 4)) * L + (lane & 15);
+                x1 = mfma64(B[ra], A[rb], x1);
+                x2 = mfma64(A[ra], B[rb], x2);
+            }
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            int x = (lane >> 4) + 4 * q, y = lane & 15;
+            double v1 = 0.5 * x1[q], v2 = 0.5 * x2[q];
+            if (ring && x < r.n && y < r.n) {
+                v1 += pair_vph(ps[w], lutS[w], x, y);
+                v2 += pair_vph(qs[w], lutS[w], x, y);
+            }
+            x1[q] = v1;
+            x2[q] = v2;
+        }
+    }
+    __syncthreads();
+    if (live) {
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            C[((lane >> 4) + 4 * q) * L + (lane & 15)] = x1[q];
+            B[((lane >> 4) + 4 * q) * L + (lane & 15)] = x2[q];
+        }
+    }
+    __syncthreads();
+    if (live) {
+        d4 z = {0.0, 0.0, 0.0, 0.0};
+        for (int x0 = 0; x0 < 16; x0 += 4) {
+            const int ra = (lane & 15) * L + x0 + (lane >> 4), rb = (x0 + (lane >> 4)) * L + (lane & 15);
+            z = mfma64(A[ra], C[rb], z);
+            z = mfma64(B[ra], A[rb], z);
+        }
+        pair_store(r, z, 0, 0, lane);
+    }
+}
+
+// pairs with n > 16: one block per item with one wave per output tile (up to
+// 16 waves; wave w owns tiles w, w + NW, ...)
+template <int N16, int NW>
+__global__ void __launch_bounds__(64 * NW) k_ringp(DevPtrs d, int cur, uint32_t mask, int base) {
+    constexpr int n16 = N16, nt = N16 / 16, lda = N16 + 1, ntt = nt * nt, TPW = (ntt + NW - 1) / NW;
+    constexpr int NT = 64 * NW;
+    extern __shared__ double lds[];
+    const Item it = d.it_ring_b[base + blockIdx.x];
+    if (it.chan < 0) return;
+    PairCtx r;
+    int32_t memQ, memP, lo;
+    if (!pair_ctx(d, it, cur, r, memQ, memP, lo)) return;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double* A = lds;
+    double* B = A + n16 * lda;
+    double* C = B + n16 * lda;
+    double* lutS = C + n16 * lda;
+    int32_t* qs = (int32_t*)(lutS + kMaxLut);
+    int32_t* ps = qs + 2 * kMaxPH;
+    const bool qring = (mask & CCD_T_QRING) != 0, ring = (mask & CCD_T_RING) != 0;
+    pair_stage(d, it, memQ, memP, lo, r.n, qs, ps, lutS, threadIdx.x, NT);
+    __syncthreads();
+    pair_fill<n16, lda, NT>(r, qs, ps, lutS, A, B, threadIdx.x, qring);
+    __syncthreads();
+    d4 x1[TPW], x2[TPW];
+#pragma unroll
+    for (int k = 0; k < TPW; k++) { x1[k] = d4{0.0, 0.0, 0.0, 0.0}; x2[k] = x1[k]; }
+    if (qring)
+        for (int m0 = 0; m0 < n16; m0 += 4) {
+#pragma unroll
+            for (int k = 0; k < TPW; k++) {
+                const int tile = w + NW * k;
+                if (tile < ntt) {
+                    const int tx = tile / nt, ty = tile - tx * nt;
+                    const int ra = (tx * 16 + (lane & 15)) * lda + m0 + (lane >> 4);
+                    const int rb = (m0 + (lane >> 4)) * lda + ty * 16 + (lane & 15);
+                    x1[k] = mfma64(B[ra], A[rb], x1[k]);
+                    x2[k] = mfma64(A[ra], B[rb], x2[k]);
+                }
+            }
+        }
+#pragma unroll
+    for (int k = 0; k < TPW; k++) {
+        const int tile = w + NW * k;
+        if (tile < ntt) {
+            const int tx = tile / nt, ty = tile - tx * nt;
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                int x = tx * 16 + (lane >> 4) + 4 * q, y = ty * 16 + (lane & 15);
+                double v1 = 0.5 * x1[k][q], v2 = 0.5 * x2[k][q];
+                if (ring && x < r.n && y < r.n) {
+                    v1 += pair_vph(ps, lutS, x, y);
+                    v2 += pair_vph(qs, lutS, x, y);
+                }
+                x1[k][q] = v1;
+                x2[k][q] = v2;
+            }
+        }
+    }
+    __syncthreads();  // every wave has finished reading B
+#pragma unroll
+    for (int k = 0; k < TPW; k++) {
+        const int tile = w + NW * k;
+        if (tile < ntt) {
+            const int tx = tile / nt, ty = tile - tx * nt;
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const int o = (tx * 16 + (lane >> 4) + 4 * q) * lda + ty * 16 + (lane & 15);
+                C[o] = x1[k][q];
+                B[o] = x2[k][q];
+            }
+        }
+        x1[k] = d4{0.0, 0.0, 0.0, 0.0};
+    }
+    __syncthreads();
+    for (int x0 = 0; x0 < n16; x0 += 4) {
+#pragma unroll
+        for (int k = 0; k < TPW; k++) {
+            const int tile = w + NW * k;
+            if (tile < ntt) {
+                const int tu = tile / nt, ty = tile - tu * nt;
+                const int ra = (tu * 16 + (lane & 15)) * lda + x0 + (lane >> 4);
+                const int rb = (x0 + (lane >> 4)) * lda + ty * 16 + (lane & 15);
+                x1[k] = mfma64(A[ra], C[rb], x1[k]);
+                x1[k] = mfma64(B[ra], A[rb], x1[k]);
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < TPW; k++) {
+        const int tile = w + NW * k;
+        if (tile < ntt) pair_store(r, x1[k], tile / nt, tile % nt, lane);
+    }
+}
+
+// the ring contribution to amplitude e of problem g: two pair-block entries
+__device__ __forceinline__ double ring_term(const DevPtrs& d, const DevGroup& G, int g, int64_t e) {
+    const double* zp = d.zp + G.zp_base + g * G.n_zp;
+    const int32_t* zi = d.zidx + G.zidx_off + 2 * e;
+    return zp[zi[0]] + zp[zi[1]];
+}
+
+// one-body sums per row (delta chi_a + delta chi_b) and column (delta chi_i +
+// delta chi_j); grid (blocks over rows + columns, problem slot)
+__global__ void __launch_bounds__(256) k_onebody(DevPtrs d) {
+    const int p = blockIdx.y;
+    const DevGroup G = d.groups[d.pgrp[p]];
+    const int g = d.pgi[p];
+    if (!d.active[G.p0 + g]) return;
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    const double* dc = d.dchi + G.eps_base + g * G.ns;
+    if (e < G.n_rows_all) {
+        int32_t ab = d.pp[G.pp0 + e];
+        d.rowX[G.rowa_base + g * G.n_rows_all + e] = dc[pa(ab)] + dc[pb(ab)];
+    } else if (e < G.n_rows_all + G.n_cols_all) {
+        int q = e - G.n_rows_all;
+        int32_t ij = d.hh[G.hh0 + q];
+        d.colX[G.cola_base + g * G.n_cols_all + q] = dc[pa(ij)] + dc[pb(ij)];
+    }
+}
+
+// fused S_z = 0 update per (64-row tile of a channel, problem).  Wave w owns
+// rows 16w .. 16w+15 and one 16-column tile of hole pairs at a time.  The pp
+// ladder runs on FP64 MFMA with <ab||cd> generated per lane in the A-operand
+// layout from W(m) in LDS; up to 256 particle-pair rows of t are staged per
+// barrier, so the K loop itself has no barrier.  Then the hh ladder (MFMA),
+// the ring term, one-body terms, t_new = R / eps_ij^ab, mixing and the energy
+// partial sum.
+constexpr int kKP = 256;  // particle-pair columns staged per barrier
+__global__ void __launch_bounds__(256) k_ladder(DevPtrs d, int cur, double alpha, uint32_t mask) {
+    __shared__ double lutS[kMaxLut];
+    __shared__ double Tk[kKP][16];
+    __shared__ int32_t cvec[kKP];
+    __shared__ int32_t cinfo[kKP];
+    __shared__ double sh[4];
+    const Item lg = d.it_lg[blockIdx.x];
+    if (lg.chan < 0) return;
+    const int litem = lg.chan, g = lg.start;
+    const Item it = d.it_ladder[litem];
+    const DevChan c = d.chans[it.chan];
+    const DevGroup G = d.groups[c.group];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int nhh = c.nhh, npp = c.npp, nct = (nhh + 15) >> 4;
+    const int32_t* st = d.st + G.st_off;
+    const bool act = d.active[G.p0 + g] != 0;
+    const bool pp_on = act && (mask & CCD_T_PP) != 0;
+    const bool hh_on = act && (mask & (CCD_T_HH | CCD_T_QHH)) != 0;
+    const bool ring_on = (mask & (CCD_T_RING | CCD_T_QRING)) != 0;
+    const int64_t T0 = G.t_base + g * G.n_amp + c.t_off;
+    const double* tcur = d.t[cur] + T0;
+
+    for (int e = threadIdx.x; e < G.nlut; e += 256) lutS[e] = d.lut[G.lut_base + g * G.nlut + e];
+
+    // generator row of this lane (A-operand row = lane % 16)
+    const int ra = it.start + 16 * w + (lane & 15);
+    const bool rav = ra < npp;
+    int ax = 0, ay = 0, az = 0, A2 = 0, AK = 0, sa = 0;
+    if (rav) {
+        int32_t s1 = st[pa(d.pp[c.pp_off + ra])];
+        ax = s_x(s1); ay = s_y(s1); az = s_z(s1); sa = s_s(s1) > 0 ? 1 : 0;
+        A2 = ax * ax + ay * ay + az * az;
+        AK = A2 - 2 * (ax * c.kx + ay * c.ky + az * c.kz);
+    }
+    double es = 0.0;
+    for (int ct = 0; ct < nct; ct++) {
+        const int col = ct * 16 + (lane & 15);
+        d4 acc = {0.0, 0.0, 0.0, 0.0};
+        if (pp_on) {
+            for (int kp = 0; kp < npp; kp += kKP) {
+                const int kn = min(kKP, npp - kp);
+                __syncthreads();
+                for (int e = threadIdx.x; e < kKP * 16; e += 256) {
+                    const int kk = e >> 4, cc = ct * 16 + (e & 15);
+                    Tk[kk][e & 15] = (kk < kn && cc < nhh) ? tcur[(int64_t)(kp + kk) * nhh + cc] : 0.0;
+                }
+                for (int kk = threadIdx.x; kk < kKP; kk += 256) {
+                    int32_t vec = 0, inf = 0;
+                    if (kk < kn) {
+                        int32_t cd = d.pp[c.pp_off + kp + kk];
+                        int32_t sc = st[pa(cd)], sd = st[pb(cd)];
+                        int cx = s_x(sc), cy = s_y(sc), cz = s_z(sc);
+                        int dx = s_x(sd), dy = s_y(sd), dz = s_z(sd);
+                        vec = sc & 0x00ffffff;
+                        inf = (cx * cx + cy * cy + cz * cz) | ((dx * dx + dy * dy + dz * dz) << 10) |
+                              ((s_s(sc) > 0 ? 1 : 0) << 20) | (1 << 21);
+                    }
+                    cvec[kk] = vec;
+                    cinfo[kk] = inf;
+                }
+                __syncthreads();
+                const int ksteps = (kn + 3) & ~3;
+#pragma unroll 4
+                for (int kk = 0; kk < ksteps; kk += 4) {
+                    const int k = kk + (lane >> 4);
+                    const int32_t vec = cvec[k], inf = cinfo[k];
+                    const int ac = ax * s_x(vec) + ay * s_y(vec) + az * s_z(vec);
+                    const bool valid = rav && ((inf >> 21) & 1);
+                    const int m1 = valid ? A2 + (inf & 1023) - 2 * ac : 0;
+                    const int m2 = valid ? AK + ((inf >> 10) & 1023) + 2 * ac : 0;
+                    double v = lutS[m1] + lutS[m2];
+                    v = valid ? ((((inf >> 20) & 1) == sa) ? v : -v) : 0.0;
+                    acc = mfma64(v, Tk[k][lane & 15], acc);
+                }
+            }
+        }
+        if (hh_on) {
+            const double* xg = d.chh + G.chh_base + g * G.n_chh + c.chh_off;
+            for (int k0 = 0; k0 < nhh; k0 += 4) {
+                const int kq = k0 + (lane >> 4);
+                double a = (rav && kq < nhh) ? tcur[(int64_t)ra * nhh + kq] : 0.0;
+                double b = (kq < nhh && col < nhh) ? xg[kq * nhh + col] : 0.0;
+                acc = mfma64(a, b, acc);
+            }
+        }
+        // epilogue: this lane owns rows 16w + lane/16 + 4r of column col
+        const double* rowE = d.rowE + G.rowa_base + g * G.n_rows_all + c.rowa_off;
+        const double* rowX = d.rowX + G.rowa_base + g * G.n_rows_all + c.rowa_off;
+        double cE = 0.0, cX = 0.0;
+        if (col < nhh) {
+            cE = d.colE[G.cola_base + g * G.n_cols_all + c.cola_off + col];
+            cX = d.colX[G.cola_base + g * G.n_cols_all + c.cola_off + col];
+        }
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const int row = it.start + 16 * w + (lane >> 4) + 4 * r;
+            if (row < npp && col < nhh) {
+                const int64_t e = (int64_t)row * nhh + col;
+                const double tc = tcur[e], v = d.vt[T0 + e];
                 double tm = tc;
                 if (act) {
-                    int32_t ij = d.hh[c.hh_off + col];
-                    int i = pa(ij), j = pb(ij);
-                    double R = v + acc[k];
-                    if (hh_on) {
-                        double s = 0.0;
-                        for (int kl = 0; kl < nhh; kl++) s += t[(int64_t)row * nhh + kl] * chi[kl * nhh + col];
-                        R += s;
-                    }
-                    if (ring_on) R += ring_gather(d, P, a, b, i, j);
-                    const double* dc = d.dchi + P.st_off;
-                    R += (dc[a] + dc[b] - dc[i] - dc[j]) * tc;
-                    double den = eps[i] + eps[j] - eps[a] - eps[b];
-                    tm = al * (R / den) + (1.0 - al) * tc;
+                    double R = v + acc[r];
+                    if (ring_on) R += ring_term(d, G, g, c.t_off + e);
+                    R += (rowX[row] - cX) * tc;
+                    tm = alpha * (R / (cE - rowE[row])) + (1.0 - alpha) * tc;
                 }
-                tn[e] = tm;
+                d.t[cur ^ 1][T0 + e] = tm;
                 es += v * tm;
             }
         }
     }
     double s = block_sum256(es, sh);
-    if (threadIdx.x == 0) d.epart[blockIdx.x] = s;
+    const int nitem = G.ladder_hi - G.ladder_lo;
+    if (threadIdx.x == 0) d.epart[G.epart_base + g * nitem + (litem - G.ladder_lo)] = s;
 }
 
 // update of the S_z = +-1 blocks: only the ring and one-body terms survive
 __global__ void __launch_bounds__(256) k_update(DevPtrs d, int cur, double alpha, uint32_t mask) {
-    const Item it = d.it_nsz0[blockIdx.x];
+    const Item ig = d.it_ng[blockIdx.x];
+    if (ig.chan < 0) return;
+    const Item it = d.it_nsz0[ig.chan];
+    const int g = ig.start;
     const DevChan c = d.chans[it.chan];
-    const DevProb P = d.probs[c.prob];
-    const bool act = d.active[c.prob] != 0;
-    const bool ring_on = act && (mask & (CCD_T_RING | CCD_T_QRING));
+    const DevGroup G = d.groups[c.group];
+    const bool ring_on = (mask & (CCD_T_RING | CCD_T_QRING)) != 0;
     const int nel = c.nhh * c.npp;
-    const double* eps = d.eps + P.st_off;
-    const double* dc = d.dchi + P.st_off;
+    const bool act = d.active[G.p0 + g] != 0;
+    const int64_t T0 = G.t_base + g * G.n_amp + c.t_off;
+    const double* rowE = d.rowE + G.rowa_base + g * G.n_rows_all + c.rowa_off;
+    const double* rowX = d.rowX + G.rowa_base + g * G.n_rows_all + c.rowa_off;
+    const double* colE = d.colE + G.cola_base + g * G.n_cols_all + c.cola_off;
+    const double* colX = d.colX + G.cola_base + g * G.n_cols_all + c.cola_off;
     for (int k = 0; k < kElemChunk / 256; k++) {
         int e = it.start + threadIdx.x + 256 * k;
         if (e < nel && e < it.start + kElemChunk) {
-            double tc = d.t[cur][c.t_off + e];
+            const int64_t E = T0 + e;
+            double tc = d.t[cur][E];
             double tm = tc;
             if (act) {
                 int r = e / c.nhh, col = e - r * c.nhh;
-                int32_t ab = d.pp[c.pp_off + r], ij = d.hh[c.hh_off + col];
-                int a = pa(ab), b = pb(ab), i = pa(ij), j = pb(ij);
-                double R = d.vt[c.t_off + e];
-                if (ring_on) R += ring_gather(d, P, a, b, i, j);
-                R += (dc[a] + dc[b] - dc[i] - dc[j]) * tc;
-                double den = eps[i] + eps[j] - eps[a] - eps[b];
-                tm = alpha * (R / den) + (1.0 - alpha) * tc;
+                double R = d.vt[E];
+                if (ring_on) R += ring_term(d, G, g, c.t_off + e);
+                R += (rowX[r] - colX[col]) * tc;
+                tm = alpha * (R / (colE[col] - rowE[r])) + (1.0 - alpha) * tc;
             }
-            d.t[cur ^ 1][c.t_off + e] = tm;
+            d.t[cur ^ 1][E] = tm;
         }
     }
 }
@@ -512,9 +777,11 @@ __global__ void __launch_bounds__(256) k_update(DevPtrs d, int cur, double alpha
 __global__ void __launch_bounds__(256) k_energy(DevPtrs d, double tol) {
     __shared__ double sh[4];
     const int p = blockIdx.x;
-    const DevProb P = d.probs[p];
+    const DevGroup G = d.groups[d.pgrp[p]];
+    const int g = d.pgi[p], n = G.ladder_hi - G.ladder_lo;
+    const double* part = d.epart + G.epart_base + g * n;
     double s = 0.0;
-    for (int x = P.ladder_lo + threadIdx.x; x < P.ladder_hi; x += 256) s += d.epart[x];
+    for (int x = threadIdx.x; x < n; x += 256) s += part[x];
     double e = block_sum256(s, sh);
     if (threadIdx.x == 0 && d.active[p]) {
         double old = d.ecorr[p];
@@ -529,9 +796,9 @@ __global__ void __launch_bounds__(256) k_energy(DevPtrs d, double tol) {
 // --------------------------------------------------------------------------
 // context
 // --------------------------------------------------------------------------
-enum Family { F_INIT = 0, F_ROWCOL, F_DCHI, F_CHH, F_SCATTER, F_RING, F_LADDER, F_UPDATE, F_ENERGY, F_NUM };
-static const char* kFamilyNames[F_NUM] = {"init", "rowcol", "dchi", "chi_hhhh", "ph_scatter",
-                                          "ring", "ladder_update", "update_sz1", "energy"};
+enum Family { F_INIT = 0, F_DIRECT, F_DCHI, F_RING_S, F_RING_B, F_LADDER, F_UPDATE, F_ENERGY, F_NUM };
+static const char* kFamilyNames[F_NUM] = {"init", "direct", "dchi", "ring_small", "ring", "ladder_update",
+                                          "update_sz1", "energy"};
 
 struct Region {
     size_t off = 0, bytes = 0;
@@ -541,17 +808,21 @@ struct ccd_ctx {
     std::vector<HostProblem> probs;
     hipStream_t stream = nullptr;
     // concatenated host tables
-    std::vector<DevProb> dprobs;
+    std::vector<DevGroup> dgroups;
     std::vector<DevChan> dchans;
     std::vector<DevPh> dph;
-    std::vector<int32_t> st, hh, pp, phmem, phq, phpos, dchi_ptr, dchi_idx, it_sz0;
-    std::vector<double> eps, lut;
-    std::vector<Item> it_elem, it_nsz0, it_ladder;
-    int64_t NT = 0, NZ = 0;
-    int n_rows = 0, n_cols = 0, n_chh = 0, ns_tot = 0, max_ph = 0;
+    std::vector<int32_t> st, hh, pp, phmem, phmap, zidx, csr_ptr, csr_idx, pgrp, pgi, it_sz0;
+    std::vector<double> eps, lut, rowE, colE;
+    std::vector<Item> it_elem, it_nsz0, it_ladder, it_dchi, it_direct, it_ring_s, it_ring_b, it_lg, it_ng;
+    int ring_lo[4] = {0}, ring_n[4] = {0};  // big pair items by padded size n16 = 32, 48, 64, 80
+    int64_t NZP = 0;                         // ring-result entries, all problems
+    std::vector<int64_t> prob_t0;  // amplitude index of each problem (caller order)
+    std::vector<int> slot_of;      // caller problem -> slot (group order) of the device flags
+    int64_t NT = 0;
+    int n_rows = 0, n_cols = 0, n_chh = 0, n_eps = 0, n_epart = 0, n_eparte = 0, max_ph = 0;
     // workspace
-    Region r_static, r_t0, r_t1, r_vt, r_chh, r_rows, r_cols, r_dchi, r_tt, r_z, r_epart, r_eparte,
-        r_ecorr, r_eprev, r_emp2, r_active, r_sweeps;
+    Region r_static, r_t0, r_t1, r_vt, r_chh, r_rows, r_cols, r_dchi, r_zp, r_rowx, r_colx, r_epart, r_eparte,
+        r_ecorr, r_eprev, r_active, r_sweeps;
     size_t ws_bytes = 0;
     char* ws = nullptr;
     bool bound = false;
@@ -568,32 +839,42 @@ struct ccd_ctx {
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+#define STATIC_TABLES(X)                                                  \
+    X(st, int32_t) X(eps, double) X(lut, double) X(dgroups, DevGroup)     \
+    X(dchans, DevChan) X(dph, DevPh) X(hh, int32_t) X(pp, int32_t)        \
+    X(phmem, int32_t) X(phmap, int32_t) X(zidx, int32_t) X(rowE, double) X(colE, double) \
+    X(csr_ptr, int32_t)                                                   \
+    X(csr_idx, int32_t) X(pgrp, int32_t) X(pgi, int32_t)                  \
+    X(it_elem, Item) X(it_nsz0, Item) X(it_ladder, Item) X(it_sz0, int32_t) X(it_dchi, Item) \
+    X(it_direct, Item) X(it_ring_s, Item) X(it_ring_b, Item) X(it_lg, Item) X(it_ng, Item)
+
 static DevPtrs make_ptrs(ccd_ctx* c) {
     DevPtrs d;
     char* base = c->ws;
     size_t o = c->r_static.off;
-    auto take = [&](size_t bytes) {
-        char* p = base + o;
-        o += align256(bytes);
-        return p;
-    };
-    d.st = (const int32_t*)take(c->st.size() * 4);
-    d.eps = (const double*)take(c->eps.size() * 8);
-    d.lut = (const double*)take(c->lut.size() * 8);
-    d.probs = (const DevProb*)take(c->dprobs.size() * sizeof(DevProb));
-    d.chans = (const DevChan*)take(c->dchans.size() * sizeof(DevChan));
-    d.ph = (const DevPh*)take(c->dph.size() * sizeof(DevPh));
-    d.hh = (const int32_t*)take(c->hh.size() * 4);
-    d.pp = (const int32_t*)take(c->pp.size() * 4);
-    d.phmem = (const int32_t*)take(c->phmem.size() * 4);
-    d.phq = (const int32_t*)take(c->phq.size() * 4);
-    d.phpos = (const int32_t*)take(c->phpos.size() * 4);
-    d.dchi_ptr = (const int32_t*)take(c->dchi_ptr.size() * 4);
-    d.dchi_idx = (const int32_t*)take(c->dchi_idx.size() * 4);
-    d.it_elem = (const Item*)take(c->it_elem.size() * sizeof(Item));
-    d.it_nsz0 = (const Item*)take(c->it_nsz0.size() * sizeof(Item));
-    d.it_ladder = (const Item*)take(c->it_ladder.size() * sizeof(Item));
-    d.it_sz0 = (const int32_t*)take(c->it_sz0.size() * 4);
+    const void* p_st; const void* p_eps; const void* p_lut; const void* p_dgroups; const void* p_dchans;
+    const void* p_dph; const void* p_hh; const void* p_pp; const void* p_phmem; const void* p_phmap;
+    const void* p_csr_ptr; const void* p_csr_idx; const void* p_pgrp; const void* p_pgi;
+    const void* p_it_elem; const void* p_it_nsz0; const void* p_it_ladder; const void* p_it_sz0;
+    const void* p_it_dchi; const void* p_it_direct; const void* p_it_ring_s; const void* p_it_ring_b;
+    const void* p_it_lg; const void* p_it_ng; const void* p_zidx; const void* p_rowE; const void* p_colE;
+#define TAKE(name, T)             \
+    p_##name = base + o;          \
+    o += align256(c->name.size() * sizeof(T));
+    STATIC_TABLES(TAKE)
+#undef TAKE
+    d.st = (const int32_t*)p_st; d.eps = (const double*)p_eps; d.lut = (const double*)p_lut;
+    d.groups = (const DevGroup*)p_dgroups; d.chans = (const DevChan*)p_dchans; d.ph = (const DevPh*)p_dph;
+    d.hh = (const int32_t*)p_hh; d.pp = (const int32_t*)p_pp; d.phmem = (const int32_t*)p_phmem;
+    d.phmap = (const int32_t*)p_phmap; d.csr_ptr = (const int32_t*)p_csr_ptr;
+    d.csr_idx = (const int32_t*)p_csr_idx; d.pgrp = (const int32_t*)p_pgrp; d.pgi = (const int32_t*)p_pgi;
+    d.it_elem = (const Item*)p_it_elem; d.it_nsz0 = (const Item*)p_it_nsz0;
+    d.it_ladder = (const Item*)p_it_ladder; d.it_sz0 = (const int32_t*)p_it_sz0;
+    d.it_dchi = (const Item*)p_it_dchi;
+    d.it_direct = (const Item*)p_it_direct; d.it_ring_s = (const Item*)p_it_ring_s;
+    d.it_ring_b = (const Item*)p_it_ring_b; d.it_lg = (const Item*)p_it_lg;
+    d.it_ng = (const Item*)p_it_ng; d.zidx = (const int32_t*)p_zidx;
+    d.rowE = (const double*)p_rowE; d.colE = (const double*)p_colE;
     d.t[0] = (double*)(base + c->r_t0.off);
     d.t[1] = (double*)(base + c->r_t1.off);
     d.vt = (double*)(base + c->r_vt.off);
@@ -601,8 +882,9 @@ static DevPtrs make_ptrs(ccd_ctx* c) {
     d.rowsum = (double*)(base + c->r_rows.off);
     d.colsum = (double*)(base + c->r_cols.off);
     d.dchi = (double*)(base + c->r_dchi.off);
-    d.tt = (double*)(base + c->r_tt.off);
-    d.z = (double*)(base + c->r_z.off);
+    d.zp = (double*)(base + c->r_zp.off);
+    d.rowX = (double*)(base + c->r_rowx.off);
+    d.colX = (double*)(base + c->r_colx.off);
     d.epart = (double*)(base + c->r_epart.off);
     d.epart_elem = (double*)(base + c->r_eparte.off);
     d.ecorr = (double*)(base + c->r_ecorr.off);
@@ -616,164 +898,243 @@ static DevPtrs make_ptrs(ccd_ctx* c) {
 static std::vector<char> static_image(const ccd_ctx* c) {
     std::vector<char> img(c->r_static.bytes, 0);
     size_t o = 0;
-    auto put = [&](const void* src, size_t bytes) {
-        if (bytes) std::memcpy(img.data() + o, src, bytes);
-        o += align256(bytes);
-    };
-    put(c->st.data(), c->st.size() * 4);
-    put(c->eps.data(), c->eps.size() * 8);
-    put(c->lut.data(), c->lut.size() * 8);
-    put(c->dprobs.data(), c->dprobs.size() * sizeof(DevProb));
-    put(c->dchans.data(), c->dchans.size() * sizeof(DevChan));
-    put(c->dph.data(), c->dph.size() * sizeof(DevPh));
-    put(c->hh.data(), c->hh.size() * 4);
-    put(c->pp.data(), c->pp.size() * 4);
-    put(c->phmem.data(), c->phmem.size() * 4);
-    put(c->phq.data(), c->phq.size() * 4);
-    put(c->phpos.data(), c->phpos.size() * 4);
-    put(c->dchi_ptr.data(), c->dchi_ptr.size() * 4);
-    put(c->dchi_idx.data(), c->dchi_idx.size() * 4);
-    put(c->it_elem.data(), c->it_elem.size() * sizeof(Item));
-    put(c->it_nsz0.data(), c->it_nsz0.size() * sizeof(Item));
-    put(c->it_ladder.data(), c->it_ladder.size() * sizeof(Item));
-    put(c->it_sz0.data(), c->it_sz0.size() * 4);
+#define PUT(name, T)                                                              \
+    if (!c->name.empty()) std::memcpy(img.data() + o, c->name.data(), c->name.size() * sizeof(T)); \
+    o += align256(c->name.size() * sizeof(T));
+    STATIC_TABLES(PUT)
+#undef PUT
     return img;
 }
 
 static void layout(ccd_ctx* c) {
     size_t s = 0;
-    auto add = [&](size_t bytes) { s += align256(bytes); };
-    add(c->st.size() * 4); add(c->eps.size() * 8); add(c->lut.size() * 8);
-    add(c->dprobs.size() * sizeof(DevProb)); add(c->dchans.size() * sizeof(DevChan));
-    add(c->dph.size() * sizeof(DevPh)); add(c->hh.size() * 4); add(c->pp.size() * 4);
-    add(c->phmem.size() * 4); add(c->phq.size() * 4); add(c->phpos.size() * 4);
-    add(c->dchi_ptr.size() * 4); add(c->dchi_idx.size() * 4);
-    add(c->it_elem.size() * sizeof(Item)); add(c->it_nsz0.size() * sizeof(Item));
-    add(c->it_ladder.size() * sizeof(Item)); add(c->it_sz0.size() * 4);
+#define ADD(name, T) s += align256(c->name.size() * sizeof(T));
+    STATIC_TABLES(ADD)
+#undef ADD
     size_t o = 0;
     auto region = [&](Region& r, size_t bytes) {
         r.off = o;
         r.bytes = bytes;
-        o += align256(bytes);
+        o += align256(std::max<size_t>(bytes, 8));
     };
     size_t P = c->probs.size();
     region(c->r_static, s);
     region(c->r_t0, c->NT * 8);
     region(c->r_t1, c->NT * 8);
     region(c->r_vt, c->NT * 8);
-    region(c->r_chh, (size_t)std::max(1, c->n_chh) * 8);
-    region(c->r_rows, (size_t)std::max(1, c->n_rows) * 8);
-    region(c->r_cols, (size_t)std::max(1, c->n_cols) * 8);
-    region(c->r_dchi, (size_t)c->ns_tot * 8);
-    region(c->r_tt, c->NZ * 8);
-    region(c->r_z, c->NZ * 8);
-    region(c->r_epart, std::max<size_t>(1, c->it_ladder.size()) * 8);
-    region(c->r_eparte, std::max<size_t>(1, c->it_elem.size()) * 8);
+    region(c->r_chh, (size_t)c->n_chh * 8);
+    region(c->r_rows, (size_t)c->n_rows * 8);
+    region(c->r_cols, (size_t)c->n_cols * 8);
+    region(c->r_dchi, (size_t)c->n_eps * 8);
+    region(c->r_zp, (size_t)c->NZP * 8);
+    region(c->r_rowx, c->rowE.size() * 8);
+    region(c->r_colx, c->colE.size() * 8);
+    region(c->r_epart, (size_t)c->n_epart * 8);
+    region(c->r_eparte, (size_t)c->n_eparte * 8);
     region(c->r_ecorr, P * 8);
     region(c->r_eprev, P * 8);
-    region(c->r_emp2, P * 8);
     region(c->r_active, P * 4);
     region(c->r_sweeps, P * 4);
     c->ws_bytes = o;
 }
 
+// Blocks are dispatched to the eight XCDs round-robin by block index.  Work
+// lists sorted by problem are cut into eight contiguous pieces, piece x going
+// to XCD x, so each XCD's L2 sees the data of about one problem.  Units of u
+// consecutive items stay together; padding items have chan = -1.
+static std::vector<Item> xcd_order(std::vector<std::pair<int, Item>> v, int u = 1) {
+    std::stable_sort(v.begin(), v.end(), [](const std::pair<int, Item>& a, const std::pair<int, Item>& b) {
+        return a.first < b.first;
+    });
+    const size_t nunits = (v.size() + u - 1) / u;
+    if (nunits == 0) return {};
+    const size_t per = (nunits + 7) / 8;
+    std::vector<Item> out(per * 8 * u, Item{-1, 0});
+    for (size_t k = 0; k < v.size(); k++) {
+        const size_t unit = k / u, x = unit / per, j = unit % per;
+        out[(j * 8 + x) * u + k % u] = v[k].second;
+    }
+    return out;
+}
+
+// group the problems by structure and lay out the device tables
 static ccd_status assemble(ccd_ctx* c) {
-    int st_off = 0, lut_off = 0, ph_off = 0, hh_off = 0, pp_off = 0, phm_off = 0, phc_off = 0;
-    int64_t t_off = 0, z_off = 0;
-    int row_off = 0, col_off = 0, chh_off = 0;
-    // per-state CSR lists for the one-body intermediates
-    std::vector<std::vector<int32_t>> lists;
-    for (size_t pi = 0; pi < c->probs.size(); pi++) {
-        HostProblem& H = c->probs[pi];
-        DevProb P;
-        P.ns = H.ns; P.nh = H.nh; P.np = H.np;
-        P.st_off = st_off; P.lut_off = lut_off; P.ph_off = ph_off;
+    std::map<std::pair<int, int>, std::vector<int>> by_structure;
+    for (size_t p = 0; p < c->probs.size(); p++)
+        by_structure[{c->probs[p].par.n_particles, c->probs[p].par.nmax2}].push_back((int)p);
+    const size_t P = c->probs.size();
+    c->pgrp.assign(P, 0);
+    c->pgi.assign(P, 0);
+    c->prob_t0.assign(P, 0);
+    c->slot_of.assign(P, 0);
+    std::vector<std::pair<int, Item>> lg, ng, dir, rs, rb[4];
+    int64_t t_base = 0, zp_base = 0;
+    int gi = 0, slot0 = 0;
+    for (auto& kv : by_structure) {
+        const std::vector<int>& members = kv.second;
+        const HostProblem& H = c->probs[members[0]];
+        DevGroup D;
+        std::memset(&D, 0, sizeof(D));
+        D.G = (int)members.size();
+        D.p0 = slot0;
+        D.ns = H.ns; D.nh = H.nh; D.np = H.np; D.nlut = (int)H.W.size();
+        D.n_amp = H.n_amp;
+        D.t_base = t_base;
+        D.st_off = (int)c->st.size();
+        D.eps_base = c->n_eps;
+        D.lut_base = (int)c->lut.size();
         for (int s = 0; s < H.ns; s++) c->st.push_back(pack_state(H.nx[s], H.ny[s], H.nz[s], H.sz[s]));
-        c->eps.insert(c->eps.end(), H.eps.begin(), H.eps.end());
-        for (double w : H.W) c->lut.push_back(0.5 * w);
-        lists.resize(st_off + H.ns);
-        // direct channels
-        P.elem_lo = (int)c->it_elem.size();
-        P.ladder_lo = (int)c->it_ladder.size();
-        for (size_t ci = 0; ci < H.chans.size(); ci++) {
-            const Chan& h = H.chans[ci];
-            DevChan d;
-            d.t_off = t_off + h.t_off;
-            d.prob = (int)pi;
-            d.nhh = h.nhh; d.npp = h.npp; d.sz = h.Sz;
-            d.hh_off = hh_off + h.hh_off;
-            d.pp_off = pp_off + h.pp_off;
-            d.chh_off = -1; d.row_off = -1; d.col_off = -1; d.pad = 0;
-            int gid = (int)c->dchans.size();
-            if (h.Sz == 0) {
-                d.chh_off = chh_off; chh_off += h.nhh * h.nhh;
-                d.row_off = row_off;
-                d.col_off = col_off;
-                for (int r = 0; r < h.npp; r++) {
-                    int a = H.pp[2 * (h.pp_off + r)], b = H.pp[2 * (h.pp_off + r) + 1];
-                    lists[st_off + a].push_back(-(row_off + r) - 1);
-                    lists[st_off + b].push_back(-(row_off + r) - 1);
-                }
-                for (int q = 0; q < h.nhh; q++) {
-                    int i = H.hh[2 * (h.hh_off + q)], j = H.hh[2 * (h.hh_off + q) + 1];
-                    lists[st_off + i].push_back(col_off + q);
-                    lists[st_off + j].push_back(col_off + q);
-                }
-                row_off += h.npp; col_off += h.nhh;
-                c->it_sz0.push_back(gid);
-                for (int r0 = 0; r0 < h.npp; r0 += kLadderRows) c->it_ladder.push_back({gid, r0});
-            }
-            int nel = h.nhh * h.npp;
-            for (int e0 = 0; e0 < nel; e0 += kElemChunk) {
-                c->it_elem.push_back({gid, e0});
-                if (h.Sz != 0) c->it_nsz0.push_back({gid, e0});
-            }
-            c->dchans.push_back(d);
+        for (int g = 0; g < D.G; g++) {
+            const HostProblem& Hg = c->probs[members[g]];
+            c->eps.insert(c->eps.end(), Hg.eps.begin(), Hg.eps.end());
+            for (double wv : Hg.W) c->lut.push_back(0.5 * wv);
+            c->pgrp[members[g]] = gi;
+            c->pgi[members[g]] = g;
+            c->slot_of[members[g]] = slot0 + g;
+            c->prob_t0[members[g]] = t_base + (int64_t)g * H.n_amp;
         }
-        P.elem_hi = (int)c->it_elem.size();
-        P.ladder_hi = (int)c->it_ladder.size();
+        c->n_eps += D.G * H.ns;
+        // direct channels
+        const int hh0 = (int)c->hh.size(), pp0 = (int)c->pp.size();
         for (size_t k = 0; k < H.hh.size() / 2; k++) c->hh.push_back(pack_pair(H.hh[2 * k], H.hh[2 * k + 1]));
         for (size_t k = 0; k < H.pp.size() / 2; k++) c->pp.push_back(pack_pair(H.pp[2 * k], H.pp[2 * k + 1]));
-        // cross channels
-        for (const PhChan& h : H.ph) {
-            DevPh d;
-            d.z_off = z_off + h.z_off;
-            d.prob = (int)pi;
-            d.n = h.n;
-            d.partner = phc_off + h.partner;
-            d.mem_off = phm_off + h.mem_off;
-            c->dph.push_back(d);
+        int rows = 0, cols = 0, chh = 0;
+        std::vector<std::vector<int32_t>> lists(H.ns);
+        D.ladder_lo = (int)c->it_ladder.size();
+        D.elem_lo = (int)c->it_elem.size();
+        for (const Chan& h : H.chans) {
+            DevChan dc;
+            std::memset(&dc, 0, sizeof(dc));
+            dc.t_off = h.t_off;
+            dc.group = gi;
+            dc.nhh = h.nhh; dc.npp = h.npp; dc.sz = h.Sz;
+            dc.hh_off = hh0 + h.hh_off;
+            dc.pp_off = pp0 + h.pp_off;
+            dc.chh_off = -1; dc.row_off = -1; dc.col_off = -1;
+            dc.kx = h.Kx; dc.ky = h.Ky; dc.kz = h.Kz;
+            dc.rowa_off = h.pp_off;
+            dc.cola_off = h.hh_off;
+            const int id = (int)c->dchans.size();
+            if (h.Sz == 0) {
+                dc.chh_off = chh; chh += h.nhh * h.nhh;
+                dc.row_off = rows;
+                dc.col_off = cols;
+                for (int r = 0; r < h.npp; r++) {
+                    lists[H.pp[2 * (h.pp_off + r)]].push_back(-(rows + r) - 1);
+                    lists[H.pp[2 * (h.pp_off + r) + 1]].push_back(-(rows + r) - 1);
+                }
+                for (int q = 0; q < h.nhh; q++) {
+                    lists[H.hh[2 * (h.hh_off + q)]].push_back(cols + q);
+                    lists[H.hh[2 * (h.hh_off + q) + 1]].push_back(cols + q);
+                }
+                rows += h.npp; cols += h.nhh;
+                c->it_sz0.push_back(id);
+                for (int g = 0; g < D.G; g++) dir.push_back({slot0 + g, Item{id, g}});
+                for (int r0 = 0; r0 < h.npp; r0 += kLadderRows) {
+                    const int li = (int)c->it_ladder.size();
+                    c->it_ladder.push_back({id, r0});
+                    for (int g = 0; g < D.G; g++) lg.push_back({slot0 + g, Item{li, g}});
+                }
+            }
+            const int nel = h.nhh * h.npp;
+            for (int e0 = 0; e0 < nel; e0 += kElemChunk) {
+                c->it_elem.push_back({id, e0});
+                if (h.Sz != 0) {
+                    const int ei = (int)c->it_nsz0.size();
+                    c->it_nsz0.push_back({id, e0});
+                    for (int g = 0; g < D.G; g++) ng.push_back({slot0 + g, Item{ei, g}});
+                }
+            }
+            c->dchans.push_back(dc);
+        }
+        D.ladder_hi = (int)c->it_ladder.size();
+        D.elem_hi = (int)c->it_elem.size();
+        D.n_rows = rows; D.n_cols = cols; D.n_chh = chh;
+        D.rows_base = c->n_rows; D.cols_base = c->n_cols; D.chh_base = c->n_chh;
+        c->n_rows += D.G * rows; c->n_cols += D.G * cols; c->n_chh += D.G * chh;
+        D.epart_base = c->n_epart;
+        c->n_epart += D.G * (D.ladder_hi - D.ladder_lo);
+        D.eelem_base = c->n_eparte;
+        c->n_eparte += D.G * (D.elem_hi - D.elem_lo);
+        // one-body CSR
+        D.csr_off = (int)c->csr_ptr.size();
+        c->csr_ptr.push_back((int32_t)c->csr_idx.size());
+        for (auto& l : lists) {
+            c->csr_idx.insert(c->csr_idx.end(), l.begin(), l.end());
+            c->csr_ptr.push_back((int32_t)c->csr_idx.size());
+        }
+        for (int s0 = 0; s0 < H.ns; s0 += 4) c->it_dchi.push_back({gi, s0});
+        // per-row / per-column Fock sums of every problem, ring indices
+        D.pp0 = pp0; D.hh0 = hh0;
+        D.n_rows_all = (int)H.pp.size() / 2;
+        D.n_cols_all = (int)H.hh.size() / 2;
+        D.rowa_base = (int)c->rowE.size();
+        D.cola_base = (int)c->colE.size();
+        for (int g = 0; g < D.G; g++) {
+            const HostProblem& Hg = c->probs[members[g]];
+            for (size_t k = 0; k < H.pp.size() / 2; k++) c->rowE.push_back(Hg.eps[H.pp[2 * k]] + Hg.eps[H.pp[2 * k + 1]]);
+            for (size_t k = 0; k < H.hh.size() / 2; k++) c->colE.push_back(Hg.eps[H.hh[2 * k]] + Hg.eps[H.hh[2 * k + 1]]);
+        }
+        D.zidx_off = (int64_t)c->zidx.size();
+        c->zidx.insert(c->zidx.end(), H.zidx.begin(), H.zidx.end());
+        // cross channels and their pairs {Q, -Q}; the lower index is the primary
+        const int ph0 = (int)c->dph.size(), mem0 = (int)c->phmem.size();
+        const int64_t map0 = (int64_t)c->phmap.size();
+        const int64_t nzp = H.n_zp;
+        for (size_t qi = 0; qi < H.ph.size(); qi++) {
+            const PhChan& h = H.ph[qi];
+            DevPh dp;
+            std::memset(&dp, 0, sizeof(dp));
+            dp.map_off = map0 + h.z_off;
+            dp.group = gi;
+            dp.n = h.n;
+            dp.partner = ph0 + h.partner;
+            dp.mem_off = mem0 + h.mem_off;
+            dp.zp_off = h.zp_off;
+            const int pid = (int)c->dph.size();
+            if (h.zp_off >= 0) {
+                for (int g = 0; g < D.G; g++) {
+                    if (h.n <= 16) rs.push_back({slot0 + g, Item{pid, g}});
+                    else rb[((h.n + 15) >> 4) - 2].push_back({slot0 + g, Item{pid, g}});
+                }
+            }
+            c->dph.push_back(dp);
             c->max_ph = std::max(c->max_ph, h.n);
         }
-        for (size_t k = 0; k < H.phmem.size() / 2; k++)
-            c->phmem.push_back(pack_pair(H.phmem[2 * k], H.phmem[2 * k + 1]));
-        for (size_t k = 0; k < H.phq.size(); k++) {
-            c->phq.push_back(phc_off + H.phq[k]);
-            c->phpos.push_back(H.phpos[k]);
-        }
-        c->dprobs.push_back(P);
-        st_off += H.ns;
-        lut_off += (int)H.W.size();
-        ph_off += (int)H.phq.size();
-        hh_off += (int)H.hh.size() / 2;
-        pp_off += (int)H.pp.size() / 2;
-        phm_off += (int)H.phmem.size() / 2;
-        phc_off += (int)H.ph.size();
-        t_off += H.n_amp;
-        z_off += H.nz_ph;
+        for (size_t k = 0; k < H.phmem.size() / 2; k++) c->phmem.push_back(pack_pair(H.phmem[2 * k], H.phmem[2 * k + 1]));
+        c->phmap.insert(c->phmap.end(), H.phmap.begin(), H.phmap.end());
+        D.phq_off = 0;
+        D.ph_base = (int)map0;
+        D.n_zp = nzp;
+        D.zp_base = zp_base;
+        zp_base += (int64_t)D.G * nzp;
+        c->dgroups.push_back(D);
+        t_base += (int64_t)D.G * H.n_amp;
+        slot0 += D.G;
+        gi++;
     }
-    c->NT = t_off;
-    c->NZ = z_off;
-    c->n_rows = row_off;
-    c->n_cols = col_off;
-    c->n_chh = chh_off;
-    c->ns_tot = st_off;
-    c->dchi_ptr.push_back(0);
-    for (auto& l : lists) {
-        c->dchi_idx.insert(c->dchi_idx.end(), l.begin(), l.end());
-        c->dchi_ptr.push_back((int32_t)c->dchi_idx.size());
+    c->NT = t_base;
+    c->NZP = zp_base;
+    if (c->csr_idx.empty()) c->csr_idx.push_back(0);
+    c->it_lg = xcd_order(lg);
+    c->it_ng = xcd_order(ng);
+    c->it_direct = xcd_order(dir);
+    c->it_ring_s = xcd_order(rs, 4);
+    c->it_ring_b.clear();
+    for (int k = 0; k < 4; k++) {
+        std::vector<Item> o = xcd_order(rb[k]);
+        c->ring_lo[k] = (int)c->it_ring_b.size();
+        c->ring_n[k] = (int)o.size();
+        c->it_ring_b.insert(c->it_ring_b.end(), o.begin(), o.end());
     }
-    if (c->dchi_idx.empty()) c->dchi_idx.push_back(0);
+    // per-slot copies of (group, index in group) for the per-problem kernels
+    std::vector<int32_t> sg(P), sgi(P);
+    for (size_t p = 0; p < P; p++) {
+        sg[c->slot_of[p]] = c->pgrp[p];
+        sgi[c->slot_of[p]] = c->pgi[p];
+    }
+    c->pgrp = sg;
+    c->pgi = sgi;
     layout(c);
     return CCD_OK;
 }
@@ -820,6 +1181,10 @@ static ccd_status harvest(ccd_ctx* c) {
         }                                                                               \
     } while (0)
 
+static size_t ring_lds(int n16) {
+    return 3 * (size_t)n16 * (n16 + 1) * sizeof(double) + kMaxLut * sizeof(double) + 4 * kMaxPH * sizeof(int32_t);
+}
+
 static ccd_status refresh_energy(ccd_ctx* c) {
     DevPtrs d = make_ptrs(c);
     LAUNCH(F_INIT, k_dot, (int)c->it_elem.size(), 256, 0, d, c->cur);
@@ -830,21 +1195,28 @@ static ccd_status refresh_energy(ccd_ctx* c) {
 static ccd_status sweep(ccd_ctx* c, double alpha, double tol, uint32_t mask) {
     DevPtrs d = make_ptrs(c);
     const int cur = c->cur;
-    const int nsz0 = (int)c->it_sz0.size();
-    if (mask & (CCD_T_QHOLE | CCD_T_QPART)) {
-        LAUNCH(F_ROWCOL, k_rowcol, nsz0, 256, 0, d, cur);
+    if (mask & (CCD_T_HH | CCD_T_QHH | CCD_T_QHOLE | CCD_T_QPART)) {
+        LAUNCH(F_DIRECT, k_direct, (int)c->it_direct.size(), 256, 0, d, cur, mask);
     }
-    LAUNCH(F_DCHI, k_dchi, (c->ns_tot + 255) / 256, 256, 0, d, c->ns_tot, mask);
-    if (mask & (CCD_T_HH | CCD_T_QHH)) {
-        LAUNCH(F_CHH, k_chh, nsz0, 256, 0, d, cur, mask);
+    LAUNCH(F_DCHI, k_dchi, (int)c->it_dchi.size(), 256, 0, d, mask);
+    {
+        int maxe = 0;
+        for (const DevGroup& D : c->dgroups) maxe = std::max(maxe, D.n_rows_all + D.n_cols_all);
+        HIP_TRY(ev_begin(c, F_DCHI));
+        hipLaunchKernelGGL(k_onebody, dim3((maxe + 255) / 256, (int)c->probs.size()), dim3(256), 0, c->stream, d);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(ev_end(c));
     }
     if (mask & (CCD_T_RING | CCD_T_QRING)) {
-        LAUNCH(F_SCATTER, k_scatter, (int)c->it_elem.size(), 256, 0, d, cur);
-        size_t lds = (size_t)2 * c->max_ph * c->max_ph * sizeof(double);
-        LAUNCH(F_RING, k_ring, (int)c->dph.size(), 256, lds, d, mask);
+        const int ns = (int)c->it_ring_s.size();
+        LAUNCH(F_RING_S, k_ringp_small, (ns + 3) / 4, 256, 0, d, cur, mask, ns);
+        LAUNCH(F_RING_B, (k_ringp<32, 4>), c->ring_n[0], 256, ring_lds(32), d, cur, mask, c->ring_lo[0]);
+        LAUNCH(F_RING_B, (k_ringp<48, 9>), c->ring_n[1], 576, ring_lds(48), d, cur, mask, c->ring_lo[1]);
+        LAUNCH(F_RING_B, (k_ringp<64, 16>), c->ring_n[2], 1024, ring_lds(64), d, cur, mask, c->ring_lo[2]);
+        LAUNCH(F_RING_B, (k_ringp<80, 16>), c->ring_n[3], 1024, ring_lds(80), d, cur, mask, c->ring_lo[3]);
     }
-    LAUNCH(F_LADDER, k_ladder, (int)c->it_ladder.size(), 256, 0, d, cur, alpha, mask);
-    LAUNCH(F_UPDATE, k_update, (int)c->it_nsz0.size(), 256, 0, d, cur, alpha, mask);
+    LAUNCH(F_LADDER, k_ladder, (int)c->it_lg.size(), 256, 0, d, cur, alpha, mask);
+    LAUNCH(F_UPDATE, k_update, (int)c->it_ng.size(), 256, 0, d, cur, alpha, mask);
     LAUNCH(F_ENERGY, k_energy, (int)c->probs.size(), 256, 0, d, tol);
     c->cur ^= 1;
     return CCD_OK;
@@ -856,7 +1228,7 @@ static ccd_status sweep(ccd_ctx* c, double alpha, double tol, uint32_t mask) {
 extern "C" {
 
 const char* ccd_last_error(void) { return g_err.c_str(); }
-const char* ccd_version(void) { return "ccd-mi355x 0.1 (gfx950)"; }
+const char* ccd_version(void) { return "ccd-mi355x 0.2 (gfx950, FP64 MFMA)"; }
 
 ccd_status ccd_build_channels(const ccd_problem* probs, int32_t n, void* stream, ccd_ctx** out) {
     if (!probs || !out || n < 1 || n > 4096) {
@@ -906,21 +1278,24 @@ ccd_status ccd_bind_workspace(ccd_ctx* c, void* ptr, size_t bytes) {
     if (bytes < c->ws_bytes) { set_error("workspace too small"); return CCD_EINVAL; }
     if (((uintptr_t)ptr) & 255) { set_error("workspace must be 256-byte aligned"); return CCD_EINVAL; }
     c->ws = (char*)ptr;
-    size_t lds = (size_t)2 * c->max_ph * c->max_ph * sizeof(double);
-    HIP_TRY(hipFuncSetAttribute((const void*)k_ring, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    HIP_TRY(hipFuncSetAttribute((const void*)k_ringp<48, 9>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)ring_lds(48)));
+    HIP_TRY(hipFuncSetAttribute((const void*)k_ringp<64, 16>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)ring_lds(64)));
+    HIP_TRY(hipFuncSetAttribute((const void*)k_ringp<80, 16>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)ring_lds(80)));
     std::vector<char> img = static_image(c);
     HIP_TRY(hipMemcpyAsync(c->ws + c->r_static.off, img.data(), img.size(), hipMemcpyHostToDevice, c->stream));
-    // dynamic regions start at zero (particle-hole positions with i = k or a = c stay zero)
     HIP_TRY(hipMemsetAsync(c->ws + c->r_t0.off, 0, c->ws_bytes - c->r_t0.off, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
     c->bound = true;
     ccd_status s = ccd_reset_amplitudes(c);
     if (s != CCD_OK) return s;
-    std::vector<double> e(c->probs.size());
-    HIP_TRY(hipMemcpyAsync(e.data(), c->ws + c->r_ecorr.off, e.size() * 8, hipMemcpyDeviceToHost, c->stream));
+    const int P = (int)c->probs.size();
+    std::vector<double> e(P);
+    HIP_TRY(hipMemcpyAsync(e.data(), c->ws + c->r_ecorr.off, P * 8, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
-    c->emp2 = e;
-    HIP_TRY(hipMemcpyAsync(c->ws + c->r_emp2.off, e.data(), e.size() * 8, hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (int p = 0; p < P; p++) c->emp2[p] = e[c->slot_of[p]];
     return CCD_OK;
 }
 
@@ -953,12 +1328,12 @@ ccd_status ccd_iterate(ccd_ctx* c, const ccd_solver_opts* o, int32_t* sweeps_don
             HIP_TRY(hipMemcpyAsync(e.data(), c->ws + c->r_ecorr.off, P * 8, hipMemcpyDeviceToHost, c->stream));
             HIP_TRY(hipMemcpyAsync(act.data(), c->ws + c->r_active.off, P * 4, hipMemcpyDeviceToHost, c->stream));
             HIP_TRY(hipStreamSynchronize(c->stream));
-            all_done = true;
+            all_done = o->tol > 0.0;
             for (int p = 0; p < P; p++) {
-                if (e_hist && was[p]) e_hist[(size_t)p * o->max_iter + s] = e[p];
-                if (act[p]) all_done = false;
+                const int sl = c->slot_of[p];
+                if (e_hist && was[sl]) e_hist[(size_t)p * o->max_iter + s] = e[sl];
+                if (act[sl]) all_done = false;
             }
-            if (o->tol <= 0.0) all_done = false;
         }
     }
     std::vector<int32_t> sw(P);
@@ -967,15 +1342,15 @@ ccd_status ccd_iterate(ccd_ctx* c, const ccd_solver_opts* o, int32_t* sweeps_don
     HIP_TRY(hipMemcpyAsync(act.data(), c->ws + c->r_active.off, P * 4, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     if (sweeps_done)
-        for (int p = 0; p < P; p++) sweeps_done[p] = sw[p];
+        for (int p = 0; p < P; p++) sweeps_done[p] = sw[c->slot_of[p]];
     for (int p = 0; p < P; p++)
-        if (!std::isfinite(e[p])) {
+        if (!std::isfinite(e[c->slot_of[p]])) {
             set_error("problem " + std::to_string(p) + ": correlation energy is not finite");
             return CCD_DIVERGED;
         }
     if (o->tol > 0.0)
         for (int p = 0; p < P; p++)
-            if (act[p]) return CCD_NOT_CONVERGED;
+            if (act[c->slot_of[p]]) return CCD_NOT_CONVERGED;
     return CCD_OK;
 }
 
@@ -986,7 +1361,7 @@ ccd_status ccd_energy(const ccd_ctx* cc, int32_t p, double* eref, double* emp2, 
     if (emp2 || ecorr) {
         if (!c->bound) { set_error("ccd_energy: no workspace bound"); return CCD_ESTATE; }
         double e = 0;
-        HIP_TRY(hipMemcpyAsync(&e, c->ws + c->r_ecorr.off + 8 * p, 8, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipMemcpyAsync(&e, c->ws + c->r_ecorr.off + 8 * c->slot_of[p], 8, hipMemcpyDeviceToHost, c->stream));
         HIP_TRY(hipStreamSynchronize(c->stream));
         if (emp2) *emp2 = c->emp2[p];
         if (ecorr) *ecorr = e;
@@ -1009,18 +1384,12 @@ ccd_status ccd_problem_info(const ccd_ctx* c, int32_t p, ccd_info* info) {
     return CCD_OK;
 }
 
-static int64_t prob_t_off(const ccd_ctx* c, int p) {
-    int64_t o = 0;
-    for (int q = 0; q < p; q++) o += c->probs[q].n_amp;
-    return o;
-}
-
 ccd_status ccd_get_amplitudes(const ccd_ctx* c, int32_t p, double* dst, size_t n) {
     if (!c || !dst || p < 0 || p >= (int)c->probs.size()) { set_error("ccd_get_amplitudes: bad argument"); return CCD_EINVAL; }
     if (!c->bound) { set_error("no workspace bound"); return CCD_ESTATE; }
     if (n != (size_t)c->probs[p].n_amp) { set_error("ccd_get_amplitudes: n != n_amplitudes"); return CCD_EINVAL; }
     const Region& r = c->cur ? c->r_t1 : c->r_t0;
-    HIP_TRY(hipMemcpyAsync(dst, c->ws + r.off + 8 * prob_t_off(c, p), n * 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(dst, c->ws + r.off + 8 * c->prob_t0[p], n * 8, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     return CCD_OK;
 }
@@ -1032,7 +1401,7 @@ ccd_status ccd_set_amplitudes(ccd_ctx* c, int32_t p, const double* src, size_t n
     for (size_t k = 0; k < n; k++)
         if (!std::isfinite(src[k])) { set_error("ccd_set_amplitudes: non-finite amplitude"); return CCD_EINVAL; }
     const Region& r = c->cur ? c->r_t1 : c->r_t0;
-    HIP_TRY(hipMemcpyAsync(c->ws + r.off + 8 * prob_t_off(c, p), src, n * 8, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->ws + r.off + 8 * c->prob_t0[p], src, n * 8, hipMemcpyHostToDevice, c->stream));
     ccd_status s = refresh_energy(c);
     if (s != CCD_OK) return s;
     HIP_TRY(hipStreamSynchronize(c->stream));

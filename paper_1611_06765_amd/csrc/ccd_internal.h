@@ -13,9 +13,11 @@ namespace ccd {
 
 // Limits of the kernels (checked when the plan is built).
 constexpr int kMaxHH = 64;        // hole pairs of one direct channel (ladder tile width)
-constexpr int kMaxPH = 90;        // pairs of one particle-hole channel (2 N^2 doubles in LDS)
+constexpr int kMaxPH = 80;        // pairs of one particle-hole channel (2 N^2 doubles in LDS)
 constexpr int kLadderRows = 64;   // particle-pair rows per ladder work item
 constexpr int kElemChunk = 1024;  // amplitudes per elementwise work item
+constexpr int kMaxNmax2 = 64;     // cutoff limit: W(m) tables of 4 nmax2 + 1 entries live in LDS
+constexpr int kMaxLut = 4 * kMaxNmax2 + 1;
 
 // A state is packed into 32 bits: bytes 0..2 = n_x, n_y, n_z (int8), byte 3 = 2 s_z (int8).
 inline int32_t pack_state(int x, int y, int z, int s) {
@@ -25,31 +27,54 @@ inline int32_t pack_state(int x, int y, int z, int s) {
 // A pair of state indices (local to the problem) is packed as p | q << 16.
 inline int32_t pack_pair(int p, int q) { return (int32_t)((uint32_t)p | ((uint32_t)q << 16)); }
 
-// ---- descriptors shared with the kernels (plain data, 8-byte aligned) ------
-struct DevProb {
-    int32_t ns, nh, np;
-    int32_t st_off;       // offset into states / eps / dchi
-    int32_t lut_off;      // offset into the W/2 table
-    int32_t ph_off;       // offset into phq / phpos ([(p-nh)*nh + h])
-    int32_t ladder_lo, ladder_hi;  // ladder work items of this problem (energy partial slots)
-    int32_t elem_lo, elem_hi;      // elementwise work items of this problem
+// ---- descriptors shared with the kernels (plain data) -----------------------
+// Problems with the same (N, nmax2) have identical channel structure; they form
+// a group whose integer tables are stored once.  Per-problem data (W table,
+// Fock energies, amplitudes, intermediates) is stored problem after problem, so
+// problem g of a group is found at base + g * stride.
+struct DevGroup {
+    int64_t n_amp;        // canonical amplitudes per problem
+    int64_t t_base;       // amplitude index of the group's first problem
+    int64_t n_zp;         // ring-result entries per problem (pair blocks)
+    int64_t zp_base;      // ring result of problem g at zp_base + g * n_zp
+    int64_t zidx_off;     // per-amplitude ring indices (shared), 2 per amplitude
+    int32_t phq_off;      // (p, h) -> cross channel / position tables (shared)
+    int32_t n_rows_all, n_cols_all; // particle-pair rows / hole-pair columns of all channels
+    int32_t rowa_base, cola_base;   // per-row / per-column arrays: + g * n_rows_all / n_cols_all
+    int32_t pp0, hh0;               // first particle / hole pair of the structure in the pair tables
+    int32_t G, p0;        // problems in the group, index of the first one
+    int32_t ns, nh, np, nlut;
+    int32_t st_off;       // packed states (shared)
+    int32_t eps_base;     // Fock energies / one-body intermediates: eps_base + g * ns
+    int32_t lut_base;     // W/2 tables: lut_base + g * nlut
+    int32_t ph_base;      // ph-map offset of the group (shared)
+    int32_t n_rows, n_cols, n_chh;  // S_z = 0 rows, columns, chi_klij entries per problem
+    int32_t rows_base, cols_base, chh_base;  // + g * n_rows / n_cols / n_chh
+    int32_t ladder_lo, ladder_hi;   // ladder items of the group
+    int32_t epart_base;   // energy partial of (item, g): epart_base + g * n_items + local item
+    int32_t elem_lo, elem_hi;       // elementwise items of the group
+    int32_t eelem_base;   // elementwise energy partial of (item, g)
+    int32_t csr_off;      // one-body CSR row pointers of the group: csr_off + s
 };
 
 struct DevChan {
-    int64_t t_off;        // element offset of the [npp][nhh] block
-    int32_t prob;         // problem index
+    int64_t t_off;        // element offset of the [npp][nhh] block inside a problem
+    int32_t group;
     int32_t nhh, npp;
     int32_t sz;           // 2 S_z: -2, 0, +2
-    int32_t hh_off, pp_off;   // offsets into hh_pairs / pp_pairs
-    int32_t chh_off;      // offset of the chi_klij block (S_z = 0), else -1
-    int32_t row_off;      // global row id of row 0 (S_z = 0), for row sums
-    int32_t col_off;      // global column id of column 0 (S_z = 0), for column sums
-    int32_t pad;
+    int32_t hh_off, pp_off;   // global offsets into hh / pp pair tables (shared)
+    int32_t chh_off;      // local offset of the chi_klij block (S_z = 0), else -1
+    int32_t row_off;      // local row id of row 0 (S_z = 0)
+    int32_t col_off;      // local column id of column 0 (S_z = 0)
+    int32_t kx, ky, kz;   // total momentum
+    int32_t rowa_off, cola_off;     // first row / column of the block among all rows / columns
 };
 
 struct DevPh {
-    int64_t z_off;        // offset of the [n][n] block in the ph-layout buffers
-    int32_t prob, n, partner, mem_off;
+    int64_t map_off;      // global offset of the [n][n] position map (shared)
+    int64_t zp_off;       // offset of the pair block if this channel is the primary of
+                          // its pair {Q, -Q} (the lower index), else -1
+    int32_t group, n, partner, mem_off;  // partner / mem_off global
 };
 
 struct Item {             // work item: a channel and a start (row or element)
@@ -65,10 +90,11 @@ struct Chan {
 };
 
 struct PhChan {
-    int Qx, Qy, Qz, sig;  // sig = 2 (s_p - s_h)/... in units of 1/2: -2, 0, +2
+    int Qx, Qy, Qz, sig;  // sig = 2 (s_p - s_h): -2, 0, +2
     int n, partner;       // local partner index
     int mem_off;          // local offset in phmem (pairs)
-    int64_t z_off;        // local
+    int64_t z_off;        // local offset of the position map
+    int64_t zp_off;       // pair-block offset if primary of {Q, -Q} (lower index), else -1
 };
 
 struct HostProblem {
@@ -87,6 +113,15 @@ struct HostProblem {
     std::vector<int32_t> phmem;          // (p, h), 2 ints each
     std::vector<int32_t> phq, phpos;     // [(p-nh)*nh + h] -> local ph channel, position
     int64_t nz_ph = 0;                   // sum n^2 over ph channels
+    // position map of the particle-hole blocks: entry (Q, u, y) for the pairs
+    // (p,h) = member u of Q and (p',h') = member y of the partner of Q names the
+    // canonical amplitude of {h,h'},{p,p'}: (e << 3) | (slot << 1) | negative,
+    // slot = 2 [p > p'] + [h > h'], or -1 when h = h' or p = p'.
+    std::vector<int32_t> phmap;
+    int64_t n_zp = 0;                    // entries of the pair blocks
+    // per canonical amplitude: the two pair-block entries that hold its ring
+    // term, positions (a,i)(b,j) and (a,j)(b,i)
+    std::vector<int32_t> zidx;           // 2 per amplitude
     int max_hh = 0, max_pp = 0, max_ph = 0;
     double flops_pp = 0, flops_hh = 0, flops_ring = 0, flops_ordered = 0;
 };

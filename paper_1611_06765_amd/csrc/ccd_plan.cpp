@@ -47,7 +47,7 @@ static double minnesota_W(const ccd_problem& p, double L, int m) {
 ccd_status build_problem(const ccd_problem& par, HostProblem& P, std::string& err) {
     P = HostProblem();
     P.par = par;
-    if (par.nmax2 < 1 || par.nmax2 > 300) { err = "nmax2 must be in [1, 300]"; return CCD_EINVAL; }
+    if (par.nmax2 < 1 || par.nmax2 > kMaxNmax2) { err = "nmax2 must be in [1, 64]"; return CCD_EINVAL; }
     if (par.n_particles < 2) { err = "n_particles must be >= 2"; return CCD_EINVAL; }
     if (!(par.density > 0.0) || !std::isfinite(par.density)) { err = "density must be > 0"; return CCD_EINVAL; }
     if (!(par.hbar2_over_m > 0.0)) { err = "hbar2_over_m must be > 0"; return CCD_EINVAL; }
@@ -201,9 +201,76 @@ ccd_status build_problem(const ccd_problem& par, HostProblem& P, std::string& er
         }
     }
     if (P.max_ph > kMaxPH) {
-        err = "a particle-hole channel has more than 90 pairs (N too large for this library)";
+        err = "a particle-hole channel has more than 80 pairs (N too large for this library)";
         return CCD_EINVAL;
     }
+    if (P.n_amp >= (int64_t)1 << 28) { err = "too many amplitudes"; return CCD_EINVAL; }
+
+    // ---- position map of the particle-hole blocks -------------------------
+    // canonical index of the element (i<j, a<b): channel block offset +
+    // row (position of (a,b)) * n_hh + column (position of (i,j))
+    std::vector<int32_t> hpos((size_t)P.nh * P.nh, -1), hchan((size_t)P.nh * P.nh, -1);
+    std::vector<int32_t> ppos((size_t)P.np * P.np, -1);
+    for (size_t ci = 0; ci < P.chans.size(); ci++) {
+        const Chan& c = P.chans[ci];
+        for (int q = 0; q < c.nhh; q++) {
+            int i = P.hh[2 * (c.hh_off + q)], j = P.hh[2 * (c.hh_off + q) + 1];
+            hpos[(size_t)i * P.nh + j] = q;
+            hchan[(size_t)i * P.nh + j] = (int)ci;
+        }
+        for (int r = 0; r < c.npp; r++) {
+            int a = P.pp[2 * (c.pp_off + r)], b = P.pp[2 * (c.pp_off + r) + 1];
+            ppos[(size_t)(a - P.nh) * P.np + (b - P.nh)] = r;
+        }
+    }
+    P.phmap.assign((size_t)P.nz_ph, -1);
+    for (const PhChan& c : P.ph) {
+        const PhChan& pc = P.ph[c.partner];
+        for (int u = 0; u < c.n; u++) {
+            int p = P.phmem[2 * (c.mem_off + u)], h = P.phmem[2 * (c.mem_off + u) + 1];
+            for (int y = 0; y < c.n; y++) {
+                int p2 = P.phmem[2 * (pc.mem_off + y)], h2 = P.phmem[2 * (pc.mem_off + y) + 1];
+                if (p == p2 || h == h2) continue;
+                int i = std::min(h, h2), j = std::max(h, h2);
+                int a = std::min(p, p2), b = std::max(p, p2);
+                int ci = hchan[(size_t)i * P.nh + j];
+                int r = ppos[(size_t)(a - P.nh) * P.np + (b - P.nh)];
+                if (ci < 0 || r < 0) { err = "internal: particle-hole position without amplitude"; return CCD_EINVAL; }
+                const Chan& dc = P.chans[ci];
+                int64_t e = dc.t_off + (int64_t)r * dc.nhh + hpos[(size_t)i * P.nh + j];
+                int slot = 2 * (p > p2) + (h > h2);
+                int neg = (p > p2) ^ (h > h2);
+                P.phmap[(size_t)c.z_off + (size_t)u * c.n + y] = (int32_t)((e << 3) | (slot << 1) | neg);
+            }
+        }
+    }
+    // ---- pair blocks {Q, -Q} and the ring indices of each amplitude ----------
+    for (size_t q = 0; q < P.ph.size(); q++) {
+        PhChan& c = P.ph[q];
+        c.zp_off = -1;
+        if (c.partner >= (int)q) {
+            c.zp_off = P.n_zp;
+            P.n_zp += (int64_t)c.n * c.n;
+        }
+    }
+    if (P.n_zp >= ((int64_t)1 << 31)) { err = "too many ring entries"; return CCD_EINVAL; }
+    auto zpos = [&](int p, int h, int p2, int h2) -> int64_t {
+        size_t x1 = (size_t)(p - P.nh) * P.nh + h, x2 = (size_t)(p2 - P.nh) * P.nh + h2;
+        const PhChan& c = P.ph[P.phq[x1]];
+        if (c.zp_off >= 0) return c.zp_off + (int64_t)P.phpos[x1] * c.n + P.phpos[x2];
+        return P.ph[c.partner].zp_off + (int64_t)P.phpos[x2] * c.n + P.phpos[x1];
+    };
+    P.zidx.resize(2 * (size_t)P.n_amp);
+    for (const Chan& c : P.chans)
+        for (int r = 0; r < c.npp; r++) {
+            int a = P.pp[2 * (c.pp_off + r)], b = P.pp[2 * (c.pp_off + r) + 1];
+            for (int q = 0; q < c.nhh; q++) {
+                int i = P.hh[2 * (c.hh_off + q)], j = P.hh[2 * (c.hh_off + q) + 1];
+                int64_t e = c.t_off + (int64_t)r * c.nhh + q;
+                P.zidx[2 * e] = (int32_t)zpos(a, i, b, j);
+                P.zidx[2 * e + 1] = (int32_t)zpos(a, j, b, i);
+            }
+        }
     return CCD_OK;
 }
 
