@@ -27,6 +27,23 @@ N, NMAX2, MIXING = 66, 20, 0.5
 # MI355X published peaks
 PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_counters.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1611_06765_amd", "csrc", "ccd_device.hip")
+
+
+def measured_traffic(family):
+    """HBM bytes per launch of a kernel family from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE passes (scaled by a plain copy of known size), or
+    None if the kernel source changed since the counters were taken."""
+    import hashlib
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+        sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256") != sha or rec.get("kernel_family") != family:
+        return None
+    return (rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"]) * 1024.0
 
 
 def cpu_baseline(budget_s=20.0):
@@ -124,7 +141,7 @@ def main():
     achieved = fam_flops[dom] / (fam_ms[dom] * 1e-3) / 1e12
     roof = {"kernel": dom if dom != "ring" else "ring (ring_small + ring)", "bound": "mfma",
             "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+            "frac": achieved / PEAK_FP64_TFLOPS, "traffic": measured_traffic(dom),
             "ms_per_step": fam_ms[dom], "flops_per_step": fam_flops[dom]}
 
     energies = [ctx.energy(p)[2] for p in range(nsolve)]
