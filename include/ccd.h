@@ -85,9 +85,14 @@ typedef struct {
                               tol <= 0 runs exactly max_iter sweeps */
     int32_t max_iter;      /* sweeps in this call (>= 1) */
     int32_t precision;     /* CCD_PREC_* for the sweeps of this call */
-    int32_t refine_sweeps; /* after a mixed-precision run converges, this many
-                              more FP64 sweeps, then FP64 iteration to tol */
+    int32_t refine_sweeps; /* mixed precision: after the mixed phase stops, at
+                              least this many FP64 sweeps, then FP64 iteration
+                              until |dE| < tol, within max_iter sweeps in total */
     uint32_t terms;        /* CCD_T_* mask; CCD_T_ALL for CCD */
+    double mixed_tol;      /* mixed precision: the mixed phase stops when
+                              |dE_n - dE_(n-1)| < mixed_tol (MeV); <= 0 means tol.
+                              Rounding in BF16 keeps |dE| from falling far below
+                              ~1e-4 |E|, so give BF16 a loose value. */
 } ccd_solver_opts;
 
 typedef struct ccd_ctx ccd_ctx; /* opaque */

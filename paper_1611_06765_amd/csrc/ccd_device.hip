@@ -30,6 +30,7 @@
 #include <cstring>
 #include <map>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "ccd_internal.h"
@@ -58,6 +59,26 @@ __device__ __forceinline__ d4 mfma64(double a, double b, d4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+
+// Mixed precision: FP32 operands on the 16x16x4 FP32 MFMA, or BF16 operands on
+// the 16x16x32 BF16 MFMA, both accumulating in FP32.  For both, lane l
+// receives D[4 (l/16) + r][l%16].  BF16: lane l supplies A[l%16][8 (l/16) + j]
+// and B[8 (l/16) + j][l%16], j = 0..7.
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+__device__ __forceinline__ f4 mfma32(float a, float b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mfmabf(bf8 a, bf8 b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+enum Prec { P_F64 = 0, P_F32 = 1, P_BF16 = 2 };
+template <int P> struct AccT { using T = f4; using E = float; };
+template <> struct AccT<P_F64> { using T = d4; using E = double; };
+// row of accumulator element r held by lane l (16x16 output tile)
+template <int P> __device__ __forceinline__ int orow(int lane, int r) {
+    return P == P_F64 ? (lane >> 4) + 4 * r : 4 * (lane >> 4) + r;
+}
 
 // --------------------------------------------------------------------------
 // device pointers, passed by value to every kernel
@@ -226,9 +247,14 @@ __global__ void __launch_bounds__(256) k_energy_elem(DevPtrs d) {
 // part on FP64 MFMA over LDS-staged row chunks) and the column sums, which are
 // the diagonal of that product.  Wave w owns output tiles w, w+4, ...
 constexpr int kDirRows = 32;
+template <int P>
 __global__ void __launch_bounds__(256) k_direct(DevPtrs d, int cur, uint32_t mask) {
-    __shared__ double vs[kDirRows][kMaxHH + 1];
-    __shared__ double ts[kDirRows][kMaxHH + 1];
+    using E = typename std::conditional<P == P_F64, double, float>::type;
+    using AT = typename std::conditional<P == P_F64, d4, f4>::type;
+    constexpr int PM = P == P_F64 ? P_F64 : P_F32;   // contraction precision used here
+    __shared__ E vs[kDirRows][kMaxHH + 1];
+    __shared__ E ts[kDirRows][kMaxHH + 1];
+    __shared__ double rsum[kDirRows];
     const Item it = d.it_direct[blockIdx.x];
     if (it.chan < 0) return;
     const DevChan c = d.chans[it.chan];
@@ -242,28 +268,31 @@ __global__ void __launch_bounds__(256) k_direct(DevPtrs d, int cur, uint32_t mas
     const double* vt = d.vt + E0;
     const bool quad = (mask & (CCD_T_QHH | CCD_T_QHOLE)) != 0;
     double* rows = d.rowsum + G.rows_base + g * G.n_rows + c.row_off;
-    d4 acc[4];
+    AT acc[4];
 #pragma unroll
-    for (int k = 0; k < 4; k++) acc[k] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int k = 0; k < 4; k++) acc[k] = AT{0, 0, 0, 0};
     for (int r0 = 0; r0 < npp; r0 += kDirRows) {
         const int rc = min(kDirRows, npp - r0);
         __syncthreads();
+        if (threadIdx.x < kDirRows) rsum[threadIdx.x] = 0.0;
         for (int e = threadIdx.x; e < kDirRows * nhh; e += 256) {
             int r = e / nhh, j = e - r * nhh;
             bool ok = r < rc;
-            vs[r][j] = ok ? vt[(int64_t)r0 * nhh + e] : 0.0;
-            ts[r][j] = ok ? t[(int64_t)r0 * nhh + e] : 0.0;
+            vs[r][j] = ok ? (E)vt[(int64_t)r0 * nhh + e] : (E)0;
+            ts[r][j] = ok ? (E)t[(int64_t)r0 * nhh + e] : (E)0;
         }
         // zero the padding columns of the last tile
         for (int e = threadIdx.x; e < kDirRows * (nt * 16 - nhh); e += 256) {
             int r = e / (nt * 16 - nhh), j = nhh + e % (nt * 16 - nhh);
-            vs[r][j] = 0.0;
-            ts[r][j] = 0.0;
+            vs[r][j] = (E)0;
+            ts[r][j] = (E)0;
         }
         __syncthreads();
+        // row sums of t v in FP64 straight from memory (one-body terms stay FP64)
         if ((mask & CCD_T_QPART) && threadIdx.x < rc) {
             double sum = 0.0;
-            for (int j = 0; j < nhh; j++) sum += ts[threadIdx.x][j] * vs[threadIdx.x][j];
+            for (int j = 0; j < nhh; j++)
+                sum += t[(int64_t)(r0 + threadIdx.x) * nhh + j] * vt[(int64_t)(r0 + threadIdx.x) * nhh + j];
             rows[r0 + threadIdx.x] = sum;
         }
         if (quad) {
@@ -273,9 +302,10 @@ __global__ void __launch_bounds__(256) k_direct(DevPtrs d, int cur, uint32_t mas
                 if (tile < nt * nt) {
                     const int ti = tile / nt, tj = tile - ti * nt;
                     for (int kk = 0; kk < kDirRows; kk += 4) {
-                        double av = vs[kk + (lane >> 4)][ti * 16 + (lane & 15)];
-                        double bv = ts[kk + (lane >> 4)][tj * 16 + (lane & 15)];
-                        acc[k] = mfma64(av, bv, acc[k]);
+                        E av = vs[kk + (lane >> 4)][ti * 16 + (lane & 15)];
+                        E bv = ts[kk + (lane >> 4)][tj * 16 + (lane & 15)];
+                        if constexpr (P == P_F64) acc[k] = mfma64(av, bv, acc[k]);
+                        else acc[k] = mfma32(av, bv, acc[k]);
                     }
                 }
             }
@@ -292,10 +322,10 @@ __global__ void __launch_bounds__(256) k_direct(DevPtrs d, int cur, uint32_t mas
             const int ti = tile / nt, tj = tile - ti * nt;
 #pragma unroll
             for (int q = 0; q < 4; q++) {
-                int kl = ti * 16 + (lane >> 4) + 4 * q, ij = tj * 16 + (lane & 15);
+                int kl = ti * 16 + orow<PM>(lane, q), ij = tj * 16 + (lane & 15);
                 if (kl < nhh && ij < nhh) {
-                    double qv = acc[k][q];
-                    if (kl == ij) cols[kl] = qv;
+                    double qv = (double)acc[k][q];
+                    if (kl == ij && P == P_F64) cols[kl] = qv;
                     double v = 0.0;
                     if (mask & CCD_T_HH) {
                         int32_t p1 = d.hh[c.hh_off + kl], p2 = d.hh[c.hh_off + ij];
@@ -304,6 +334,14 @@ __global__ void __launch_bounds__(256) k_direct(DevPtrs d, int cur, uint32_t mas
                     chh[kl * nhh + ij] = v + ((mask & CCD_T_QHH) ? qv : 0.0);
                 }
             }
+        }
+    }
+    // column sums (hole one-body terms) in FP64 for the mixed modes
+    if constexpr (P != P_F64) {
+        if ((mask & CCD_T_QHOLE) && threadIdx.x < nhh) {
+            double sum = 0.0;
+            for (int r = 0; r < npp; r++) sum += t[(int64_t)r * nhh + threadIdx.x] * vt[(int64_t)r * nhh + threadIdx.x];
+            cols[threadIdx.x] = sum;
         }
     }
 }
@@ -384,10 +422,11 @@ __device__ __forceinline__ void pair_stage(const DevPtrs& d, const Item it, int 
     for (int e = t0; e < G.nlut; e += stride) lutS[e] = d.lut[lut_off + e];
 }
 
-// A = gathered T~_Q (signed), B = Vbar, zero padded; gathers issued 8 at a time
-template <int n16, int lda, int stride>
+// A = gathered T~_Q (signed), B = Vbar, zero padded; gathers issued 8 at a time.
+// With TR set (BF16), the transposes At = A^T and Bt = B^T are written too.
+template <typename E, int n16, int lda, int stride, bool TR>
 __device__ __forceinline__ void pair_fill(const PairCtx& r, const int32_t* qs, const int32_t* ps,
-                                          const double* lutS, double* A, double* B, int t0, bool qring) {
+                                          const double* lutS, E* A, E* B, E* At, E* Bt, int t0, bool qring) {
     const int n = r.n;
     constexpr int tot = n16 * n16;
     for (int base = t0; base < tot; base += 8 * stride) {
@@ -409,8 +448,13 @@ __device__ __forceinline__ void pair_fill(const PairCtx& r, const int32_t* qs, c
                 double b = 0.0;
                 if (qring && u < n && x < n)  // <kl||cd>: (c,k) = P member u, (d,l) = Q member x
                     b = vas(lutS, ps[2 * u + 1], qs[2 * x + 1], ps[2 * u], qs[2 * x]);
-                A[u * lda + x] = (m[j] & 1) ? -tv[j] : tv[j];
-                B[u * lda + x] = b;
+                const E av = (E)((m[j] & 1) ? -tv[j] : tv[j]), bv = (E)b;
+                A[u * lda + x] = av;
+                B[u * lda + x] = bv;
+                if constexpr (TR) {
+                    At[x * lda + u] = av;
+                    Bt[x * lda + u] = bv;
+                }
             }
         }
     }
@@ -421,129 +465,109 @@ __device__ __forceinline__ double pair_vph(const int32_t* s2, const double* lutS
     return vas(lutS, s2[2 * x + 1], s2[2 * y], s2[2 * x], s2[2 * y + 1]);
 }
 
-__device__ __forceinline__ void pair_store(const PairCtx& r, d4 acc, int tu, int ty, int lane) {
+template <int P, typename AT>
+__device__ __forceinline__ void pair_store(const PairCtx& r, AT acc, int tu, int ty, int lane) {
 #pragma unroll
     for (int q = 0; q < 4; q++) {
-        int u = tu * 16 + (lane >> 4) + 4 * q, y = ty * 16 + (lane & 15);
+        int u = tu * 16 + orow<P>(lane, q), y = ty * 16 + (lane & 15);
         if (u < r.n && y < r.n) {
             int m = r.map[u * r.n + y];
             // a self pair holds both orders of one amplitude: keep the p < p' one
-            if (m >= 0 && !(r.self && ((m >> 2) & 1))) r.zp[u * r.n + y] = (m & 1) ? -acc[q] : acc[q];
+            const double v = (double)acc[q];
+            if (m >= 0 && !(r.self && ((m >> 2) & 1))) r.zp[u * r.n + y] = (m & 1) ? -v : v;
         }
     }
 }
 
-// pairs with n <= 16: one wave per item, four items per block
-__global__ void __launch_bounds__(256) k_ringp_small(DevPtrs d, int cur, uint32_t mask, int n_items) {
-    constexpr int L = 17, M = 16 * 17;
-    __shared__ double mat[4][3 * M];
-    __shared__ double lutS[4][kMaxLut];
-    __shared__ int32_t qs[4][32], ps[4][32];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int idx = (int)blockIdx.x * 4 + w;
-    const Item it = d.it_ring_s[min(idx, n_items - 1)];
+// products of one 16x16 output tile, k from 0 to kmax (FP64 / FP32: 16x16x4)
+template <int P, typename E, typename AT>
+__device__ __forceinline__ AT mm4(const E* X, const E* Y, int lda, int tx, int ty, int kmax, int lane, AT acc) {
+    for (int k0 = 0; k0 < kmax; k0 += 4) {
+        const E a = X[(tx * 16 + (lane & 15)) * lda + k0 + (lane >> 4)];
+        const E b = Y[(k0 + (lane >> 4)) * lda + ty * 16 + (lane & 15)];
+        if constexpr (P == P_F64) acc = mfma64(a, b, acc);
+        else acc = mfma32(a, b, acc);
+    }
+    return acc;
+}
+// BF16: X row-major, Yt = Y^T row-major, k from 0 to kmax (a multiple of 32)
+__device__ __forceinline__ f4 mmbf(const __bf16* X, const __bf16* Yt, int lda, int tx, int ty, int kmax,
+                                   int lane, f4 acc) {
+    for (int k0 = 0; k0 < kmax; k0 += 32) {
+        const bf8 a = *(const bf8*)&X[(tx * 16 + (lane & 15)) * lda + k0 + 8 * (lane >> 4)];
+        const bf8 b = *(const bf8*)&Yt[(ty * 16 + (lane & 15)) * lda + k0 + 8 * (lane >> 4)];
+        acc = mfmabf(a, b, acc);
+    }
+    return acc;
+}
+
+// byte offset of the matrices in a pair item's LDS (after W/2 and member states)
+__host__ __device__ constexpr size_t pair_mat_off() {
+    return ((size_t)kMaxLut * 8 + 4 * (size_t)kMaxPH * 4 + 15) & ~(size_t)15;
+}
+
+// One pair item with NW waves, wave w owning output tiles w, w + NW, ...
+// Matrices padded to n16 (K padded to kpad = n16 for 16x16x4, 32-multiple for
+// BF16) with row stride lda.
+template <int P, int N16, int NW>
+__device__ __forceinline__ void pair_body(const DevPtrs& d, const Item it, int cur, uint32_t mask, char* lds,
+                                          int tid) {
+    using E = typename std::conditional<P == P_F64, double, typename std::conditional<P == P_F32, float, __bf16>::type>::type;
+    using AT = typename AccT<P>::T;
+    constexpr int n16 = N16, nt = N16 / 16, ntt = nt * nt, TPW = (ntt + NW - 1) / NW;
+    constexpr int kpad = P == P_BF16 ? ((N16 + 31) & ~31) : N16;
+    constexpr int lda = P == P_BF16 ? kpad + 8 : N16 + 1;
+    constexpr int rows = P == P_BF16 ? kpad : N16;  // rows allocated per matrix
     PairCtx r;
+    r.n = 0; r.self = false; r.map = nullptr; r.t = nullptr; r.zp = nullptr;
     int32_t memQ = 0, memP = 0, lo = 0;
-    bool live = idx < n_items && it.chan >= 0;
-    if (live) live = pair_ctx(d, it, cur, r, memQ, memP, lo);
-    const bool qring = (mask & CCD_T_QRING) != 0, ring = (mask & CCD_T_RING) != 0;
-    double* A = mat[w];
-    double* B = mat[w] + M;
-    double* C = mat[w] + 2 * M;
-    if (live) pair_stage(d, it, memQ, memP, lo, r.n, qs[w], ps[w], lutS[w], lane, 64);
-    __syncthreads();
-    if (live) pair_fill<16, L, 64>(r, qs[w], ps[w], lutS[w], A, B, lane, qring);
-    __syncthreads();
-    d4 x1 = {0.0, 0.0, 0.0, 0.0}, x2 = {0.0, 0.0, 0.0, 0.0};
-    if (live) {
-        if (qring)
-            for (int m0 = 0; m0 < 16; m0 += 4) {
-                const int ra = (lane & 15) * L + m0 + (lane >> 4), rb = (m0 + (lane >> 4)) * L + (lane & 15);
-                x1 = mfma64(B[ra], A[rb], x1);
-                x2 = mfma64(A[ra], B[rb], x2);
-            }
-#pragma unroll
-        for (int q = 0; q < 4; q++) {
-            int x = (lane >> 4) + 4 * q, y = lane & 15;
-            double v1 = 0.5 * x1[q], v2 = 0.5 * x2[q];
-            if (ring && x < r.n && y < r.n) {
-                v1 += pair_vph(ps[w], lutS[w], x, y);
-                v2 += pair_vph(qs[w], lutS[w], x, y);
-            }
-            x1[q] = v1;
-            x2[q] = v2;
-        }
-    }
-    __syncthreads();
-    if (live) {
-#pragma unroll
-        for (int q = 0; q < 4; q++) {
-            C[((lane >> 4) + 4 * q) * L + (lane & 15)] = x1[q];
-            B[((lane >> 4) + 4 * q) * L + (lane & 15)] = x2[q];
-        }
-    }
-    __syncthreads();
-    if (live) {
-        d4 z = {0.0, 0.0, 0.0, 0.0};
-        for (int x0 = 0; x0 < 16; x0 += 4) {
-            const int ra = (lane & 15) * L + x0 + (lane >> 4), rb = (x0 + (lane >> 4)) * L + (lane & 15);
-            z = mfma64(A[ra], C[rb], z);
-            z = mfma64(B[ra], A[rb], z);
-        }
-        pair_store(r, z, 0, 0, lane);
-    }
-}
-
-// pairs with n > 16: one block per item with one wave per output tile (up to
-// 16 waves; wave w owns tiles w, w + NW, ...)
-template <int N16, int NW>
-__global__ void __launch_bounds__(64 * NW) k_ringp(DevPtrs d, int cur, uint32_t mask, int base) {
-    constexpr int n16 = N16, nt = N16 / 16, lda = N16 + 1, ntt = nt * nt, TPW = (ntt + NW - 1) / NW;
-    constexpr int NT = 64 * NW;
-    extern __shared__ double lds[];
-    const Item it = d.it_ring_b[base + blockIdx.x];
-    if (it.chan < 0) return;
-    PairCtx r;
-    int32_t memQ, memP, lo;
-    if (!pair_ctx(d, it, cur, r, memQ, memP, lo)) return;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    double* A = lds;
-    double* B = A + n16 * lda;
-    double* C = B + n16 * lda;
-    double* lutS = C + n16 * lda;
+    // every wave reaches every barrier below; only the work is guarded by live
+    const bool live = it.chan >= 0 && pair_ctx(d, it, cur, r, memQ, memP, lo);
+    const int lane = tid & 63, w = tid >> 6;
+    double* lutS = (double*)lds;
     int32_t* qs = (int32_t*)(lutS + kMaxLut);
     int32_t* ps = qs + 2 * kMaxPH;
+    E* A = (E*)(lds + pair_mat_off());
+    E* B = A + rows * lda;
+    E* At = B + rows * lda;  // C for FP64 / FP32; A^T for BF16
+    E* Bt = At + rows * lda; // BF16 only
     const bool qring = (mask & CCD_T_QRING) != 0, ring = (mask & CCD_T_RING) != 0;
-    pair_stage(d, it, memQ, memP, lo, r.n, qs, ps, lutS, threadIdx.x, NT);
+    if (live) {
+        pair_stage(d, it, memQ, memP, lo, r.n, qs, ps, lutS, tid, 64 * NW);
+        if constexpr (P == P_BF16) {
+            // zero the K padding (rows and columns n16 .. kpad) of all four matrices
+            for (int e = tid; e < 4 * rows * lda; e += 64 * NW) A[e] = (E)0.0f;
+        }
+    }
     __syncthreads();
-    pair_fill<n16, lda, NT>(r, qs, ps, lutS, A, B, threadIdx.x, qring);
+    if (live) pair_fill<E, n16, lda, 64 * NW, P == P_BF16>(r, qs, ps, lutS, A, B, At, Bt, tid, qring);
     __syncthreads();
-    d4 x1[TPW], x2[TPW];
+    AT x1[TPW], x2[TPW];
 #pragma unroll
-    for (int k = 0; k < TPW; k++) { x1[k] = d4{0.0, 0.0, 0.0, 0.0}; x2[k] = x1[k]; }
-    if (qring)
-        for (int m0 = 0; m0 < n16; m0 += 4) {
-#pragma unroll
-            for (int k = 0; k < TPW; k++) {
-                const int tile = w + NW * k;
-                if (tile < ntt) {
-                    const int tx = tile / nt, ty = tile - tx * nt;
-                    const int ra = (tx * 16 + (lane & 15)) * lda + m0 + (lane >> 4);
-                    const int rb = (m0 + (lane >> 4)) * lda + ty * 16 + (lane & 15);
-                    x1[k] = mfma64(B[ra], A[rb], x1[k]);
-                    x2[k] = mfma64(A[ra], B[rb], x2[k]);
-                }
+    for (int k = 0; k < TPW; k++) {
+        x1[k] = AT{0, 0, 0, 0};
+        x2[k] = x1[k];
+        const int tile = w + NW * k;
+        if (live && qring && tile < ntt) {
+            const int tx = tile / nt, ty = tile - tx * nt;
+            if constexpr (P == P_BF16) {
+                x1[k] = mmbf(B, At, lda, tx, ty, kpad, lane, x1[k]);  // B A
+                x2[k] = mmbf(A, Bt, lda, tx, ty, kpad, lane, x2[k]);  // A B
+            } else {
+                x1[k] = mm4<P>(B, A, lda, tx, ty, n16, lane, x1[k]);
+                x2[k] = mm4<P>(A, B, lda, tx, ty, n16, lane, x2[k]);
             }
         }
+    }
 #pragma unroll
     for (int k = 0; k < TPW; k++) {
         const int tile = w + NW * k;
-        if (tile < ntt) {
+        if (live && tile < ntt) {
             const int tx = tile / nt, ty = tile - tx * nt;
 #pragma unroll
             for (int q = 0; q < 4; q++) {
-                int x = tx * 16 + (lane >> 4) + 4 * q, y = ty * 16 + (lane & 15);
-                double v1 = 0.5 * x1[k][q], v2 = 0.5 * x2[k][q];
+                int x = tx * 16 + orow<P>(lane, q), y = ty * 16 + (lane & 15);
+                double v1 = 0.5 * (double)x1[k][q], v2 = 0.5 * (double)x2[k][q];
                 if (ring && x < r.n && y < r.n) {
                     v1 += pair_vph(ps, lutS, x, y);
                     v2 += pair_vph(qs, lutS, x, y);
@@ -553,40 +577,68 @@ __global__ void __launch_bounds__(64 * NW) k_ringp(DevPtrs d, int cur, uint32_t 
             }
         }
     }
-    __syncthreads();  // every wave has finished reading B
+    __syncthreads();  // every wave has finished reading B (and Bt)
+    // chi_P goes to C (as its transpose for BF16, in Bt's place), M_Q into B
+    E* C = P == P_BF16 ? Bt : At;
 #pragma unroll
     for (int k = 0; k < TPW; k++) {
         const int tile = w + NW * k;
-        if (tile < ntt) {
+        if (live && tile < ntt) {
             const int tx = tile / nt, ty = tile - tx * nt;
 #pragma unroll
             for (int q = 0; q < 4; q++) {
-                const int o = (tx * 16 + (lane >> 4) + 4 * q) * lda + ty * 16 + (lane & 15);
-                C[o] = x1[k][q];
-                B[o] = x2[k][q];
+                const int x = tx * 16 + orow<P>(lane, q), y = ty * 16 + (lane & 15);
+                if constexpr (P == P_BF16) C[y * lda + x] = (E)(float)x1[k][q];
+                else C[x * lda + y] = (E)x1[k][q];
+                B[x * lda + y] = (E)x2[k][q];
             }
         }
-        x1[k] = d4{0.0, 0.0, 0.0, 0.0};
     }
     __syncthreads();
-    for (int x0 = 0; x0 < n16; x0 += 4) {
-#pragma unroll
-        for (int k = 0; k < TPW; k++) {
-            const int tile = w + NW * k;
-            if (tile < ntt) {
-                const int tu = tile / nt, ty = tile - tu * nt;
-                const int ra = (tu * 16 + (lane & 15)) * lda + x0 + (lane >> 4);
-                const int rb = (x0 + (lane >> 4)) * lda + ty * 16 + (lane & 15);
-                x1[k] = mfma64(A[ra], C[rb], x1[k]);
-                x1[k] = mfma64(B[ra], A[rb], x1[k]);
-            }
-        }
-    }
 #pragma unroll
     for (int k = 0; k < TPW; k++) {
         const int tile = w + NW * k;
-        if (tile < ntt) pair_store(r, x1[k], tile / nt, tile % nt, lane);
+        if (live && tile < ntt) {
+            const int tu = tile / nt, ty = tile - tu * nt;
+            AT acc = {0, 0, 0, 0};
+            if constexpr (P == P_BF16) {
+                acc = mmbf(A, C, lda, tu, ty, kpad, lane, acc);   // A chi_P
+                acc = mmbf(B, At, lda, tu, ty, kpad, lane, acc);  // M_Q A
+            } else {
+                acc = mm4<P>(A, C, lda, tu, ty, n16, lane, acc);
+                acc = mm4<P>(B, A, lda, tu, ty, n16, lane, acc);
+            }
+            pair_store<P>(r, acc, tu, ty, lane);
+        }
     }
+}
+
+template <int P> __host__ __device__ constexpr size_t pair_lds(int n16) {
+    const size_t es = P == P_F64 ? 8 : (P == P_F32 ? 4 : 2);
+    const size_t kpad = P == P_BF16 ? ((n16 + 31) & ~31) : n16;
+    const size_t lda = P == P_BF16 ? kpad + 8 : n16 + 1;
+    const size_t rows = P == P_BF16 ? kpad : n16;
+    const size_t mats = P == P_BF16 ? 4 : 3;
+    return pair_mat_off() + mats * rows * lda * es;
+}
+
+// pairs with n <= 16: one wave per item, four items per block
+template <int P>
+__global__ void __launch_bounds__(256) k_ringp_small(DevPtrs d, int cur, uint32_t mask, int n_items) {
+    constexpr size_t per = (pair_lds<P>(16) + 15) & ~(size_t)15;
+    __shared__ __attribute__((aligned(16))) char lds[4 * per];
+    const int w = threadIdx.x >> 6;
+    const int idx = (int)blockIdx.x * 4 + w;
+    Item it = d.it_ring_s[min(idx, n_items - 1)];
+    if (idx >= n_items) it.chan = -1;
+    pair_body<P, 16, 1>(d, it, cur, mask, lds + w * per, threadIdx.x & 63);
+}
+
+// pairs with n > 16: one block per item, one wave per output tile
+template <int P, int N16, int NW>
+__global__ void __launch_bounds__(64 * NW) k_ringp(DevPtrs d, int cur, uint32_t mask, int base) {
+    extern __shared__ __attribute__((aligned(16))) char dyn_lds[];
+    pair_body<P, N16, NW>(d, d.it_ring_b[base + blockIdx.x], cur, mask, dyn_lds, threadIdx.x);
 }
 
 // the ring contribution to amplitude e of problem g: two pair-block entries
@@ -617,15 +669,19 @@ __global__ void __launch_bounds__(256) k_onebody(DevPtrs d) {
 
 // fused S_z = 0 update per (64-row tile of a channel, problem).  Wave w owns
 // rows 16w .. 16w+15 and one 16-column tile of hole pairs at a time.  The pp
-// ladder runs on FP64 MFMA with <ab||cd> generated per lane in the A-operand
-// layout from W(m) in LDS; up to 256 particle-pair rows of t are staged per
-// barrier, so the K loop itself has no barrier.  Then the hh ladder (MFMA),
-// the ring term, one-body terms, t_new = R / eps_ij^ab, mixing and the energy
-// partial sum.
+// ladder runs on MFMA with <ab||cd> generated per lane in the A-operand layout
+// from W(m) in LDS; up to 256 particle-pair rows of t are staged per barrier,
+// so the K loop has no barrier.  Then the hh ladder (MFMA), the ring term,
+// one-body terms, t_new = R / eps_ij^ab, mixing and the energy partial sum, all
+// in FP64.  P selects the precision of the two ladder contractions.
 constexpr int kKP = 256;  // particle-pair columns staged per barrier
+template <int P>
 __global__ void __launch_bounds__(256) k_ladder(DevPtrs d, int cur, double alpha, uint32_t mask) {
-    __shared__ double lutS[kMaxLut];
-    __shared__ double Tk[kKP][16];
+    using ET = typename AccT<P>::E;   // element type of the generated operand
+    using AT = typename AccT<P>::T;   // accumulator
+    __shared__ ET lutS[kMaxLut];
+    // t chunk: [k][16] for FP64 / FP32, transposed [16][k] for BF16
+    __shared__ __attribute__((aligned(16))) char tks[P == P_F64 ? kKP * 16 * 8 : (P == P_F32 ? kKP * 16 * 4 : 16 * (kKP + 8) * 2)];
     __shared__ int32_t cvec[kKP];
     __shared__ int32_t cinfo[kKP];
     __shared__ double sh[4];
@@ -645,7 +701,7 @@ __global__ void __launch_bounds__(256) k_ladder(DevPtrs d, int cur, double alpha
     const int64_t T0 = G.t_base + g * G.n_amp + c.t_off;
     const double* tcur = d.t[cur] + T0;
 
-    for (int e = threadIdx.x; e < G.nlut; e += 256) lutS[e] = d.lut[G.lut_base + g * G.nlut + e];
+    for (int e = threadIdx.x; e < G.nlut; e += 256) lutS[e] = (ET)d.lut[G.lut_base + g * G.nlut + e];
 
     // generator row of this lane (A-operand row = lane % 16)
     const int ra = it.start + 16 * w + (lane & 15);
@@ -657,17 +713,30 @@ __global__ void __launch_bounds__(256) k_ladder(DevPtrs d, int cur, double alpha
         A2 = ax * ax + ay * ay + az * az;
         AK = A2 - 2 * (ax * c.kx + ay * c.ky + az * c.kz);
     }
+    // <ab||cd> for chunk column k (generator row fixed per lane)
+    auto gen = [&](int k) -> ET {
+        const int32_t vec = cvec[k], inf = cinfo[k];
+        const int ac = ax * s_x(vec) + ay * s_y(vec) + az * s_z(vec);
+        const bool valid = rav && ((inf >> 21) & 1);
+        const int m1 = valid ? A2 + (inf & 1023) - 2 * ac : 0;
+        const int m2 = valid ? AK + ((inf >> 10) & 1023) + 2 * ac : 0;
+        ET v = lutS[m1] + lutS[m2];
+        return valid ? ((((inf >> 20) & 1) == sa) ? v : -v) : (ET)0;
+    };
     double es = 0.0;
     for (int ct = 0; ct < nct; ct++) {
         const int col = ct * 16 + (lane & 15);
-        d4 acc = {0.0, 0.0, 0.0, 0.0};
+        AT acc = {0, 0, 0, 0};
         if (pp_on) {
             for (int kp = 0; kp < npp; kp += kKP) {
                 const int kn = min(kKP, npp - kp);
                 __syncthreads();
                 for (int e = threadIdx.x; e < kKP * 16; e += 256) {
-                    const int kk = e >> 4, cc = ct * 16 + (e & 15);
-                    Tk[kk][e & 15] = (kk < kn && cc < nhh) ? tcur[(int64_t)(kp + kk) * nhh + cc] : 0.0;
+                    const int kk = e >> 4, jj = e & 15, cc = ct * 16 + jj;
+                    const double v = (kk < kn && cc < nhh) ? tcur[(int64_t)(kp + kk) * nhh + cc] : 0.0;
+                    if constexpr (P == P_F64) ((double*)tks)[kk * 16 + jj] = v;
+                    else if constexpr (P == P_F32) ((float*)tks)[kk * 16 + jj] = (float)v;
+                    else ((__bf16*)tks)[jj * (kKP + 8) + kk] = (__bf16)v;
                 }
                 for (int kk = threadIdx.x; kk < kKP; kk += 256) {
                     int32_t vec = 0, inf = 0;
@@ -684,18 +753,25 @@ __global__ void __launch_bounds__(256) k_ladder(DevPtrs d, int cur, double alpha
                     cinfo[kk] = inf;
                 }
                 __syncthreads();
-                const int ksteps = (kn + 3) & ~3;
+                if constexpr (P == P_BF16) {
+                    const int ksteps = (kn + 31) & ~31;
+                    for (int kk = 0; kk < ksteps; kk += 32) {
+                        const int k0 = kk + 8 * (lane >> 4);
+                        bf8 av;
+#pragma unroll
+                        for (int j = 0; j < 8; j++) av[j] = (__bf16)gen(k0 + j);
+                        const bf8 bv = *(const bf8*)&((const __bf16*)tks)[(lane & 15) * (kKP + 8) + k0];
+                        acc = mfmabf(av, bv, acc);
+                    }
+                } else {
+                    const int ksteps = (kn + 3) & ~3;
 #pragma unroll 4
-                for (int kk = 0; kk < ksteps; kk += 4) {
-                    const int k = kk + (lane >> 4);
-                    const int32_t vec = cvec[k], inf = cinfo[k];
-                    const int ac = ax * s_x(vec) + ay * s_y(vec) + az * s_z(vec);
-                    const bool valid = rav && ((inf >> 21) & 1);
-                    const int m1 = valid ? A2 + (inf & 1023) - 2 * ac : 0;
-                    const int m2 = valid ? AK + ((inf >> 10) & 1023) + 2 * ac : 0;
-                    double v = lutS[m1] + lutS[m2];
-                    v = valid ? ((((inf >> 20) & 1) == sa) ? v : -v) : 0.0;
-                    acc = mfma64(v, Tk[k][lane & 15], acc);
+                    for (int kk = 0; kk < ksteps; kk += 4) {
+                        const int k = kk + (lane >> 4);
+                        const ET v = gen(k);
+                        if constexpr (P == P_F64) acc = mfma64(v, ((const double*)tks)[k * 16 + (lane & 15)], acc);
+                        else acc = mfma32(v, ((const float*)tks)[k * 16 + (lane & 15)], acc);
+                    }
                 }
             }
         }
@@ -705,10 +781,11 @@ __global__ void __launch_bounds__(256) k_ladder(DevPtrs d, int cur, double alpha
                 const int kq = k0 + (lane >> 4);
                 double a = (rav && kq < nhh) ? tcur[(int64_t)ra * nhh + kq] : 0.0;
                 double b = (kq < nhh && col < nhh) ? xg[kq * nhh + col] : 0.0;
-                acc = mfma64(a, b, acc);
+                if constexpr (P == P_F64) acc = mfma64(a, b, acc);
+                else acc = mfma32((float)a, (float)b, acc);
             }
         }
-        // epilogue: this lane owns rows 16w + lane/16 + 4r of column col
+        // epilogue (FP64): this lane owns rows orow(lane, r) of the wave's 16 rows, column col
         const double* rowE = d.rowE + G.rowa_base + g * G.n_rows_all + c.rowa_off;
         const double* rowX = d.rowX + G.rowa_base + g * G.n_rows_all + c.rowa_off;
         double cE = 0.0, cX = 0.0;
@@ -718,13 +795,13 @@ __global__ void __launch_bounds__(256) k_ladder(DevPtrs d, int cur, double alpha
         }
 #pragma unroll
         for (int r = 0; r < 4; r++) {
-            const int row = it.start + 16 * w + (lane >> 4) + 4 * r;
+            const int row = it.start + 16 * w + orow<P>(lane, r);
             if (row < npp && col < nhh) {
                 const int64_t e = (int64_t)row * nhh + col;
                 const double tc = tcur[e], v = d.vt[T0 + e];
                 double tm = tc;
                 if (act) {
-                    double R = v + acc[r];
+                    double R = v + (double)acc[r];
                     if (ring_on) R += ring_term(d, G, g, c.t_off + e);
                     R += (rowX[row] - cX) * tc;
                     tm = alpha * (R / (cE - rowE[row])) + (1.0 - alpha) * tc;
@@ -1181,9 +1258,6 @@ static ccd_status harvest(ccd_ctx* c) {
         }                                                                               \
     } while (0)
 
-static size_t ring_lds(int n16) {
-    return 3 * (size_t)n16 * (n16 + 1) * sizeof(double) + kMaxLut * sizeof(double) + 4 * kMaxPH * sizeof(int32_t);
-}
 
 static ccd_status refresh_energy(ccd_ctx* c) {
     DevPtrs d = make_ptrs(c);
@@ -1192,11 +1266,10 @@ static ccd_status refresh_energy(ccd_ctx* c) {
     return CCD_OK;
 }
 
-static ccd_status sweep(ccd_ctx* c, double alpha, double tol, uint32_t mask) {
-    DevPtrs d = make_ptrs(c);
-    const int cur = c->cur;
+template <int P>
+static ccd_status launch_contractions(ccd_ctx* c, const DevPtrs& d, int cur, double alpha, uint32_t mask) {
     if (mask & (CCD_T_HH | CCD_T_QHH | CCD_T_QHOLE | CCD_T_QPART)) {
-        LAUNCH(F_DIRECT, k_direct, (int)c->it_direct.size(), 256, 0, d, cur, mask);
+        LAUNCH(F_DIRECT, k_direct<P>, (int)c->it_direct.size(), 256, 0, d, cur, mask);
     }
     LAUNCH(F_DCHI, k_dchi, (int)c->it_dchi.size(), 256, 0, d, mask);
     {
@@ -1209,13 +1282,36 @@ static ccd_status sweep(ccd_ctx* c, double alpha, double tol, uint32_t mask) {
     }
     if (mask & (CCD_T_RING | CCD_T_QRING)) {
         const int ns = (int)c->it_ring_s.size();
-        LAUNCH(F_RING_S, k_ringp_small, (ns + 3) / 4, 256, 0, d, cur, mask, ns);
-        LAUNCH(F_RING_B, (k_ringp<32, 4>), c->ring_n[0], 256, ring_lds(32), d, cur, mask, c->ring_lo[0]);
-        LAUNCH(F_RING_B, (k_ringp<48, 9>), c->ring_n[1], 576, ring_lds(48), d, cur, mask, c->ring_lo[1]);
-        LAUNCH(F_RING_B, (k_ringp<64, 16>), c->ring_n[2], 1024, ring_lds(64), d, cur, mask, c->ring_lo[2]);
-        LAUNCH(F_RING_B, (k_ringp<80, 16>), c->ring_n[3], 1024, ring_lds(80), d, cur, mask, c->ring_lo[3]);
+        LAUNCH(F_RING_S, k_ringp_small<P>, (ns + 3) / 4, 256, 0, d, cur, mask, ns);
+        LAUNCH(F_RING_B, (k_ringp<P, 32, 4>), c->ring_n[0], 256, pair_lds<P>(32), d, cur, mask, c->ring_lo[0]);
+        LAUNCH(F_RING_B, (k_ringp<P, 48, 9>), c->ring_n[1], 576, pair_lds<P>(48), d, cur, mask, c->ring_lo[1]);
+        LAUNCH(F_RING_B, (k_ringp<P, 64, 16>), c->ring_n[2], 1024, pair_lds<P>(64), d, cur, mask, c->ring_lo[2]);
+        LAUNCH(F_RING_B, (k_ringp<P, 80, 16>), c->ring_n[3], 1024, pair_lds<P>(80), d, cur, mask, c->ring_lo[3]);
     }
-    LAUNCH(F_LADDER, k_ladder, (int)c->it_lg.size(), 256, 0, d, cur, alpha, mask);
+    LAUNCH(F_LADDER, k_ladder<P>, (int)c->it_lg.size(), 256, 0, d, cur, alpha, mask);
+    return CCD_OK;
+}
+
+template <int P>
+static hipError_t set_ring_attrs() {
+    hipError_t e;
+    if ((e = hipFuncSetAttribute((const void*)k_ringp<P, 32, 4>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)pair_lds<P>(32))) != hipSuccess) return e;
+    if ((e = hipFuncSetAttribute((const void*)k_ringp<P, 48, 9>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)pair_lds<P>(48))) != hipSuccess) return e;
+    if ((e = hipFuncSetAttribute((const void*)k_ringp<P, 64, 16>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)pair_lds<P>(64))) != hipSuccess) return e;
+    return hipFuncSetAttribute((const void*)k_ringp<P, 80, 16>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)pair_lds<P>(80));
+}
+
+static ccd_status sweep(ccd_ctx* c, double alpha, double tol, uint32_t mask, int prec) {
+    DevPtrs d = make_ptrs(c);
+    const int cur = c->cur;
+    ccd_status s = prec == CCD_PREC_BF16 ? launch_contractions<P_BF16>(c, d, cur, alpha, mask)
+                 : prec == CCD_PREC_FP32 ? launch_contractions<P_F32>(c, d, cur, alpha, mask)
+                                         : launch_contractions<P_F64>(c, d, cur, alpha, mask);
+    if (s != CCD_OK) return s;
     LAUNCH(F_UPDATE, k_update, (int)c->it_ng.size(), 256, 0, d, cur, alpha, mask);
     LAUNCH(F_ENERGY, k_energy, (int)c->probs.size(), 256, 0, d, tol);
     c->cur ^= 1;
@@ -1228,7 +1324,7 @@ static ccd_status sweep(ccd_ctx* c, double alpha, double tol, uint32_t mask) {
 extern "C" {
 
 const char* ccd_last_error(void) { return g_err.c_str(); }
-const char* ccd_version(void) { return "ccd-mi355x 0.2 (gfx950, FP64 MFMA)"; }
+const char* ccd_version(void) { return "ccd-mi355x 0.3 (gfx950; FP64, FP32 and BF16 MFMA contractions)"; }
 
 ccd_status ccd_build_channels(const ccd_problem* probs, int32_t n, void* stream, ccd_ctx** out) {
     if (!probs || !out || n < 1 || n > 4096) {
@@ -1278,12 +1374,9 @@ ccd_status ccd_bind_workspace(ccd_ctx* c, void* ptr, size_t bytes) {
     if (bytes < c->ws_bytes) { set_error("workspace too small"); return CCD_EINVAL; }
     if (((uintptr_t)ptr) & 255) { set_error("workspace must be 256-byte aligned"); return CCD_EINVAL; }
     c->ws = (char*)ptr;
-    HIP_TRY(hipFuncSetAttribute((const void*)k_ringp<48, 9>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)ring_lds(48)));
-    HIP_TRY(hipFuncSetAttribute((const void*)k_ringp<64, 16>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)ring_lds(64)));
-    HIP_TRY(hipFuncSetAttribute((const void*)k_ringp<80, 16>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)ring_lds(80)));
+    HIP_TRY(set_ring_attrs<P_F64>());
+    HIP_TRY(set_ring_attrs<P_F32>());
+    HIP_TRY(set_ring_attrs<P_BF16>());
     std::vector<char> img = static_image(c);
     HIP_TRY(hipMemcpyAsync(c->ws + c->r_static.off, img.data(), img.size(), hipMemcpyHostToDevice, c->stream));
     HIP_TRY(hipMemsetAsync(c->ws + c->r_t0.off, 0, c->ws_bytes - c->r_t0.off, c->stream));
@@ -1299,6 +1392,39 @@ ccd_status ccd_bind_workspace(ccd_ctx* c, void* ptr, size_t bytes) {
     return CCD_OK;
 }
 
+// one phase of sweeps in precision prec; updates the history and counters.
+// min_sweeps: sweeps run before the convergence test may stop a problem.
+static ccd_status run_phase(ccd_ctx* c, const ccd_solver_opts* o, int prec, double tol_phase, int budget,
+                            int min_sweeps, int hist_base, double* e_hist, int& used) {
+    const int P = (int)c->probs.size();
+    std::vector<int32_t> ones(P, 1);
+    HIP_TRY(hipMemcpyAsync(c->ws + c->r_active.off, ones.data(), P * 4, hipMemcpyHostToDevice, c->stream));
+    const bool check = tol_phase > 0.0 || e_hist;
+    std::vector<double> e(P);
+    std::vector<int32_t> act(P, 1);
+    bool all_done = false;
+    used = 0;
+    for (int s = 0; s < budget && !all_done; s++) {
+        const double tol = s + 1 >= min_sweeps ? tol_phase : 0.0;
+        ccd_status st = sweep(c, o->mixing, tol, o->terms, prec);
+        if (st != CCD_OK) return st;
+        used++;
+        if (check) {
+            std::vector<int32_t> was = act;
+            HIP_TRY(hipMemcpyAsync(e.data(), c->ws + c->r_ecorr.off, P * 8, hipMemcpyDeviceToHost, c->stream));
+            HIP_TRY(hipMemcpyAsync(act.data(), c->ws + c->r_active.off, P * 4, hipMemcpyDeviceToHost, c->stream));
+            HIP_TRY(hipStreamSynchronize(c->stream));
+            all_done = tol_phase > 0.0;
+            for (int p = 0; p < P; p++) {
+                const int sl = c->slot_of[p];
+                if (e_hist && was[sl] && hist_base + s < o->max_iter) e_hist[(size_t)p * o->max_iter + hist_base + s] = e[sl];
+                if (act[sl]) all_done = false;
+            }
+        }
+    }
+    return CCD_OK;
+}
+
 ccd_status ccd_iterate(ccd_ctx* c, const ccd_solver_opts* o, int32_t* sweeps_done, double* e_hist) {
     if (!c || !o) { set_error("ccd_iterate: NULL argument"); return CCD_EINVAL; }
     if (!c->bound) { set_error("ccd_iterate: no workspace bound"); return CCD_ESTATE; }
@@ -1306,37 +1432,30 @@ ccd_status ccd_iterate(ccd_ctx* c, const ccd_solver_opts* o, int32_t* sweeps_don
         set_error("ccd_iterate: need 0 < mixing <= 1 and max_iter >= 1");
         return CCD_EINVAL;
     }
-    if (o->precision != CCD_PREC_FP64) {
-        set_error("ccd_iterate: this build runs the FP64 contraction path only");
+    if (o->precision != CCD_PREC_FP64 && o->precision != CCD_PREC_FP32 && o->precision != CCD_PREC_BF16) {
+        set_error("ccd_iterate: unknown precision");
         return CCD_EINVAL;
     }
+    if (o->refine_sweeps < 0) { set_error("ccd_iterate: refine_sweeps < 0"); return CCD_EINVAL; }
     const int P = (int)c->probs.size();
-    std::vector<int32_t> ones(P, 1), zeros(P, 0);
-    HIP_TRY(hipMemcpyAsync(c->ws + c->r_active.off, ones.data(), P * 4, hipMemcpyHostToDevice, c->stream));
+    std::vector<int32_t> zeros(P, 0);
     HIP_TRY(hipMemcpyAsync(c->ws + c->r_sweeps.off, zeros.data(), P * 4, hipMemcpyHostToDevice, c->stream));
-    const bool check = o->tol > 0.0 || e_hist;
-    std::vector<double> e(P);
-    std::vector<int32_t> act(P, 1);
     if (e_hist)
         for (size_t k = 0; k < (size_t)P * o->max_iter; k++) e_hist[k] = NAN;
-    bool all_done = false;
-    for (int s = 0; s < o->max_iter && !all_done; s++) {
-        ccd_status st = sweep(c, o->mixing, o->tol, o->terms);
+    int used = 0;
+    const bool mixed = o->precision != CCD_PREC_FP64;
+    const double tol1 = mixed && o->mixed_tol > 0.0 ? o->mixed_tol : o->tol;
+    ccd_status st = run_phase(c, o, o->precision, tol1, o->max_iter, 1, 0, e_hist, used);
+    if (st != CCD_OK) return st;
+    if (mixed && used < o->max_iter) {
+        // FP64 refinement: continue the FP64 iteration from the mixed-precision iterate
+        int used2 = 0;
+        st = run_phase(c, o, CCD_PREC_FP64, o->tol, o->max_iter - used, std::max(1, o->refine_sweeps), used,
+                       e_hist, used2);
         if (st != CCD_OK) return st;
-        if (check) {
-            std::vector<int32_t> was = act;
-            HIP_TRY(hipMemcpyAsync(e.data(), c->ws + c->r_ecorr.off, P * 8, hipMemcpyDeviceToHost, c->stream));
-            HIP_TRY(hipMemcpyAsync(act.data(), c->ws + c->r_active.off, P * 4, hipMemcpyDeviceToHost, c->stream));
-            HIP_TRY(hipStreamSynchronize(c->stream));
-            all_done = o->tol > 0.0;
-            for (int p = 0; p < P; p++) {
-                const int sl = c->slot_of[p];
-                if (e_hist && was[sl]) e_hist[(size_t)p * o->max_iter + s] = e[sl];
-                if (act[sl]) all_done = false;
-            }
-        }
     }
-    std::vector<int32_t> sw(P);
+    std::vector<int32_t> sw(P), act(P);
+    std::vector<double> e(P);
     HIP_TRY(hipMemcpyAsync(sw.data(), c->ws + c->r_sweeps.off, P * 4, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipMemcpyAsync(e.data(), c->ws + c->r_ecorr.off, P * 8, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipMemcpyAsync(act.data(), c->ws + c->r_active.off, P * 4, hipMemcpyDeviceToHost, c->stream));
