@@ -93,6 +93,13 @@ typedef struct {
                               |dE_n - dE_(n-1)| < mixed_tol (MeV); <= 0 means tol.
                               Rounding in BF16 keeps |dE| from falling far below
                               ~1e-4 |E|, so give BF16 a loose value. */
+    int32_t check_every;   /* sweeps between host reads of the convergence flags
+                              and energies (1..64; 0 = 1).  Problems that converge
+                              inside a chunk stop there; the rest of the chunk
+                              passes them over, so results do not depend on it. */
+    int32_t use_graph;     /* nonzero: each chunk of sweeps is captured once as a
+                              HIP graph and replayed (up to 4 captured shapes are
+                              kept per context); ignored while kernel timing is on */
 } ccd_solver_opts;
 
 typedef struct ccd_ctx ccd_ctx; /* opaque */
@@ -146,12 +153,41 @@ ccd_status ccd_bind_workspace(ccd_ctx* ctx, void* device_ptr, size_t bytes);
  * max_iter sweeps.
  *   sweeps_done  host, n_problems entries (nullable): sweeps each problem ran in this call
  *   e_hist       host, n_problems * max_iter entries (nullable): correlation energy
- *                of problem p after sweep s at e_hist[p*max_iter + s] (NaN after
- *                the problem stopped).  Requesting it synchronises every sweep.
+ *                of problem p after its sweep s at e_hist[p*max_iter + s] (NaN
+ *                after the problem stopped).  The device keeps the energies of the
+ *                last 64 sweeps; the host collects them after every chunk.
  * Returns CCD_OK, CCD_NOT_CONVERGED (tol > 0 and a problem is still moving;
  * with tol <= 0 always CCD_OK), CCD_DIVERGED, CCD_EINVAL, CCD_ESTATE, CCD_EHIP. */
 ccd_status ccd_iterate(ccd_ctx* ctx, const ccd_solver_opts* opts, int32_t* sweeps_done,
                        double* e_hist);
+
+/* Launch shapes.  A context holds CCD_TUNE_LEN integer slots:
+ *  - slots CCD_TUNE_DIRECT .. CCD_TUNE_UPDATE, one per kernel family: 0 = one
+ *    workgroup per work item; m in {1, 2, 4} = a persistent grid of m
+ *    workgroups per compute unit, each looping over the work items.
+ *  - slots CCD_TUNE_RING_NW32 .. NW80, one per size bucket of the ring pair
+ *    blocks (padded order 32, 48, 64, 80): 0 or 1 picks one of two waves-per-
+ *    workgroup shapes (32: 4|2, 48: 9|3, 64: 16|8, 80: 16|9).
+ * Shapes change speed only: every choice gives bit-identical results.
+ * ccd_autotune times the candidates of each slot on the context's own
+ * problems (reps launches each, after a warm launch) and keeps the fastest;
+ * best_ms (nullable, CCD_TUNE_LEN entries) receives each slot's best time per
+ * launch.  It recomputes the sweep's intermediates from the current amplitudes
+ * but does not advance the iteration.  A fresh context has all slots 0. */
+#define CCD_TUNE_DIRECT      0
+#define CCD_TUNE_DCHI        1
+#define CCD_TUNE_RING_SMALL  2
+#define CCD_TUNE_RING        3
+#define CCD_TUNE_LADDER      4
+#define CCD_TUNE_UPDATE      5
+#define CCD_TUNE_RING_NW32   6
+#define CCD_TUNE_RING_NW48   7
+#define CCD_TUNE_RING_NW64   8
+#define CCD_TUNE_RING_NW80   9
+#define CCD_TUNE_LEN        10
+ccd_status ccd_autotune(ccd_ctx* ctx, int32_t precision, int32_t reps, double* best_ms);
+ccd_status ccd_get_tuning(const ccd_ctx* ctx, int32_t* dst, int32_t n);
+ccd_status ccd_set_tuning(ccd_ctx* ctx, const int32_t* src, int32_t n);
 
 /* Energies of problem `problem` (MeV, box totals): E_ref, the MBPT2
  * correlation energy and the current correlation energy 1/4 sum <ij||ab> t

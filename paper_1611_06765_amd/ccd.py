@@ -34,6 +34,9 @@ CCD_T_PP, CCD_T_HH, CCD_T_RING, CCD_T_QHH = 1, 2, 4, 8
 CCD_T_QRING, CCD_T_QHOLE, CCD_T_QPART, CCD_T_ALL = 16, 32, 64, 127
 CCD_PREC_FP64, CCD_PREC_FP32, CCD_PREC_BF16 = 0, 1, 2
 CCD_MAP_STATES, CCD_MAP_CHANNELS, CCD_MAP_HH, CCD_MAP_PP, CCD_MAP_PH_CHANNELS, CCD_MAP_PH = range(6)
+(CCD_TUNE_DIRECT, CCD_TUNE_DCHI, CCD_TUNE_RING_SMALL, CCD_TUNE_RING, CCD_TUNE_LADDER, CCD_TUNE_UPDATE,
+ CCD_TUNE_RING_NW32, CCD_TUNE_RING_NW48, CCD_TUNE_RING_NW64, CCD_TUNE_RING_NW80) = range(10)
+CCD_TUNE_LEN = 10
 
 
 class ccd_problem(C.Structure):
@@ -45,7 +48,7 @@ class ccd_problem(C.Structure):
 class ccd_solver_opts(C.Structure):
     _fields_ = [("mixing", C.c_double), ("tol", C.c_double), ("max_iter", C.c_int32),
                 ("precision", C.c_int32), ("refine_sweeps", C.c_int32), ("terms", C.c_uint32),
-                ("mixed_tol", C.c_double)]
+                ("mixed_tol", C.c_double), ("check_every", C.c_int32), ("use_graph", C.c_int32)]
 
 
 class ccd_info(C.Structure):
@@ -71,6 +74,9 @@ _SIGS = {
     "ccd_reset_amplitudes": (_i32, [_vp]),
     "ccd_export_maps": (_i32, [_vp, _i32, _i32, _ip, _sz, C.POINTER(_sz)]),
     "ccd_export_tables": (_i32, [_vp, _i32, _dp, _dp, _dp]),
+    "ccd_autotune": (_i32, [_vp, _i32, _i32, _dp]),
+    "ccd_get_tuning": (_i32, [_vp, _ip, _i32]),
+    "ccd_set_tuning": (_i32, [_vp, _ip, _i32]),
     "ccd_set_timing": (_i32, [_vp, _i32]),
     "ccd_kernel_families": (_i32, []),
     "ccd_kernel_name": (C.c_char_p, [_i32]),
@@ -173,8 +179,9 @@ class Context:
         return self
 
     def iterate(self, mixing=1.0, tol=0.0, max_iter=1, precision=CCD_PREC_FP64, refine_sweeps=0,
-                terms=CCD_T_ALL, history=False, mixed_tol=0.0):
-        o = ccd_solver_opts(mixing, tol, max_iter, precision, refine_sweeps, terms, mixed_tol)
+                terms=CCD_T_ALL, history=False, mixed_tol=0.0, check_every=1, graph=False):
+        o = ccd_solver_opts(mixing, tol, max_iter, precision, refine_sweeps, terms, mixed_tol,
+                            check_every, int(bool(graph)))
         sweeps = np.zeros(self.n, dtype=np.int32)
         hist = np.zeros(self.n * max_iter) if history else None
         st = _lib.ccd_iterate(self._h, C.byref(o), sweeps.ctypes.data_as(_ip),
@@ -208,6 +215,22 @@ class Context:
 
     def reset_amplitudes(self):
         _check(_lib.ccd_reset_amplitudes(self._h), "ccd_reset_amplitudes")
+
+    def autotune(self, precision=CCD_PREC_FP64, reps=10):
+        """Time the launch shapes of every tuning slot and keep the fastest;
+        returns (table, best ms per launch of each slot)."""
+        best = np.zeros(CCD_TUNE_LEN)
+        _check(_lib.ccd_autotune(self._h, precision, reps, _dptr(best)), "ccd_autotune")
+        return self.get_tuning(), best
+
+    def get_tuning(self):
+        t = np.zeros(CCD_TUNE_LEN, dtype=np.int32)
+        _check(_lib.ccd_get_tuning(self._h, t.ctypes.data_as(_ip), CCD_TUNE_LEN), "ccd_get_tuning")
+        return t
+
+    def set_tuning(self, table):
+        t = np.ascontiguousarray(table, dtype=np.int32)
+        _check(_lib.ccd_set_tuning(self._h, t.ctypes.data_as(_ip), t.size), "ccd_set_tuning")
 
     def set_timing(self, on=True):
         _check(_lib.ccd_set_timing(self._h, int(on)), "ccd_set_timing")

@@ -28,6 +28,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <string>
 #include <type_traits>
@@ -126,7 +127,10 @@ struct DevPtrs {
     double* eprev;
     int32_t* active;
     int32_t* sweeps;
+    double* ehist;           // per problem: energies of the last kHistCap sweeps (ring)
 };
+
+constexpr int kHistCap = 64;  // sweeps between two host reads of the energy history
 
 // --------------------------------------------------------------------------
 // small device helpers
@@ -248,19 +252,19 @@ __global__ void __launch_bounds__(256) k_energy_elem(DevPtrs d) {
 // the diagonal of that product.  Wave w owns output tiles w, w+4, ...
 constexpr int kDirRows = 32;
 template <int P>
-__global__ void __launch_bounds__(256) k_direct(DevPtrs d, int cur, uint32_t mask) {
+__global__ void __launch_bounds__(256) k_direct(DevPtrs d, int cur, uint32_t mask, int n_items) {
     using E = typename std::conditional<P == P_F64, double, float>::type;
     using AT = typename std::conditional<P == P_F64, d4, f4>::type;
     constexpr int PM = P == P_F64 ? P_F64 : P_F32;   // contraction precision used here
     __shared__ E vs[kDirRows][kMaxHH + 1];
     __shared__ E ts[kDirRows][kMaxHH + 1];
-    __shared__ double rsum[kDirRows];
-    const Item it = d.it_direct[blockIdx.x];
-    if (it.chan < 0) return;
+    for (int bi = blockIdx.x; bi < n_items; bi += gridDim.x) {
+    const Item it = d.it_direct[bi];
+    if (it.chan < 0) continue;
     const DevChan c = d.chans[it.chan];
     const DevGroup G = d.groups[c.group];
     const int g = it.start;
-    if (!d.active[G.p0 + g]) return;
+    if (!d.active[G.p0 + g]) continue;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int nhh = c.nhh, npp = c.npp, nt = (nhh + 15) >> 4;
     const int64_t E0 = G.t_base + g * G.n_amp + c.t_off;
@@ -274,7 +278,6 @@ __global__ void __launch_bounds__(256) k_direct(DevPtrs d, int cur, uint32_t mas
     for (int r0 = 0; r0 < npp; r0 += kDirRows) {
         const int rc = min(kDirRows, npp - r0);
         __syncthreads();
-        if (threadIdx.x < kDirRows) rsum[threadIdx.x] = 0.0;
         for (int e = threadIdx.x; e < kDirRows * nhh; e += 256) {
             int r = e / nhh, j = e - r * nhh;
             bool ok = r < rc;
@@ -288,12 +291,23 @@ __global__ void __launch_bounds__(256) k_direct(DevPtrs d, int cur, uint32_t mas
             ts[r][j] = (E)0;
         }
         __syncthreads();
-        // row sums of t v in FP64 straight from memory (one-body terms stay FP64)
-        if ((mask & CCD_T_QPART) && threadIdx.x < rc) {
-            double sum = 0.0;
-            for (int j = 0; j < nhh; j++)
-                sum += t[(int64_t)(r0 + threadIdx.x) * nhh + j] * vt[(int64_t)(r0 + threadIdx.x) * nhh + j];
-            rows[r0 + threadIdx.x] = sum;
+        // row sums of t v (one-body particle terms), FP64 in every mode: from
+        // the staged chunk in FP64, straight from memory (a wave per row) else
+        if (mask & CCD_T_QPART) {
+            if constexpr (P == P_F64) {
+                if (threadIdx.x < rc) {
+                    double sum = 0.0;
+                    for (int j = 0; j < nhh; j++) sum += ts[threadIdx.x][j] * vs[threadIdx.x][j];
+                    rows[r0 + threadIdx.x] = sum;
+                }
+            } else {
+                for (int r = w; r < rc; r += 4) {
+                    const int64_t o = (int64_t)(r0 + r) * nhh;
+                    double sum = lane < nhh ? t[o + lane] * vt[o + lane] : 0.0;
+                    sum = wave_sum(sum);
+                    if (lane == 0) rows[r0 + r] = sum;
+                }
+            }
         }
         if (quad) {
 #pragma unroll
@@ -344,16 +358,18 @@ __global__ void __launch_bounds__(256) k_direct(DevPtrs d, int cur, uint32_t mas
             cols[threadIdx.x] = sum;
         }
     }
+    }
 }
 
 // one-body intermediates: one wave per (state, problem); CSR entries x >= 0
 // name a column sum (holes, +), x < 0 the row sum -x-1 (particles, -)
-__global__ void __launch_bounds__(256) k_dchi(DevPtrs d, uint32_t mask) {
-    const Item it = d.it_dchi[blockIdx.x];
+__global__ void __launch_bounds__(256) k_dchi(DevPtrs d, uint32_t mask, int n_items) {
+    for (int bi = blockIdx.x; bi < n_items; bi += gridDim.x) {
+    const Item it = d.it_dchi[bi];
     const DevGroup G = d.groups[it.chan];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int s = it.start + w;
-    if (s >= G.ns) return;
+    if (s >= G.ns) continue;
     const int x0 = d.csr_ptr[G.csr_off + s], x1 = d.csr_ptr[G.csr_off + s + 1];
     for (int g = 0; g < G.G; g++) {
         if (!d.active[G.p0 + g]) continue;
@@ -370,6 +386,7 @@ __global__ void __launch_bounds__(256) k_dchi(DevPtrs d, uint32_t mask) {
         }
         acc = wave_sum(acc);
         if (lane == 0) d.dchi[G.eps_base + g * G.ns + s] = acc;
+    }
     }
 }
 
@@ -628,17 +645,24 @@ __global__ void __launch_bounds__(256) k_ringp_small(DevPtrs d, int cur, uint32_
     constexpr size_t per = (pair_lds<P>(16) + 15) & ~(size_t)15;
     __shared__ __attribute__((aligned(16))) char lds[4 * per];
     const int w = threadIdx.x >> 6;
-    const int idx = (int)blockIdx.x * 4 + w;
-    Item it = d.it_ring_s[min(idx, n_items - 1)];
-    if (idx >= n_items) it.chan = -1;
-    pair_body<P, 16, 1>(d, it, cur, mask, lds + w * per, threadIdx.x & 63);
+    const int nb = (n_items + 3) / 4;
+    for (int bi = blockIdx.x; bi < nb; bi += gridDim.x) {
+        const int idx = bi * 4 + w;
+        Item it = d.it_ring_s[min(idx, n_items - 1)];
+        if (idx >= n_items) it.chan = -1;
+        __syncthreads();  // the previous item's reads of LDS are done
+        pair_body<P, 16, 1>(d, it, cur, mask, lds + w * per, threadIdx.x & 63);
+    }
 }
 
 // pairs with n > 16: one block per item, one wave per output tile
 template <int P, int N16, int NW>
-__global__ void __launch_bounds__(64 * NW) k_ringp(DevPtrs d, int cur, uint32_t mask, int base) {
+__global__ void __launch_bounds__(64 * NW) k_ringp(DevPtrs d, int cur, uint32_t mask, int base, int n_items) {
     extern __shared__ __attribute__((aligned(16))) char dyn_lds[];
-    pair_body<P, N16, NW>(d, d.it_ring_b[base + blockIdx.x], cur, mask, dyn_lds, threadIdx.x);
+    for (int bi = blockIdx.x; bi < n_items; bi += gridDim.x) {
+        __syncthreads();  // the previous item's reads of LDS are done
+        pair_body<P, N16, NW>(d, d.it_ring_b[base + bi], cur, mask, dyn_lds, threadIdx.x);
+    }
 }
 
 // the ring contribution to amplitude e of problem g: two pair-block entries
@@ -676,7 +700,7 @@ __global__ void __launch_bounds__(256) k_onebody(DevPtrs d) {
 // in FP64.  P selects the precision of the two ladder contractions.
 constexpr int kKP = 256;  // particle-pair columns staged per barrier
 template <int P>
-__global__ void __launch_bounds__(256) k_ladder(DevPtrs d, int cur, double alpha, uint32_t mask) {
+__global__ void __launch_bounds__(256) k_ladder(DevPtrs d, int cur, double alpha, uint32_t mask, int n_items) {
     using ET = typename AccT<P>::E;   // element type of the generated operand
     using AT = typename AccT<P>::T;   // accumulator
     __shared__ ET lutS[kMaxLut];
@@ -685,8 +709,9 @@ __global__ void __launch_bounds__(256) k_ladder(DevPtrs d, int cur, double alpha
     __shared__ int32_t cvec[kKP];
     __shared__ int32_t cinfo[kKP];
     __shared__ double sh[4];
-    const Item lg = d.it_lg[blockIdx.x];
-    if (lg.chan < 0) return;
+    for (int bi = blockIdx.x; bi < n_items; bi += gridDim.x) {
+    const Item lg = d.it_lg[bi];
+    if (lg.chan < 0) continue;
     const int litem = lg.chan, g = lg.start;
     const Item it = d.it_ladder[litem];
     const DevChan c = d.chans[it.chan];
@@ -701,6 +726,7 @@ __global__ void __launch_bounds__(256) k_ladder(DevPtrs d, int cur, double alpha
     const int64_t T0 = G.t_base + g * G.n_amp + c.t_off;
     const double* tcur = d.t[cur] + T0;
 
+    __syncthreads();  // the previous item's reads of lutS are done
     for (int e = threadIdx.x; e < G.nlut; e += 256) lutS[e] = (ET)d.lut[G.lut_base + g * G.nlut + e];
 
     // generator row of this lane (A-operand row = lane % 16)
@@ -814,12 +840,14 @@ __global__ void __launch_bounds__(256) k_ladder(DevPtrs d, int cur, double alpha
     double s = block_sum256(es, sh);
     const int nitem = G.ladder_hi - G.ladder_lo;
     if (threadIdx.x == 0) d.epart[G.epart_base + g * nitem + (litem - G.ladder_lo)] = s;
+    }
 }
 
 // update of the S_z = +-1 blocks: only the ring and one-body terms survive
-__global__ void __launch_bounds__(256) k_update(DevPtrs d, int cur, double alpha, uint32_t mask) {
-    const Item ig = d.it_ng[blockIdx.x];
-    if (ig.chan < 0) return;
+__global__ void __launch_bounds__(256) k_update(DevPtrs d, int cur, double alpha, uint32_t mask, int n_items) {
+    for (int bi = blockIdx.x; bi < n_items; bi += gridDim.x) {
+    const Item ig = d.it_ng[bi];
+    if (ig.chan < 0) continue;
     const Item it = d.it_nsz0[ig.chan];
     const int g = ig.start;
     const DevChan c = d.chans[it.chan];
@@ -848,6 +876,7 @@ __global__ void __launch_bounds__(256) k_update(DevPtrs d, int cur, double alpha
             d.t[cur ^ 1][E] = tm;
         }
     }
+    }
 }
 
 // per-problem energy after a sweep, convergence test, divergence flag
@@ -864,6 +893,7 @@ __global__ void __launch_bounds__(256) k_energy(DevPtrs d, double tol) {
         double old = d.ecorr[p];
         d.eprev[p] = old;
         d.ecorr[p] = e;
+        d.ehist[(size_t)p * kHistCap + d.sweeps[p] % kHistCap] = e;
         d.sweeps[p] += 1;
         if (!isfinite(e)) d.active[p] = 0;
         else if (tol > 0.0 && fabs(e - old) < tol) d.active[p] = 0;
@@ -879,6 +909,19 @@ static const char* kFamilyNames[F_NUM] = {"init", "direct", "dchi", "ring_small"
 
 struct Region {
     size_t off = 0, bytes = 0;
+};
+
+// a captured run of n sweeps and the arguments it was captured with
+struct GraphEntry {
+    int prec, cur, n;
+    uint32_t mask;
+    double alpha, tol;
+    int32_t tune[CCD_TUNE_LEN];
+    hipGraphExec_t exec;
+    bool same(int p, int c0, int n0, uint32_t m, double a, double t, const int32_t* tu) const {
+        return prec == p && cur == c0 && n == n0 && mask == m && alpha == a && tol == t &&
+               std::memcmp(tune, tu, sizeof(tune)) == 0;
+    }
 };
 
 struct ccd_ctx {
@@ -899,7 +942,7 @@ struct ccd_ctx {
     int n_rows = 0, n_cols = 0, n_chh = 0, n_eps = 0, n_epart = 0, n_eparte = 0, max_ph = 0;
     // workspace
     Region r_static, r_t0, r_t1, r_vt, r_chh, r_rows, r_cols, r_dchi, r_zp, r_rowx, r_colx, r_epart, r_eparte,
-        r_ecorr, r_eprev, r_active, r_sweeps;
+        r_ecorr, r_eprev, r_active, r_sweeps, r_ehist;
     size_t ws_bytes = 0;
     char* ws = nullptr;
     bool bound = false;
@@ -912,6 +955,11 @@ struct ccd_ctx {
     size_t ev_used = 0;
     double ms[F_NUM] = {0};
     int64_t launches[F_NUM] = {0};
+    // launch shapes (CCD_TUNE_* slots), chosen by ccd_autotune or set by the caller
+    int32_t tune[CCD_TUNE_LEN] = {0};
+    // replayable sweep graphs
+    hipStream_t cap_stream = nullptr;
+    std::vector<GraphEntry> graphs;
 };
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -968,6 +1016,7 @@ static DevPtrs make_ptrs(ccd_ctx* c) {
     d.eprev = (double*)(base + c->r_eprev.off);
     d.active = (int32_t*)(base + c->r_active.off);
     d.sweeps = (int32_t*)(base + c->r_sweeps.off);
+    d.ehist = (double*)(base + c->r_ehist.off);
     return d;
 }
 
@@ -1012,6 +1061,7 @@ static void layout(ccd_ctx* c) {
     region(c->r_eprev, P * 8);
     region(c->r_active, P * 4);
     region(c->r_sweeps, P * 4);
+    region(c->r_ehist, P * kHistCap * 8);
     c->ws_bytes = o;
 }
 
@@ -1266,43 +1316,105 @@ static ccd_status refresh_energy(ccd_ctx* c) {
     return CCD_OK;
 }
 
+// grid of a family: one block per item, or (slot value m > 0) a persistent
+// grid of m blocks per compute unit looping over the items; a multiple of 8
+// keeps every item on the XCD that xcd_order chose for it
+static int grid_for(const ccd_ctx* c, int slot, int nb) {
+    const int m = c->tune[slot];
+    if (m <= 0 || nb <= 0) return nb;
+    return std::min(nb, m * 256);
+}
+
+template <int P>
+static ccd_status L_direct(ccd_ctx* c, const DevPtrs& d, int cur, uint32_t mask) {
+    const int n = (int)c->it_direct.size();
+    if (mask & (CCD_T_HH | CCD_T_QHH | CCD_T_QHOLE | CCD_T_QPART))
+        LAUNCH(F_DIRECT, k_direct<P>, grid_for(c, CCD_TUNE_DIRECT, n), 256, 0, d, cur, mask, n);
+    return CCD_OK;
+}
+
+static ccd_status L_dchi(ccd_ctx* c, const DevPtrs& d, uint32_t mask) {
+    const int n = (int)c->it_dchi.size();
+    LAUNCH(F_DCHI, k_dchi, grid_for(c, CCD_TUNE_DCHI, n), 256, 0, d, mask, n);
+    int maxe = 0;
+    for (const DevGroup& D : c->dgroups) maxe = std::max(maxe, D.n_rows_all + D.n_cols_all);
+    HIP_TRY(ev_begin(c, F_DCHI));
+    hipLaunchKernelGGL(k_onebody, dim3((maxe + 255) / 256, (int)c->probs.size()), dim3(256), 0, c->stream, d);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(ev_end(c));
+    return CCD_OK;
+}
+
+template <int P>
+static ccd_status L_ring_small(ccd_ctx* c, const DevPtrs& d, int cur, uint32_t mask) {
+    const int n = (int)c->it_ring_s.size();
+    if (mask & (CCD_T_RING | CCD_T_QRING))
+        LAUNCH(F_RING_S, k_ringp_small<P>, grid_for(c, CCD_TUNE_RING_SMALL, (n + 3) / 4), 256, 0, d, cur, mask, n);
+    return CCD_OK;
+}
+
+// waves per block of each ring size class: slot value 0 -> NWA, 1 -> NWB
+template <int P, int N16, int NWA, int NWB>
+static ccd_status L_ring_class(ccd_ctx* c, const DevPtrs& d, int cur, uint32_t mask, int k) {
+    const int n = c->ring_n[k], lo = c->ring_lo[k];
+    const int grid = grid_for(c, CCD_TUNE_RING, n);
+    if (c->tune[CCD_TUNE_RING_NW32 + k] == 0)
+        LAUNCH(F_RING_B, (k_ringp<P, N16, NWA>), grid, 64 * NWA, pair_lds<P>(N16), d, cur, mask, lo, n);
+    else
+        LAUNCH(F_RING_B, (k_ringp<P, N16, NWB>), grid, 64 * NWB, pair_lds<P>(N16), d, cur, mask, lo, n);
+    return CCD_OK;
+}
+
+template <int P>
+static ccd_status L_ring(ccd_ctx* c, const DevPtrs& d, int cur, uint32_t mask, int only = -1) {
+    if (!(mask & (CCD_T_RING | CCD_T_QRING))) return CCD_OK;
+    ccd_status s = CCD_OK;
+    if (s == CCD_OK && (only < 0 || only == 0)) s = L_ring_class<P, 32, 4, 2>(c, d, cur, mask, 0);
+    if (s == CCD_OK && (only < 0 || only == 1)) s = L_ring_class<P, 48, 9, 3>(c, d, cur, mask, 1);
+    if (s == CCD_OK && (only < 0 || only == 2)) s = L_ring_class<P, 64, 16, 8>(c, d, cur, mask, 2);
+    if (s == CCD_OK && (only < 0 || only == 3)) s = L_ring_class<P, 80, 16, 9>(c, d, cur, mask, 3);
+    return s;
+}
+
+template <int P>
+static ccd_status L_ladder(ccd_ctx* c, const DevPtrs& d, int cur, double alpha, uint32_t mask) {
+    const int n = (int)c->it_lg.size();
+    LAUNCH(F_LADDER, k_ladder<P>, grid_for(c, CCD_TUNE_LADDER, n), 256, 0, d, cur, alpha, mask, n);
+    return CCD_OK;
+}
+
+static ccd_status L_update(ccd_ctx* c, const DevPtrs& d, int cur, double alpha, uint32_t mask) {
+    const int n = (int)c->it_ng.size();
+    LAUNCH(F_UPDATE, k_update, grid_for(c, CCD_TUNE_UPDATE, n), 256, 0, d, cur, alpha, mask, n);
+    return CCD_OK;
+}
+
 template <int P>
 static ccd_status launch_contractions(ccd_ctx* c, const DevPtrs& d, int cur, double alpha, uint32_t mask) {
-    if (mask & (CCD_T_HH | CCD_T_QHH | CCD_T_QHOLE | CCD_T_QPART)) {
-        LAUNCH(F_DIRECT, k_direct<P>, (int)c->it_direct.size(), 256, 0, d, cur, mask);
-    }
-    LAUNCH(F_DCHI, k_dchi, (int)c->it_dchi.size(), 256, 0, d, mask);
-    {
-        int maxe = 0;
-        for (const DevGroup& D : c->dgroups) maxe = std::max(maxe, D.n_rows_all + D.n_cols_all);
-        HIP_TRY(ev_begin(c, F_DCHI));
-        hipLaunchKernelGGL(k_onebody, dim3((maxe + 255) / 256, (int)c->probs.size()), dim3(256), 0, c->stream, d);
-        HIP_TRY(hipGetLastError());
-        HIP_TRY(ev_end(c));
-    }
-    if (mask & (CCD_T_RING | CCD_T_QRING)) {
-        const int ns = (int)c->it_ring_s.size();
-        LAUNCH(F_RING_S, k_ringp_small<P>, (ns + 3) / 4, 256, 0, d, cur, mask, ns);
-        LAUNCH(F_RING_B, (k_ringp<P, 32, 4>), c->ring_n[0], 256, pair_lds<P>(32), d, cur, mask, c->ring_lo[0]);
-        LAUNCH(F_RING_B, (k_ringp<P, 48, 9>), c->ring_n[1], 576, pair_lds<P>(48), d, cur, mask, c->ring_lo[1]);
-        LAUNCH(F_RING_B, (k_ringp<P, 64, 16>), c->ring_n[2], 1024, pair_lds<P>(64), d, cur, mask, c->ring_lo[2]);
-        LAUNCH(F_RING_B, (k_ringp<P, 80, 16>), c->ring_n[3], 1024, pair_lds<P>(80), d, cur, mask, c->ring_lo[3]);
-    }
-    LAUNCH(F_LADDER, k_ladder<P>, (int)c->it_lg.size(), 256, 0, d, cur, alpha, mask);
-    return CCD_OK;
+    ccd_status s = L_direct<P>(c, d, cur, mask);
+    if (s == CCD_OK) s = L_dchi(c, d, mask);
+    if (s == CCD_OK) s = L_ring_small<P>(c, d, cur, mask);
+    if (s == CCD_OK) s = L_ring<P>(c, d, cur, mask);
+    if (s == CCD_OK) s = L_ladder<P>(c, d, cur, alpha, mask);
+    return s;
+}
+
+template <int P, int N16, int NWA, int NWB>
+static hipError_t set_ring_attr_pair() {
+    hipError_t e = hipFuncSetAttribute((const void*)k_ringp<P, N16, NWA>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)pair_lds<P>(N16));
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void*)k_ringp<P, N16, NWB>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)pair_lds<P>(N16));
 }
 
 template <int P>
 static hipError_t set_ring_attrs() {
     hipError_t e;
-    if ((e = hipFuncSetAttribute((const void*)k_ringp<P, 32, 4>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)pair_lds<P>(32))) != hipSuccess) return e;
-    if ((e = hipFuncSetAttribute((const void*)k_ringp<P, 48, 9>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)pair_lds<P>(48))) != hipSuccess) return e;
-    if ((e = hipFuncSetAttribute((const void*)k_ringp<P, 64, 16>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)pair_lds<P>(64))) != hipSuccess) return e;
-    return hipFuncSetAttribute((const void*)k_ringp<P, 80, 16>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)pair_lds<P>(80));
+    if ((e = set_ring_attr_pair<P, 32, 4, 2>()) != hipSuccess) return e;
+    if ((e = set_ring_attr_pair<P, 48, 9, 3>()) != hipSuccess) return e;
+    if ((e = set_ring_attr_pair<P, 64, 16, 8>()) != hipSuccess) return e;
+    return set_ring_attr_pair<P, 80, 16, 9>();
 }
 
 static ccd_status sweep(ccd_ctx* c, double alpha, double tol, uint32_t mask, int prec) {
@@ -1312,9 +1424,132 @@ static ccd_status sweep(ccd_ctx* c, double alpha, double tol, uint32_t mask, int
                  : prec == CCD_PREC_FP32 ? launch_contractions<P_F32>(c, d, cur, alpha, mask)
                                          : launch_contractions<P_F64>(c, d, cur, alpha, mask);
     if (s != CCD_OK) return s;
-    LAUNCH(F_UPDATE, k_update, (int)c->it_ng.size(), 256, 0, d, cur, alpha, mask);
+    s = L_update(c, d, cur, alpha, mask);
+    if (s != CCD_OK) return s;
     LAUNCH(F_ENERGY, k_energy, (int)c->probs.size(), 256, 0, d, tol);
     c->cur ^= 1;
+    return CCD_OK;
+}
+
+// n sweeps: launched one by one, or (graph) as one replay of a captured graph
+// of the same n sweeps; kernel timing disables the graph
+static constexpr size_t kMaxGraphs = 4;
+static ccd_status run_sweeps(ccd_ctx* c, int n, double alpha, double tol, uint32_t mask, int prec, bool graph) {
+    if (!graph || c->timing) {
+        for (int k = 0; k < n; k++) {
+            ccd_status s = sweep(c, alpha, tol, mask, prec);
+            if (s != CCD_OK) return s;
+        }
+        return CCD_OK;
+    }
+    GraphEntry* ge = nullptr;
+    for (GraphEntry& g : c->graphs)
+        if (g.same(prec, c->cur, n, mask, alpha, tol, c->tune)) ge = &g;
+    if (!ge) {
+        // captured on a private stream (the caller's may be the null stream),
+        // replayed on the caller's stream in order with its other work
+        if (!c->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+        const hipStream_t user = c->stream;
+        const int cur0 = c->cur;
+        HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+        c->stream = c->cap_stream;
+        ccd_status s = CCD_OK;
+        for (int k = 0; k < n && s == CCD_OK; k++) s = sweep(c, alpha, tol, mask, prec);
+        hipGraph_t gr = nullptr;
+        const hipError_t ec = hipStreamEndCapture(c->cap_stream, &gr);
+        c->stream = user;
+        c->cur = cur0;
+        if (s != CCD_OK) {
+            if (gr) (void)hipGraphDestroy(gr);
+            return s;
+        }
+        if (ec != hipSuccess) {
+            set_error(std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
+            return CCD_EHIP;
+        }
+        hipGraphExec_t ex = nullptr;
+        const hipError_t ei = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(gr);
+        if (ei != hipSuccess) {
+            set_error(std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+            return CCD_EHIP;
+        }
+        if (c->graphs.size() >= kMaxGraphs) {
+            (void)hipGraphExecDestroy(c->graphs.front().exec);
+            c->graphs.erase(c->graphs.begin());
+        }
+        GraphEntry e;
+        e.prec = prec; e.cur = cur0; e.n = n; e.mask = mask; e.alpha = alpha; e.tol = tol;
+        std::memcpy(e.tune, c->tune, sizeof(e.tune));
+        e.exec = ex;
+        c->graphs.push_back(e);
+        ge = &c->graphs.back();
+    }
+    HIP_TRY(hipGraphLaunch(ge->exec, c->stream));
+    c->cur ^= (n & 1);
+    return CCD_OK;
+}
+
+// ---- autotuner ---------------------------------------------------------------
+// Every family launch is idempotent for a fixed cur (it rewrites its outputs
+// from t[cur] and the other families' outputs), so a family can be launched
+// repeatedly and timed alone.  Slots are tuned one at a time in pipeline
+// order, each candidate timed over reps launches after one warm launch; a
+// candidate replaces the incumbent only when it is 2% faster.
+template <typename F>
+static ccd_status time_family(ccd_ctx* c, F&& launch, int reps, hipEvent_t e0, hipEvent_t e1, double& ms) {
+    ccd_status s = launch();
+    if (s != CCD_OK) return s;
+    HIP_TRY(hipEventRecord(e0, c->stream));
+    for (int r = 0; r < reps && s == CCD_OK; r++) s = launch();
+    if (s != CCD_OK) return s;
+    HIP_TRY(hipEventRecord(e1, c->stream));
+    HIP_TRY(hipEventSynchronize(e1));
+    float f = 0.f;
+    HIP_TRY(hipEventElapsedTime(&f, e0, e1));
+    ms = (double)f / reps;
+    return CCD_OK;
+}
+
+template <int P>
+static ccd_status autotune_impl(ccd_ctx* c, int reps, double* best_ms, hipEvent_t e0, hipEvent_t e1) {
+    const DevPtrs d = make_ptrs(c);
+    const int cur = c->cur;
+    const uint32_t mask = CCD_T_ALL;
+    const double alpha = 0.5;
+    ccd_status s = launch_contractions<P>(c, d, cur, alpha, mask);
+    if (s == CCD_OK) s = L_update(c, d, cur, alpha, mask);
+    if (s != CCD_OK) return s;
+    struct Spec {
+        int slot, ncand;
+        int cand[4];
+        std::function<ccd_status()> fn;
+    };
+    const Spec specs[] = {
+        {CCD_TUNE_DIRECT, 4, {0, 1, 2, 4}, [&] { return L_direct<P>(c, d, cur, mask); }},
+        {CCD_TUNE_DCHI, 4, {0, 1, 2, 4}, [&] { return L_dchi(c, d, mask); }},
+        {CCD_TUNE_RING_SMALL, 4, {0, 1, 2, 4}, [&] { return L_ring_small<P>(c, d, cur, mask); }},
+        {CCD_TUNE_RING_NW32, 2, {0, 1}, [&] { return L_ring<P>(c, d, cur, mask, 0); }},
+        {CCD_TUNE_RING_NW48, 2, {0, 1}, [&] { return L_ring<P>(c, d, cur, mask, 1); }},
+        {CCD_TUNE_RING_NW64, 2, {0, 1}, [&] { return L_ring<P>(c, d, cur, mask, 2); }},
+        {CCD_TUNE_RING_NW80, 2, {0, 1}, [&] { return L_ring<P>(c, d, cur, mask, 3); }},
+        {CCD_TUNE_RING, 4, {0, 1, 2, 4}, [&] { return L_ring<P>(c, d, cur, mask); }},
+        {CCD_TUNE_LADDER, 4, {0, 1, 2, 4}, [&] { return L_ladder<P>(c, d, cur, alpha, mask); }},
+        {CCD_TUNE_UPDATE, 4, {0, 1, 2, 4}, [&] { return L_update(c, d, cur, alpha, mask); }},
+    };
+    for (const Spec& sp : specs) {
+        double best = 0.0;
+        int bestv = sp.cand[0];
+        for (int k = 0; k < sp.ncand; k++) {
+            c->tune[sp.slot] = sp.cand[k];
+            double ms = 0.0;
+            s = time_family(c, sp.fn, reps, e0, e1, ms);
+            if (s != CCD_OK) return s;
+            if (k == 0 || ms < 0.98 * best) { best = ms; bestv = sp.cand[k]; }
+        }
+        c->tune[sp.slot] = bestv;
+        if (best_ms) best_ms[sp.slot] = best;
+    }
     return CCD_OK;
 }
 
@@ -1392,32 +1627,53 @@ ccd_status ccd_bind_workspace(ccd_ctx* c, void* ptr, size_t bytes) {
     return CCD_OK;
 }
 
-// one phase of sweeps in precision prec; updates the history and counters.
+// one phase of sweeps in precision prec.  Sweeps run in chunks of up to
+// check_every (graph replays when asked); after each chunk the host reads the
+// per-problem sweep counters, active flags and the device energy history.
 // min_sweeps: sweeps run before the convergence test may stop a problem.
 static ccd_status run_phase(ccd_ctx* c, const ccd_solver_opts* o, int prec, double tol_phase, int budget,
-                            int min_sweeps, int hist_base, double* e_hist, int& used) {
+                            int min_sweeps, double* e_hist, int& used) {
     const int P = (int)c->probs.size();
     std::vector<int32_t> ones(P, 1);
     HIP_TRY(hipMemcpyAsync(c->ws + c->r_active.off, ones.data(), P * 4, hipMemcpyHostToDevice, c->stream));
     const bool check = tol_phase > 0.0 || e_hist;
-    std::vector<double> e(P);
-    std::vector<int32_t> act(P, 1);
+    const int every = check ? std::max(1, std::min(o->check_every > 0 ? o->check_every : 1, kHistCap)) : kHistCap;
+    const bool graph = o->use_graph != 0;
+    std::vector<int32_t> sw(P, 0), sw0(P, 0), act(P, 1);
+    std::vector<double> hb((size_t)P * kHistCap);
+    if (e_hist) {
+        HIP_TRY(hipMemcpyAsync(sw.data(), c->ws + c->r_sweeps.off, P * 4, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+    }
     bool all_done = false;
     used = 0;
-    for (int s = 0; s < budget && !all_done; s++) {
-        const double tol = s + 1 >= min_sweeps ? tol_phase : 0.0;
-        ccd_status st = sweep(c, o->mixing, tol, o->terms, prec);
+    while (used < budget && !all_done) {
+        int n;
+        double tol;
+        if (used + 1 < min_sweeps) {
+            n = std::min(std::min(min_sweeps - 1 - used, budget - used), every);
+            tol = 0.0;
+        } else {
+            n = std::min(every, budget - used);
+            tol = tol_phase;
+        }
+        ccd_status st = run_sweeps(c, n, o->mixing, tol, o->terms, prec, graph);
         if (st != CCD_OK) return st;
-        used++;
+        used += n;
         if (check) {
-            std::vector<int32_t> was = act;
-            HIP_TRY(hipMemcpyAsync(e.data(), c->ws + c->r_ecorr.off, P * 8, hipMemcpyDeviceToHost, c->stream));
+            sw0 = sw;
+            HIP_TRY(hipMemcpyAsync(sw.data(), c->ws + c->r_sweeps.off, P * 4, hipMemcpyDeviceToHost, c->stream));
             HIP_TRY(hipMemcpyAsync(act.data(), c->ws + c->r_active.off, P * 4, hipMemcpyDeviceToHost, c->stream));
+            if (e_hist)
+                HIP_TRY(hipMemcpyAsync(hb.data(), c->ws + c->r_ehist.off, hb.size() * 8, hipMemcpyDeviceToHost,
+                                       c->stream));
             HIP_TRY(hipStreamSynchronize(c->stream));
             all_done = tol_phase > 0.0;
             for (int p = 0; p < P; p++) {
                 const int sl = c->slot_of[p];
-                if (e_hist && was[sl] && hist_base + s < o->max_iter) e_hist[(size_t)p * o->max_iter + hist_base + s] = e[sl];
+                if (e_hist)
+                    for (int k = sw0[sl]; k < sw[sl] && k < o->max_iter; k++)
+                        e_hist[(size_t)p * o->max_iter + k] = hb[(size_t)sl * kHistCap + k % kHistCap];
                 if (act[sl]) all_done = false;
             }
         }
@@ -1436,7 +1692,10 @@ ccd_status ccd_iterate(ccd_ctx* c, const ccd_solver_opts* o, int32_t* sweeps_don
         set_error("ccd_iterate: unknown precision");
         return CCD_EINVAL;
     }
-    if (o->refine_sweeps < 0) { set_error("ccd_iterate: refine_sweeps < 0"); return CCD_EINVAL; }
+    if (o->refine_sweeps < 0 || o->check_every < 0) {
+        set_error("ccd_iterate: refine_sweeps and check_every must be >= 0");
+        return CCD_EINVAL;
+    }
     const int P = (int)c->probs.size();
     std::vector<int32_t> zeros(P, 0);
     HIP_TRY(hipMemcpyAsync(c->ws + c->r_sweeps.off, zeros.data(), P * 4, hipMemcpyHostToDevice, c->stream));
@@ -1445,13 +1704,13 @@ ccd_status ccd_iterate(ccd_ctx* c, const ccd_solver_opts* o, int32_t* sweeps_don
     int used = 0;
     const bool mixed = o->precision != CCD_PREC_FP64;
     const double tol1 = mixed && o->mixed_tol > 0.0 ? o->mixed_tol : o->tol;
-    ccd_status st = run_phase(c, o, o->precision, tol1, o->max_iter, 1, 0, e_hist, used);
+    ccd_status st = run_phase(c, o, o->precision, tol1, o->max_iter, 1, e_hist, used);
     if (st != CCD_OK) return st;
     if (mixed && used < o->max_iter) {
         // FP64 refinement: continue the FP64 iteration from the mixed-precision iterate
         int used2 = 0;
-        st = run_phase(c, o, CCD_PREC_FP64, o->tol, o->max_iter - used, std::max(1, o->refine_sweeps), used,
-                       e_hist, used2);
+        st = run_phase(c, o, CCD_PREC_FP64, o->tol, o->max_iter - used, std::max(1, o->refine_sweeps), e_hist,
+                       used2);
         if (st != CCD_OK) return st;
     }
     std::vector<int32_t> sw(P), act(P);
@@ -1570,6 +1829,55 @@ ccd_status ccd_set_timing(ccd_ctx* c, int32_t on) {
     return CCD_OK;
 }
 
+ccd_status ccd_autotune(ccd_ctx* c, int32_t precision, int32_t reps, double* best_ms) {
+    if (!c) { set_error("ccd_autotune: NULL context"); return CCD_EINVAL; }
+    if (!c->bound) { set_error("ccd_autotune: no workspace bound"); return CCD_ESTATE; }
+    if (precision < CCD_PREC_FP64 || precision > CCD_PREC_BF16 || reps < 1 || reps > 1000) {
+        set_error("ccd_autotune: need a CCD_PREC_* precision and 1 <= reps <= 1000");
+        return CCD_EINVAL;
+    }
+    ccd_status s = harvest(c);
+    if (s != CCD_OK) return s;
+    const bool timing = c->timing;
+    c->timing = false;
+    const int P = (int)c->probs.size();
+    std::vector<int32_t> ones(P, 1);
+    HIP_TRY(hipMemcpyAsync(c->ws + c->r_active.off, ones.data(), P * 4, hipMemcpyHostToDevice, c->stream));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    hipError_t he = hipEventCreate(&e1);
+    if (he != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        set_error(std::string("hipEventCreate: ") + hipGetErrorString(he));
+        return CCD_EHIP;
+    }
+    s = precision == CCD_PREC_BF16 ? autotune_impl<P_BF16>(c, reps, best_ms, e0, e1)
+      : precision == CCD_PREC_FP32 ? autotune_impl<P_F32>(c, reps, best_ms, e0, e1)
+                                   : autotune_impl<P_F64>(c, reps, best_ms, e0, e1);
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->timing = timing;
+    return s;
+}
+
+ccd_status ccd_get_tuning(const ccd_ctx* c, int32_t* dst, int32_t n) {
+    if (!c || !dst || n < CCD_TUNE_LEN) { set_error("ccd_get_tuning: need dst of CCD_TUNE_LEN entries"); return CCD_EINVAL; }
+    std::copy(c->tune, c->tune + CCD_TUNE_LEN, dst);
+    return CCD_OK;
+}
+
+ccd_status ccd_set_tuning(ccd_ctx* c, const int32_t* src, int32_t n) {
+    if (!c || !src || n < CCD_TUNE_LEN) { set_error("ccd_set_tuning: need src of CCD_TUNE_LEN entries"); return CCD_EINVAL; }
+    for (int k = 0; k < CCD_TUNE_LEN; k++) {
+        const bool ok = k < CCD_TUNE_RING_NW32 ? (src[k] == 0 || src[k] == 1 || src[k] == 2 || src[k] == 4)
+                                              : (src[k] == 0 || src[k] == 1);
+        if (!ok) { set_error("ccd_set_tuning: value out of range in slot " + std::to_string(k)); return CCD_EINVAL; }
+    }
+    std::copy(src, src + CCD_TUNE_LEN, c->tune);
+    return CCD_OK;
+}
+
 int32_t ccd_kernel_families(void) { return F_NUM; }
 const char* ccd_kernel_name(int32_t f) { return (f >= 0 && f < F_NUM) ? kFamilyNames[f] : ""; }
 
@@ -1587,6 +1895,9 @@ ccd_status ccd_kernel_times(ccd_ctx* c, double* ms, int64_t* launches, int32_t r
 
 void ccd_destroy(ccd_ctx* c) {
     if (!c) return;
+    if (!c->graphs.empty() || c->cap_stream) (void)hipStreamSynchronize(c->stream);
+    for (GraphEntry& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     if (!c->ev_pool.empty()) {
         if (!c->pending.empty()) (void)hipStreamSynchronize(c->stream);
         for (auto e : c->ev_pool) (void)hipEventDestroy(e);

@@ -185,3 +185,12 @@ def test_batched_plan_keeps_problems_separate(orc):
         single = ccd.Context([probs[p]])
         assert c.info(p) == single.info(0)
     assert c.workspace_size() > 0
+
+
+def test_build_step_does_not_need_the_library():
+    """The build module imports without loading libccd.so (fresh checkouts)."""
+    import subprocess
+    import sys
+    code = ("import sys, paper_1611_06765_amd.build_lib as b; "
+            "assert 'paper_1611_06765_amd.ccd' not in sys.modules; print(b.LIB)")
+    subprocess.check_call([sys.executable, "-c", code], cwd=ROOT)
