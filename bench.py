@@ -10,7 +10,18 @@ value = CCD iterations per second, counting one iteration per solve per sweep
 durations come from HIP events recorded by the library on its own stream during
 a second, identical region.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+Beside the throughput line, wall time to convergence (|dE_n - dE_(n-1)| below
+CONV_TOL MeV) of the three other forms against the plain FP64 GPU path on the
+same GPU, each with its energy error against a tightly converged FP64 solve:
+  mixed_c3    N=66, n^2<=36, rho=0.16: FP32 or BF16 contractions, then FP64
+              refinement;
+  batched_c4  40 solves (N in {14,38,54,66} x 10 densities, seeded cutoffs
+              12..36) in one context with graph replay and tuned launch shapes,
+              against the same 40 solved one after another in plain FP64;
+  learned_c5  (when a trained warm-start network is given) held-out densities
+              at n^2<=36 started from the network against the MBPT2 start.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-forms]
 """
 import argparse
 import json
@@ -23,6 +34,9 @@ sys.path.insert(0, ROOT)
 
 DENSITIES = [round(0.02 * (k + 1), 2) for k in range(10)]
 N, NMAX2, MIXING = 66, 20, 0.5
+CONV_TOL = 1e-6          # MeV, box total: stop criterion of every timed solve
+REF_TOL = 1e-10          # MeV: the FP64 reference the errors are taken against
+C4_SEED = 20161121
 
 # MI355X published peaks
 PEAK_HBM_GBS = 8000.0
@@ -66,12 +80,103 @@ def cpu_baseline(budget_s=20.0):
                       f"in {el:.1f} s, OpenMP threads={threads}"}
 
 
+def _timed(fn):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = fn()
+    torch.cuda.synchronize()
+    return r, time.perf_counter() - t0
+
+
+def _rel(a, b):
+    return abs(a - b) / abs(b)
+
+
+def form_mixed_c3(ccd, stream):
+    """N=66, n^2<=36, rho=0.16: plain FP64 vs FP32 / BF16 contractions + FP64
+    refinement, wall time to CONV_TOL and error against the FP64 reference."""
+    prob = [ccd.problem(66, 36, 0.16)]
+    ref = ccd.Context(prob, stream=stream).bind()
+    ref.iterate(mixing=MIXING, tol=REF_TOL, max_iter=2000, check_every=16, graph=True)
+    e_ref = ref.energy()[2]
+    out = {"workload": "PNM N=66, n^2<=36 (1850 states), rho=0.16, mixing 0.5, MBPT2 start",
+           "conv_tol_mev": CONV_TOL, "e_corr_fp64_ref": e_ref}
+    runs = [("fp64", ccd.CCD_PREC_FP64, 0.0), ("fp32_refined", ccd.CCD_PREC_FP32, 1e-5),
+            ("bf16_refined", ccd.CCD_PREC_BF16, 1e-3)]
+    for name, prec, mtol in runs:
+        c = ccd.Context(prob, stream=stream).bind()
+        if prec != ccd.CCD_PREC_FP64:
+            c.autotune(prec, reps=3)
+        r, el = _timed(lambda: c.iterate(mixing=MIXING, tol=CONV_TOL, max_iter=2000, precision=prec,
+                                         mixed_tol=mtol, refine_sweeps=2, history=True))
+        h = r["history"][0]
+        n = int(r["sweeps"][0])
+        e = c.energy()[2]
+        out[name] = {"wall_s": el, "sweeps": n, "e_corr": e, "rel_err_vs_fp64": _rel(e, e_ref),
+                     "status": int(r["status"]), "mixed_tol_mev": mtol or None}
+        c.close()
+    f = out["fp64"]["wall_s"]
+    for name in ("fp32_refined", "bf16_refined"):
+        out[name]["speedup_vs_fp64"] = f / out[name]["wall_s"]
+    return out
+
+
+def c4_problems(ccd, seed=C4_SEED):
+    import numpy as np
+    cut = np.random.default_rng(seed).integers(12, 37, size=40)
+    probs = []
+    for a, n in enumerate([14, 38, 54, 66]):
+        for b, r in enumerate(DENSITIES):
+            probs.append(ccd.problem(n, int(cut[10 * a + b]), r))
+    return probs, [int(x) for x in cut]
+
+
+def form_batched_c4(ccd, stream):
+    """40 solves: sequential plain FP64 (one context each, solved one after
+    another) vs one batched context (FP64, and BF16 + FP64 refinement) with
+    graph replay and autotuned launch shapes."""
+    probs, cut = c4_problems(ccd)
+    ref = ccd.Context(probs, stream=stream).bind()
+    ref.iterate(mixing=MIXING, tol=REF_TOL, max_iter=4000, check_every=16, graph=True)
+    e_ref = [ref.energy(p)[2] for p in range(len(probs))]
+    ref.close()
+    singles = [ccd.Context([p], stream=stream).bind() for p in probs]
+
+    def seq():
+        return [s.iterate(mixing=MIXING, tol=CONV_TOL, max_iter=4000)["sweeps"][0] for s in singles]
+    sw, t_seq = _timed(seq)
+    e_seq = [s.energy()[2] for s in singles]
+    for s in singles:
+        s.close()
+    out = {"workload": "40 PNM solves, N in {14,38,54,66} x rho 0.02..0.20, n^2 cutoffs drawn from "
+                       f"numpy default_rng({C4_SEED}).integers(12, 37)", "seed": C4_SEED, "cutoffs": cut,
+           "conv_tol_mev": CONV_TOL,
+           "sequential_fp64": {"wall_s": t_seq, "sweeps_total": int(sum(sw)),
+                               "max_rel_err": max(_rel(a, b) for a, b in zip(e_seq, e_ref))}}
+    for name, prec, mtol in [("batched_fp64", ccd.CCD_PREC_FP64, 0.0),
+                             ("batched_bf16_refined", ccd.CCD_PREC_BF16, 1e-3)]:
+        c = ccd.Context(probs, stream=stream).bind()
+        tab, _ = c.autotune(prec, reps=3)
+        r, el = _timed(lambda: c.iterate(mixing=MIXING, tol=CONV_TOL, max_iter=4000, precision=prec,
+                                         mixed_tol=mtol, refine_sweeps=2, check_every=8, graph=True))
+        e = [c.energy(p)[2] for p in range(len(probs))]
+        out[name] = {"wall_s": el, "speedup_vs_sequential_fp64": t_seq / el,
+                     "sweeps_max": int(max(r["sweeps"])), "status": int(r["status"]),
+                     "max_rel_err": max(_rel(a, b) for a, b in zip(e, e_ref)),
+                     "tuning": [int(x) for x in tab]}
+        c.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the mixed / batched / learned wall-time comparisons")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -169,6 +274,10 @@ def main():
         "roofline": roof,
         "e_corr_last": energies,
     }
+    if not args.no_forms:
+        ctx.close()
+        out["mixed_c3"] = form_mixed_c3(ccd, stream.cuda_stream)
+        out["batched_c4"] = form_batched_c4(ccd, stream.cuda_stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
