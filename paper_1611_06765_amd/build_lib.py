@@ -2,8 +2,8 @@
 
     python -m paper_1611_06765_amd.build_lib
 
-Produces paper_1611_06765_amd/libccd.so from csrc/ccd_plan.cpp and
-csrc/ccd_device.hip.  Packed FP32 instructions are disabled for all device
+Produces paper_1611_06765_amd/libccd.so from csrc/ccd_plan.cpp,
+csrc/ccd_device.hip and csrc/ccd_mlp.hip.  Packed FP32 instructions are disabled for all device
 code.
 """
 import os
@@ -25,6 +25,7 @@ def build(verbose: bool = False) -> str:
            "-Wall", "-Wno-unused-function", *DEVICE_FLAGS,
            "-I", os.path.join(HERE, "..", "include"),
            os.path.join(CSRC, "ccd_plan.cpp"), os.path.join(CSRC, "ccd_device.hip"),
+           os.path.join(CSRC, "ccd_mlp.hip"),
            "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)

@@ -60,6 +60,13 @@ class ccd_info(C.Structure):
                 ("flops_ordered", C.c_double)]
 
 
+class ccd_adam_opts(C.Structure):
+    _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
+                ("batch", C.c_int32)]
+
+
+CCD_MLP_NPACK, CCD_MLP_NPARAM = 8, 17800
+
 _vp, _i32, _sz = C.c_void_p, C.c_int32, C.c_size_t
 _dp, _ip = C.POINTER(C.c_double), C.POINTER(C.c_int32)
 _SIGS = {
@@ -74,6 +81,13 @@ _SIGS = {
     "ccd_reset_amplitudes": (_i32, [_vp]),
     "ccd_export_maps": (_i32, [_vp, _i32, _i32, _ip, _sz, C.POINTER(_sz)]),
     "ccd_export_tables": (_i32, [_vp, _i32, _dp, _dp, _dp]),
+    "ccd_mlp_features": (_i32, [_vp, _i32, _vp, _vp]),
+    "ccd_mlp_forward": (_i32, [_vp, _vp, C.c_int64, _i32, _vp, _vp]),
+    "ccd_mlp_work_size": (_i32, [C.c_int64, C.POINTER(_sz)]),
+    "ccd_mlp_loss_grad": (_i32, [_vp, _vp, _vp, C.c_int64, _vp, _dp, _vp, _sz, _vp]),
+    "ccd_mlp_train": (_i32, [_vp, _vp, _vp, C.POINTER(C.c_int64), _vp, _vp, _vp, C.c_int64,
+                             C.POINTER(ccd_adam_opts), _vp, _sz, _dp, _vp]),
+    "ccd_warm_start": (_i32, [_vp, _vp, _i32, _ip]),
     "ccd_autotune": (_i32, [_vp, _i32, _i32, _dp]),
     "ccd_get_tuning": (_i32, [_vp, _ip, _i32]),
     "ccd_set_tuning": (_i32, [_vp, _ip, _i32]),
@@ -232,6 +246,28 @@ class Context:
         t = np.ascontiguousarray(table, dtype=np.int32)
         _check(_lib.ccd_set_tuning(self._h, t.ctypes.data_as(_ip), t.size), "ccd_set_tuning")
 
+    # ---- learned warm start ---------------------------------------------------
+    def mlp_features(self, p=0, targets=False):
+        """Packed features [n_amp, 8] (and targets y*) of problem p as float32
+        device tensors."""
+        import torch
+        n = self.info(p)["n_amplitudes"]
+        dev = self.workspace.device
+        feat = torch.empty((n, CCD_MLP_NPACK), dtype=torch.float32, device=dev)
+        tgt = torch.empty(n, dtype=torch.float32, device=dev) if targets else None
+        _check(_lib.ccd_mlp_features(self._h, p, _vp(feat.data_ptr()),
+                                     _vp(tgt.data_ptr()) if targets else None), "ccd_mlp_features")
+        return (feat, tgt) if targets else feat
+
+    def warm_start(self, params=None, precision=CCD_PREC_BF16):
+        """Network warm start of every problem (params: float32 device tensor of
+        CCD_MLP_NPARAM entries; None restores the MBPT2 start); returns per
+        problem whether the network's amplitudes were kept."""
+        used = np.zeros(self.n, dtype=np.int32)
+        ptr = None if params is None else _vp(params.data_ptr())
+        _check(_lib.ccd_warm_start(self._h, ptr, precision, used.ctypes.data_as(_ip)), "ccd_warm_start")
+        return used.astype(bool)
+
     def set_timing(self, on=True):
         _check(_lib.ccd_set_timing(self._h, int(on)), "ccd_set_timing")
 
@@ -242,6 +278,69 @@ class Context:
         _check(_lib.ccd_kernel_times(self._h, _dptr(ms), cnt.ctypes.data_as(C.POINTER(C.c_int64)),
                                      int(reset)), "ccd_kernel_times")
         return {_lib.ccd_kernel_name(f).decode(): (float(ms[f]), int(cnt[f])) for f in range(nf)}
+
+
+def _stream_of(t):
+    import torch
+    return _vp(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def mlp_forward(params, feat, precision=CCD_PREC_BF16):
+    """Network prediction y for packed features feat [n, 8] (device tensors)."""
+    import torch
+    n = feat.shape[0]
+    y = torch.empty(n, dtype=torch.float32, device=feat.device)
+    _check(_lib.ccd_mlp_forward(_vp(params.data_ptr()), _vp(feat.data_ptr()), n, precision,
+                                _vp(y.data_ptr()), _stream_of(feat)), "ccd_mlp_forward")
+    return y
+
+
+def _work(n, device):
+    import torch
+    nb = _sz()
+    _check(_lib.ccd_mlp_work_size(n, C.byref(nb)), "ccd_mlp_work_size")
+    w = torch.empty(nb.value + 256, dtype=torch.uint8, device=device)
+    ptr = (w.data_ptr() + 255) & ~255
+    return w, ptr, nb.value
+
+
+def mlp_loss_grad(params, feat, target):
+    """(loss, gradient tensor) of the mean squared error over all rows."""
+    import torch
+    n = feat.shape[0]
+    g = torch.empty(CCD_MLP_NPARAM, dtype=torch.float32, device=feat.device)
+    w, ptr, nb = _work(n, feat.device)
+    loss = C.c_double()
+    _check(_lib.ccd_mlp_loss_grad(_vp(params.data_ptr()), _vp(feat.data_ptr()), _vp(target.data_ptr()), n,
+                                  _vp(g.data_ptr()), C.byref(loss), _vp(ptr), nb, _stream_of(feat)),
+           "ccd_mlp_loss_grad")
+    del w
+    return loss.value, g
+
+
+class AdamState:
+    """Adam moments and step counter of one parameter tensor."""
+
+    def __init__(self, params):
+        import torch
+        self.m = torch.zeros_like(params)
+        self.v = torch.zeros_like(params)
+        self.step = C.c_int64(0)
+
+
+def mlp_train(params, state, feat, target, order, batch, lr, beta1=0.9, beta2=0.999, eps=1e-8, work=None):
+    """len(order) // batch Adam steps over minibatches order[s*batch:(s+1)*batch]
+    (int32 device tensor of row indices); returns the mean minibatch loss."""
+    o = ccd_adam_opts(lr, beta1, beta2, eps, batch)
+    if work is None:
+        work = _work(batch, feat.device)
+    _, ptr, nb = work
+    loss = C.c_double()
+    _check(_lib.ccd_mlp_train(_vp(params.data_ptr()), _vp(state.m.data_ptr()), _vp(state.v.data_ptr()),
+                              C.byref(state.step), _vp(feat.data_ptr()), _vp(target.data_ptr()),
+                              _vp(order.data_ptr()), order.shape[0], C.byref(o), _vp(ptr), nb, C.byref(loss),
+                              _stream_of(feat)), "ccd_mlp_train")
+    return loss.value
 
 
 def canonical_index(ctx: Context, p=0):

@@ -35,6 +35,8 @@
 #include <vector>
 
 #include "ccd_internal.h"
+#include "mlp_net.h"
+#include "../../include/ccd_mlp.h"
 
 using namespace ccd;
 
@@ -102,6 +104,7 @@ struct DevPtrs {
     const double* colE;      // per hole-pair column: eps_i + eps_j (per problem)
     const int32_t* pgrp;     // per problem: group
     const int32_t* pgi;      // per problem: index inside the group
+    const double* pscale;    // per problem: rho, 2 pi / L, L^3 / 1000 (network features)
     const Item* it_elem;     // elementwise items, all channels
     const Item* it_nsz0;     // elementwise items, S_z != 0 channels
     const Item* it_ladder;   // ladder items (S_z = 0)
@@ -179,7 +182,7 @@ __device__ __forceinline__ double block_sum256(double v, double* sh) {
 // --------------------------------------------------------------------------
 
 // <ab||ij>, t0 = <ab||ij> / eps_ij^ab (eq. ccdGuess), energy partials
-__global__ void __launch_bounds__(256) k_init(DevPtrs d, int cur) {
+__global__ void __launch_bounds__(256) k_init(DevPtrs d, int cur, int only) {
     __shared__ double sh[4];
     const int item = blockIdx.x;
     const Item it = d.it_elem[item];
@@ -188,6 +191,7 @@ __global__ void __launch_bounds__(256) k_init(DevPtrs d, int cur) {
     const int nel = c.nhh * c.npp;
     const int32_t* st = d.st + G.st_off;
     for (int g = 0; g < G.G; g++) {
+        if (only >= 0 && G.p0 + g != only) continue;
         const double* eps = d.eps + G.eps_base + g * G.ns;
         const double* lut = d.lut + G.lut_base + g * G.nlut;
         const int64_t E0 = G.t_base + g * G.n_amp + c.t_off;
@@ -241,6 +245,100 @@ __global__ void __launch_bounds__(256) k_energy_elem(DevPtrs d) {
     for (int x = threadIdx.x; x < n; x += 256) s += part[x];
     double e = block_sum256(s, sh);
     if (threadIdx.x == 0) { d.ecorr[p] = e; d.eprev[p] = e; }
+}
+
+// --------------------------------------------------------------------------
+// learned warm start: features and prediction of the amplitude network
+// --------------------------------------------------------------------------
+
+// packed features of canonical amplitude e of channel c, problem g of group G
+// (rho, |q|, |q'|, eps_i, eps_j, eps_a, eps_b scaled, v L^3 / 1000), and the
+// FP64 quantities of the decoding t = (v + y / s) / D
+__device__ __forceinline__ void amp_features(const DevPtrs& d, const DevChan& c, const DevGroup& G, int g, int e,
+                                             float* f, double& D, double& v, double& sc) {
+    const int r = e / c.nhh, col = e - r * c.nhh;
+    const int32_t ab = d.pp[c.pp_off + r], ij = d.hh[c.hh_off + col];
+    const int a = pa(ab), b = pb(ab), i = pa(ij), j = pb(ij);
+    const int32_t* st = d.st + G.st_off;
+    const int32_t sa = st[a], sb = st[b], si = st[i], sj = st[j];
+    const double* eps = d.eps + G.eps_base + g * G.ns;
+    const int slot = G.p0 + g;
+    const double rho = d.pscale[3 * slot], ku = d.pscale[3 * slot + 1];
+    sc = d.pscale[3 * slot + 2];
+    // twice the transfers, in units of 2 pi / L
+    const int qx = s_x(sa) - s_x(sb) - s_x(si) + s_x(sj), qy = s_y(sa) - s_y(sb) - s_y(si) + s_y(sj),
+              qz = s_z(sa) - s_z(sb) - s_z(si) + s_z(sj);
+    const int px = s_x(sb) - s_x(sa) - s_x(si) + s_x(sj), py = s_y(sb) - s_y(sa) - s_y(si) + s_y(sj),
+              pz = s_z(sb) - s_z(sa) - s_z(si) + s_z(sj);
+    v = d.vt[G.t_base + g * G.n_amp + c.t_off + e];
+    D = eps[i] + eps[j] - eps[a] - eps[b];
+    f[0] = (float)(rho / mlp::kRho0);
+    f[1] = (float)(0.5 * ku * sqrt((double)(qx * qx + qy * qy + qz * qz)));
+    f[2] = (float)(0.5 * ku * sqrt((double)(px * px + py * py + pz * pz)));
+    f[3] = (float)(eps[i] / mlp::kE0);
+    f[4] = (float)(eps[j] / mlp::kE0);
+    f[5] = (float)(eps[a] / mlp::kE0);
+    f[6] = (float)(eps[b] / mlp::kE0);
+    f[7] = (float)(v * sc);
+}
+
+// features (and targets y* = (t D - v) s of the current amplitudes) of one
+// problem, canonical order; one block per elementwise item of its group
+__global__ void __launch_bounds__(256) k_features(DevPtrs d, int cur, int gi, int g, float* feat, float* target) {
+    const DevGroup G = d.groups[gi];
+    const Item it = d.it_elem[G.elem_lo + blockIdx.x];
+    const DevChan c = d.chans[it.chan];
+    const int nel = c.nhh * c.npp;
+    for (int k = 0; k < kElemChunk / 256; k++) {
+        const int e = it.start + threadIdx.x + 256 * k;
+        if (e < nel && e < it.start + kElemChunk) {
+            float f[mlp::kPack];
+            double D, v, sc;
+            amp_features(d, c, G, g, e, f, D, v, sc);
+            const int64_t loc = c.t_off + e;
+            float4* o = (float4*)(feat + loc * mlp::kPack);
+            o[0] = make_float4(f[0], f[1], f[2], f[3]);
+            o[1] = make_float4(f[4], f[5], f[6], f[7]);
+            if (target) {
+                const double t = d.t[cur][G.t_base + g * G.n_amp + loc];
+                target[loc] = (float)((t * D - v) * sc);
+            }
+        }
+    }
+}
+
+// warm start of every problem: per (elementwise item, problem) the wave tiles
+// of four amplitudes go through the network (W2 staged once per block) and
+// the decoded amplitudes replace the current ones
+template <bool BF16>
+__global__ void __launch_bounds__(256) k_warm(DevPtrs d, int cur, const float* __restrict__ P, int n_items) {
+    extern __shared__ __attribute__((aligned(16))) char lds[];
+    const mlp::Lds s = mlp::lds_carve<BF16>(lds);
+    mlp::lds_load<BF16>(P, s, threadIdx.x, 256);
+    __syncthreads();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, kq = lane >> 4;
+    for (int bi = blockIdx.x; bi < n_items; bi += gridDim.x) {
+        const Item it = d.it_elem[bi];
+        const DevChan c = d.chans[it.chan];
+        const DevGroup G = d.groups[c.group];
+        const int nel = c.nhh * c.npp;
+        const int lim = min(nel, it.start + kElemChunk);
+        for (int g = 0; g < G.G; g++) {
+            for (int t = w; 4 * t + it.start < lim; t += 4) {
+                const int e = it.start + 4 * t + ((lane & 15) >> 2);
+                float f[mlp::kPack];
+                double D = 1.0, v = 0.0, sc = 1.0;
+                if (e < lim) amp_features(d, c, G, g, e, f, D, v, sc);
+                else
+#pragma unroll
+                    for (int q = 0; q < mlp::kPack; q++) f[q] = 0.f;
+                const float y = mlp::tile_predict<BF16>(f, s, lane);
+                // lane 20 kq: A-operand row 4 kq, i.e. amplitude kq of the tile, variant 0
+                if ((lane & 15) == 4 * kq && e < lim)
+                    d.t[cur][G.t_base + g * G.n_amp + c.t_off + e] = (v + (double)y / sc) / D;
+            }
+        }
+    }
 }
 
 // --------------------------------------------------------------------------
@@ -932,7 +1030,7 @@ struct ccd_ctx {
     std::vector<DevChan> dchans;
     std::vector<DevPh> dph;
     std::vector<int32_t> st, hh, pp, phmem, phmap, zidx, csr_ptr, csr_idx, pgrp, pgi, it_sz0;
-    std::vector<double> eps, lut, rowE, colE;
+    std::vector<double> eps, lut, rowE, colE, pscale;
     std::vector<Item> it_elem, it_nsz0, it_ladder, it_dchi, it_direct, it_ring_s, it_ring_b, it_lg, it_ng;
     int ring_lo[4] = {0}, ring_n[4] = {0};  // big pair items by padded size n16 = 32, 48, 64, 80
     int64_t NZP = 0;                         // ring-result entries, all problems
@@ -969,7 +1067,7 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
     X(dchans, DevChan) X(dph, DevPh) X(hh, int32_t) X(pp, int32_t)        \
     X(phmem, int32_t) X(phmap, int32_t) X(zidx, int32_t) X(rowE, double) X(colE, double) \
     X(csr_ptr, int32_t)                                                   \
-    X(csr_idx, int32_t) X(pgrp, int32_t) X(pgi, int32_t)                  \
+    X(csr_idx, int32_t) X(pgrp, int32_t) X(pgi, int32_t) X(pscale, double) \
     X(it_elem, Item) X(it_nsz0, Item) X(it_ladder, Item) X(it_sz0, int32_t) X(it_dchi, Item) \
     X(it_direct, Item) X(it_ring_s, Item) X(it_ring_b, Item) X(it_lg, Item) X(it_ng, Item)
 
@@ -983,6 +1081,7 @@ static DevPtrs make_ptrs(ccd_ctx* c) {
     const void* p_it_elem; const void* p_it_nsz0; const void* p_it_ladder; const void* p_it_sz0;
     const void* p_it_dchi; const void* p_it_direct; const void* p_it_ring_s; const void* p_it_ring_b;
     const void* p_it_lg; const void* p_it_ng; const void* p_zidx; const void* p_rowE; const void* p_colE;
+    const void* p_pscale;
 #define TAKE(name, T)             \
     p_##name = base + o;          \
     o += align256(c->name.size() * sizeof(T));
@@ -1000,6 +1099,7 @@ static DevPtrs make_ptrs(ccd_ctx* c) {
     d.it_ring_b = (const Item*)p_it_ring_b; d.it_lg = (const Item*)p_it_lg;
     d.it_ng = (const Item*)p_it_ng; d.zidx = (const int32_t*)p_zidx;
     d.rowE = (const double*)p_rowE; d.colE = (const double*)p_colE;
+    d.pscale = (const double*)p_pscale;
     d.t[0] = (double*)(base + c->r_t0.off);
     d.t[1] = (double*)(base + c->r_t1.off);
     d.vt = (double*)(base + c->r_vt.off);
@@ -1262,6 +1362,14 @@ static ccd_status assemble(ccd_ctx* c) {
     }
     c->pgrp = sg;
     c->pgi = sgi;
+    c->pscale.assign(3 * P, 0.0);
+    for (size_t p = 0; p < P; p++) {
+        const HostProblem& H = c->probs[p];
+        const int sl = c->slot_of[p];
+        c->pscale[3 * sl] = H.par.density;
+        c->pscale[3 * sl + 1] = 2.0 * M_PI / H.L;
+        c->pscale[3 * sl + 2] = H.L * H.L * H.L / mlp::kVScale;
+    }
     layout(c);
     return CCD_OK;
 }
@@ -1598,7 +1706,7 @@ ccd_status ccd_reset_amplitudes(ccd_ctx* c) {
     if (!c->bound) { set_error("no workspace bound"); return CCD_ESTATE; }
     c->cur = 0;
     DevPtrs d = make_ptrs(c);
-    LAUNCH(F_INIT, k_init, (int)c->it_elem.size(), 256, 0, d, 0);
+    LAUNCH(F_INIT, k_init, (int)c->it_elem.size(), 256, 0, d, 0, -1);
     LAUNCH(F_ENERGY, k_energy_elem, (int)c->probs.size(), 256, 0, d);
     return CCD_OK;
 }
@@ -1859,6 +1967,74 @@ ccd_status ccd_autotune(ccd_ctx* c, int32_t precision, int32_t reps, double* bes
     (void)hipEventDestroy(e1);
     c->timing = timing;
     return s;
+}
+
+ccd_status ccd_mlp_features(const ccd_ctx* cc, int32_t p, float* feat, float* target) {
+    ccd_ctx* c = const_cast<ccd_ctx*>(cc);
+    if (!c || !feat || p < 0 || p >= (int)c->probs.size()) {
+        set_error("ccd_mlp_features: bad argument");
+        return CCD_EINVAL;
+    }
+    if (!c->bound) { set_error("ccd_mlp_features: no workspace bound"); return CCD_ESTATE; }
+    if (((uintptr_t)feat) & 15) { set_error("ccd_mlp_features: feat must be 16-byte aligned"); return CCD_EINVAL; }
+    const int sl = c->slot_of[p];
+    const int gi = c->pgrp[sl], g = c->pgi[sl];
+    const DevGroup& G = c->dgroups[gi];
+    DevPtrs d = make_ptrs(c);
+    LAUNCH(F_INIT, k_features, G.elem_hi - G.elem_lo, 256, 0, d, c->cur, gi, g, feat, target);
+    return CCD_OK;
+}
+
+ccd_status ccd_warm_start(ccd_ctx* c, const float* params, int32_t precision, int32_t* used_net) {
+    if (!c) { set_error("ccd_warm_start: NULL context"); return CCD_EINVAL; }
+    if (!c->bound) { set_error("ccd_warm_start: no workspace bound"); return CCD_ESTATE; }
+    const int P = (int)c->probs.size();
+    if (!params) {
+        ccd_status s = ccd_reset_amplitudes(c);
+        if (s != CCD_OK) return s;
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        if (used_net) std::fill(used_net, used_net + P, 0);
+        return CCD_OK;
+    }
+    if (precision != CCD_PREC_FP32 && precision != CCD_PREC_BF16) {
+        set_error("ccd_warm_start: precision must be CCD_PREC_FP32 or CCD_PREC_BF16");
+        return CCD_EINVAL;
+    }
+    if (((uintptr_t)params) & 15) { set_error("ccd_warm_start: params must be 16-byte aligned"); return CCD_EINVAL; }
+    static bool attr = false;
+    if (!attr) {
+        HIP_TRY(hipFuncSetAttribute((const void*)k_warm<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)mlp::lds_bytes<false>()));
+        attr = true;
+    }
+    DevPtrs d = make_ptrs(c);
+    const int n = (int)c->it_elem.size();
+    const int grid = std::min(n, 2048);
+    if (precision == CCD_PREC_BF16)
+        LAUNCH(F_INIT, k_warm<true>, grid, 256, mlp::lds_bytes<true>(), d, c->cur, params, n);
+    else
+        LAUNCH(F_INIT, k_warm<false>, grid, 256, mlp::lds_bytes<false>(), d, c->cur, params, n);
+    ccd_status s = refresh_energy(c);
+    if (s != CCD_OK) return s;
+    std::vector<double> e(P);
+    HIP_TRY(hipMemcpyAsync(e.data(), c->ws + c->r_ecorr.off, P * 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    bool any = false;
+    for (int p = 0; p < P; p++) {
+        const double ew = e[c->slot_of[p]], r = ew / c->emp2[p];
+        const bool keep = std::isfinite(ew) && r >= 0.5 && r <= 2.0;
+        if (used_net) used_net[p] = keep ? 1 : 0;
+        if (!keep) {
+            LAUNCH(F_INIT, k_init, n, 256, 0, d, c->cur, c->slot_of[p]);
+            any = true;
+        }
+    }
+    if (any) {
+        s = refresh_energy(c);
+        if (s != CCD_OK) return s;
+        HIP_TRY(hipStreamSynchronize(c->stream));
+    }
+    return CCD_OK;
 }
 
 ccd_status ccd_get_tuning(const ccd_ctx* c, int32_t* dst, int32_t n) {

@@ -17,9 +17,12 @@ ccd = pytest.importorskip("paper_1611_06765_amd.ccd")
 
 
 def header_functions():
-    src = open(os.path.join(ROOT, "include", "ccd.h")).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(ccd_[a-z_0-9]+)\s*\(", src)))
+    names = set()
+    for h in ("ccd.h", "ccd_mlp.h"):
+        src = open(os.path.join(ROOT, "include", h)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names |= set(re.findall(r"\b(ccd_[a-z_0-9]+)\s*\(", src))
+    return sorted(names)
 
 
 def test_library_exports_every_declared_function():
