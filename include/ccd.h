@@ -81,8 +81,8 @@ typedef struct {
 
 typedef struct {
     double mixing;         /* alpha in (0, 1]: t <- alpha t_new + (1-alpha) t_old */
-    double tol;            /* stop when |dE_n - dE_(n-1)| < tol (MeV, box total);
-                              tol <= 0 runs exactly max_iter sweeps */
+    double tol;            /* stop when |dE_n - dE_(n-1)| < tol (MeV, box total),
+                              see also tol_rel */
     int32_t max_iter;      /* sweeps in this call (>= 1) */
     int32_t precision;     /* CCD_PREC_* for the sweeps of this call */
     int32_t refine_sweeps; /* mixed precision: after the mixed phase stops, at
@@ -100,6 +100,9 @@ typedef struct {
     int32_t use_graph;     /* nonzero: each chunk of sweeps is captured once as a
                               HIP graph and replayed (up to 4 captured shapes are
                               kept per context); ignored while kernel timing is on */
+    double tol_rel;        /* relative part of the stop test: a problem stops when
+                              |dE_n - dE_(n-1)| < tol + tol_rel |dE_n|; both <= 0
+                              run exactly max_iter sweeps */
 } ccd_solver_opts;
 
 typedef struct ccd_ctx ccd_ctx; /* opaque */
@@ -148,7 +151,7 @@ ccd_status ccd_bind_workspace(ccd_ctx* ctx, void* device_ptr, size_t bytes);
 
 /* Jacobi sweeps of eq. ccd3 in the intermediates form on the GPU (every term
  * from t^(n), linear mixing, energy of the mixed amplitudes), for all
- * problems of the context.  A problem whose |dE_n - dE_(n-1)| < tol stops
+ * problems of the context.  A problem whose |dE_n - dE_(n-1)| < tol + tol_rel |dE_n| stops
  * changing; the call returns when all problems have converged or after
  * max_iter sweeps.
  *   sweeps_done  host, n_problems entries (nullable): sweeps each problem ran in this call

@@ -978,7 +978,7 @@ __global__ void __launch_bounds__(256) k_update(DevPtrs d, int cur, double alpha
 }
 
 // per-problem energy after a sweep, convergence test, divergence flag
-__global__ void __launch_bounds__(256) k_energy(DevPtrs d, double tol) {
+__global__ void __launch_bounds__(256) k_energy(DevPtrs d, double tol, double tol_rel) {
     __shared__ double sh[4];
     const int p = blockIdx.x;
     const DevGroup G = d.groups[d.pgrp[p]];
@@ -994,7 +994,7 @@ __global__ void __launch_bounds__(256) k_energy(DevPtrs d, double tol) {
         d.ehist[(size_t)p * kHistCap + d.sweeps[p] % kHistCap] = e;
         d.sweeps[p] += 1;
         if (!isfinite(e)) d.active[p] = 0;
-        else if (tol > 0.0 && fabs(e - old) < tol) d.active[p] = 0;
+        else if ((tol > 0.0 || tol_rel > 0.0) && fabs(e - old) < tol + tol_rel * fabs(e)) d.active[p] = 0;
     }
 }
 
@@ -1013,11 +1013,11 @@ struct Region {
 struct GraphEntry {
     int prec, cur, n;
     uint32_t mask;
-    double alpha, tol;
+    double alpha, tol, tol_rel;
     int32_t tune[CCD_TUNE_LEN];
     hipGraphExec_t exec;
-    bool same(int p, int c0, int n0, uint32_t m, double a, double t, const int32_t* tu) const {
-        return prec == p && cur == c0 && n == n0 && mask == m && alpha == a && tol == t &&
+    bool same(int p, int c0, int n0, uint32_t m, double a, double t, double tr, const int32_t* tu) const {
+        return prec == p && cur == c0 && n == n0 && mask == m && alpha == a && tol == t && tol_rel == tr &&
                std::memcmp(tune, tu, sizeof(tune)) == 0;
     }
 };
@@ -1525,7 +1525,7 @@ static hipError_t set_ring_attrs() {
     return set_ring_attr_pair<P, 80, 16, 9>();
 }
 
-static ccd_status sweep(ccd_ctx* c, double alpha, double tol, uint32_t mask, int prec) {
+static ccd_status sweep(ccd_ctx* c, double alpha, double tol, double tol_rel, uint32_t mask, int prec) {
     DevPtrs d = make_ptrs(c);
     const int cur = c->cur;
     ccd_status s = prec == CCD_PREC_BF16 ? launch_contractions<P_BF16>(c, d, cur, alpha, mask)
@@ -1534,7 +1534,7 @@ static ccd_status sweep(ccd_ctx* c, double alpha, double tol, uint32_t mask, int
     if (s != CCD_OK) return s;
     s = L_update(c, d, cur, alpha, mask);
     if (s != CCD_OK) return s;
-    LAUNCH(F_ENERGY, k_energy, (int)c->probs.size(), 256, 0, d, tol);
+    LAUNCH(F_ENERGY, k_energy, (int)c->probs.size(), 256, 0, d, tol, tol_rel);
     c->cur ^= 1;
     return CCD_OK;
 }
@@ -1542,17 +1542,18 @@ static ccd_status sweep(ccd_ctx* c, double alpha, double tol, uint32_t mask, int
 // n sweeps: launched one by one, or (graph) as one replay of a captured graph
 // of the same n sweeps; kernel timing disables the graph
 static constexpr size_t kMaxGraphs = 4;
-static ccd_status run_sweeps(ccd_ctx* c, int n, double alpha, double tol, uint32_t mask, int prec, bool graph) {
+static ccd_status run_sweeps(ccd_ctx* c, int n, double alpha, double tol, double tol_rel, uint32_t mask, int prec,
+                             bool graph) {
     if (!graph || c->timing) {
         for (int k = 0; k < n; k++) {
-            ccd_status s = sweep(c, alpha, tol, mask, prec);
+            ccd_status s = sweep(c, alpha, tol, tol_rel, mask, prec);
             if (s != CCD_OK) return s;
         }
         return CCD_OK;
     }
     GraphEntry* ge = nullptr;
     for (GraphEntry& g : c->graphs)
-        if (g.same(prec, c->cur, n, mask, alpha, tol, c->tune)) ge = &g;
+        if (g.same(prec, c->cur, n, mask, alpha, tol, tol_rel, c->tune)) ge = &g;
     if (!ge) {
         // captured on a private stream (the caller's may be the null stream),
         // replayed on the caller's stream in order with its other work
@@ -1562,7 +1563,7 @@ static ccd_status run_sweeps(ccd_ctx* c, int n, double alpha, double tol, uint32
         HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
         c->stream = c->cap_stream;
         ccd_status s = CCD_OK;
-        for (int k = 0; k < n && s == CCD_OK; k++) s = sweep(c, alpha, tol, mask, prec);
+        for (int k = 0; k < n && s == CCD_OK; k++) s = sweep(c, alpha, tol, tol_rel, mask, prec);
         hipGraph_t gr = nullptr;
         const hipError_t ec = hipStreamEndCapture(c->cap_stream, &gr);
         c->stream = user;
@@ -1587,7 +1588,7 @@ static ccd_status run_sweeps(ccd_ctx* c, int n, double alpha, double tol, uint32
             c->graphs.erase(c->graphs.begin());
         }
         GraphEntry e;
-        e.prec = prec; e.cur = cur0; e.n = n; e.mask = mask; e.alpha = alpha; e.tol = tol;
+        e.prec = prec; e.cur = cur0; e.n = n; e.mask = mask; e.alpha = alpha; e.tol = tol; e.tol_rel = tol_rel;
         std::memcpy(e.tune, c->tune, sizeof(e.tune));
         e.exec = ex;
         c->graphs.push_back(e);
@@ -1739,12 +1740,13 @@ ccd_status ccd_bind_workspace(ccd_ctx* c, void* ptr, size_t bytes) {
 // check_every (graph replays when asked); after each chunk the host reads the
 // per-problem sweep counters, active flags and the device energy history.
 // min_sweeps: sweeps run before the convergence test may stop a problem.
-static ccd_status run_phase(ccd_ctx* c, const ccd_solver_opts* o, int prec, double tol_phase, int budget,
-                            int min_sweeps, double* e_hist, int& used) {
+static ccd_status run_phase(ccd_ctx* c, const ccd_solver_opts* o, int prec, double tol_phase, double rel_phase,
+                            int budget, int min_sweeps, double* e_hist, int& used) {
     const int P = (int)c->probs.size();
     std::vector<int32_t> ones(P, 1);
     HIP_TRY(hipMemcpyAsync(c->ws + c->r_active.off, ones.data(), P * 4, hipMemcpyHostToDevice, c->stream));
-    const bool check = tol_phase > 0.0 || e_hist;
+    const bool stops = tol_phase > 0.0 || rel_phase > 0.0;
+    const bool check = stops || e_hist;
     const int every = check ? std::max(1, std::min(o->check_every > 0 ? o->check_every : 1, kHistCap)) : kHistCap;
     const bool graph = o->use_graph != 0;
     std::vector<int32_t> sw(P, 0), sw0(P, 0), act(P, 1);
@@ -1757,15 +1759,16 @@ static ccd_status run_phase(ccd_ctx* c, const ccd_solver_opts* o, int prec, doub
     used = 0;
     while (used < budget && !all_done) {
         int n;
-        double tol;
+        double tol, rel;
         if (used + 1 < min_sweeps) {
             n = std::min(std::min(min_sweeps - 1 - used, budget - used), every);
-            tol = 0.0;
+            tol = rel = 0.0;
         } else {
             n = std::min(every, budget - used);
             tol = tol_phase;
+            rel = rel_phase;
         }
-        ccd_status st = run_sweeps(c, n, o->mixing, tol, o->terms, prec, graph);
+        ccd_status st = run_sweeps(c, n, o->mixing, tol, rel, o->terms, prec, graph);
         if (st != CCD_OK) return st;
         used += n;
         if (check) {
@@ -1776,7 +1779,7 @@ static ccd_status run_phase(ccd_ctx* c, const ccd_solver_opts* o, int prec, doub
                 HIP_TRY(hipMemcpyAsync(hb.data(), c->ws + c->r_ehist.off, hb.size() * 8, hipMemcpyDeviceToHost,
                                        c->stream));
             HIP_TRY(hipStreamSynchronize(c->stream));
-            all_done = tol_phase > 0.0;
+            all_done = stops;
             for (int p = 0; p < P; p++) {
                 const int sl = c->slot_of[p];
                 if (e_hist)
@@ -1811,14 +1814,15 @@ ccd_status ccd_iterate(ccd_ctx* c, const ccd_solver_opts* o, int32_t* sweeps_don
         for (size_t k = 0; k < (size_t)P * o->max_iter; k++) e_hist[k] = NAN;
     int used = 0;
     const bool mixed = o->precision != CCD_PREC_FP64;
-    const double tol1 = mixed && o->mixed_tol > 0.0 ? o->mixed_tol : o->tol;
-    ccd_status st = run_phase(c, o, o->precision, tol1, o->max_iter, 1, e_hist, used);
+    const bool own = mixed && o->mixed_tol > 0.0;  // the mixed phase has its own (absolute) criterion
+    ccd_status st = run_phase(c, o, o->precision, own ? o->mixed_tol : o->tol, own ? 0.0 : o->tol_rel, o->max_iter,
+                              1, e_hist, used);
     if (st != CCD_OK) return st;
     if (mixed && used < o->max_iter) {
         // FP64 refinement: continue the FP64 iteration from the mixed-precision iterate
         int used2 = 0;
-        st = run_phase(c, o, CCD_PREC_FP64, o->tol, o->max_iter - used, std::max(1, o->refine_sweeps), e_hist,
-                       used2);
+        st = run_phase(c, o, CCD_PREC_FP64, o->tol, o->tol_rel, o->max_iter - used, std::max(1, o->refine_sweeps),
+                       e_hist, used2);
         if (st != CCD_OK) return st;
     }
     std::vector<int32_t> sw(P), act(P);
@@ -1834,7 +1838,7 @@ ccd_status ccd_iterate(ccd_ctx* c, const ccd_solver_opts* o, int32_t* sweeps_don
             set_error("problem " + std::to_string(p) + ": correlation energy is not finite");
             return CCD_DIVERGED;
         }
-    if (o->tol > 0.0)
+    if (o->tol > 0.0 || o->tol_rel > 0.0)
         for (int p = 0; p < P; p++)
             if (act[c->slot_of[p]]) return CCD_NOT_CONVERGED;
     return CCD_OK;
