@@ -36,7 +36,7 @@ sys.path.insert(0, ROOT)
 
 DENSITIES = [round(0.02 * (k + 1), 2) for k in range(10)]
 N, NMAX2, MIXING = 66, 20, 0.5
-CONV_REL = 1e-7          # relative stop criterion of every timed solve
+CONV_REL = 2e-8          # relative stop criterion of every timed solve
 REF_TOL = 1e-10          # MeV: the FP64 reference the errors are taken against
 C4_SEED = 20161121
 

@@ -110,7 +110,9 @@ struct DevPtrs {
     const Item* it_ladder;   // ladder items (S_z = 0)
     const int32_t* it_sz0;   // S_z = 0 channel ids
     const Item* it_dchi;     // (group, first state)
-    const Item* it_direct;   // (S_z = 0 channel, problem in group)
+    const Item* it_dsub;     // (S_z = 0 channel, first row) of the chi_klij product items
+    const Item* it_direct;   // (product item, problem in group)
+    const Item* it_dsum;     // (S_z = 0 channel, problem in group)
     const Item* it_ring_s;   // (primary cross channel with n <= 16, problem in group)
     const Item* it_ring_b;   // (primary cross channel with n > 16, problem in group)
     const Item* it_lg;       // (ladder item, problem in group)
@@ -118,6 +120,8 @@ struct DevPtrs {
     double* t[2];
     double* vt;              // <ab||ij>
     double* chh;
+    double* dpart;           // partial chi_klij per product item
+    double* dcolp;           // partial column sums per product item
     double* rowsum;
     double* colsum;
     double* dchi;
@@ -345,26 +349,30 @@ __global__ void __launch_bounds__(256) k_warm(DevPtrs d, int cur, const float* _
 // sweep kernels
 // --------------------------------------------------------------------------
 
-// per (S_z = 0 channel, problem): row sums of t v, chi_klij (its quadratic
-// part on FP64 MFMA over LDS-staged row chunks) and the column sums, which are
-// the diagonal of that product.  Wave w owns output tiles w, w+4, ...
+// per (item of kDirSplit particle-pair rows of an S_z = 0 channel, problem):
+// row sums of t v, the item's part of 1/2 sum_cd <kl||cd> t_ij^cd on MFMA over
+// LDS-staged 32-row chunks, and its part of the column sums (the diagonal of
+// that product in FP64; summed in FP64 from memory in the mixed modes).
+// k_dsum adds the parts in a fixed order.  Wave w owns output tiles w, w+4, ...
 constexpr int kDirRows = 32;
 template <int P>
 __global__ void __launch_bounds__(256) k_direct(DevPtrs d, int cur, uint32_t mask, int n_items) {
     using E = typename std::conditional<P == P_F64, double, float>::type;
     using AT = typename std::conditional<P == P_F64, d4, f4>::type;
     constexpr int PM = P == P_F64 ? P_F64 : P_F32;   // contraction precision used here
-    __shared__ E vs[kDirRows][kMaxHH + 1];
+    __shared__ __attribute__((aligned(16))) E vs[kDirRows][kMaxHH + 1];
     __shared__ E ts[kDirRows][kMaxHH + 1];
     for (int bi = blockIdx.x; bi < n_items; bi += gridDim.x) {
     const Item it = d.it_direct[bi];
     if (it.chan < 0) continue;
-    const DevChan c = d.chans[it.chan];
+    const Item sub = d.it_dsub[it.chan];
+    const DevChan c = d.chans[sub.chan];
     const DevGroup G = d.groups[c.group];
     const int g = it.start;
     if (!d.active[G.p0 + g]) continue;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int nhh = c.nhh, npp = c.npp, nt = (nhh + 15) >> 4;
+    const int k0 = sub.start, k1 = min(npp, k0 + kDirSplit), si = it.chan - c.dsub_lo;
     const int64_t E0 = G.t_base + g * G.n_amp + c.t_off;
     const double* t = d.t[cur] + E0;
     const double* vt = d.vt + E0;
@@ -373,8 +381,9 @@ __global__ void __launch_bounds__(256) k_direct(DevPtrs d, int cur, uint32_t mas
     AT acc[4];
 #pragma unroll
     for (int k = 0; k < 4; k++) acc[k] = AT{0, 0, 0, 0};
-    for (int r0 = 0; r0 < npp; r0 += kDirRows) {
-        const int rc = min(kDirRows, npp - r0);
+    double cpart = 0.0;  // mixed modes: this thread's share of a column sum
+    for (int r0 = k0; r0 < k1; r0 += kDirRows) {
+        const int rc = min(kDirRows, k1 - r0);
         __syncthreads();
         for (int e = threadIdx.x; e < kDirRows * nhh; e += 256) {
             int r = e / nhh, j = e - r * nhh;
@@ -387,6 +396,12 @@ __global__ void __launch_bounds__(256) k_direct(DevPtrs d, int cur, uint32_t mas
             int r = e / (nt * 16 - nhh), j = nhh + e % (nt * 16 - nhh);
             vs[r][j] = (E)0;
             ts[r][j] = (E)0;
+        }
+        if constexpr (P != P_F64) {
+            const int j = threadIdx.x & 63;
+            if ((mask & CCD_T_QHOLE) && j < nhh)
+                for (int r = threadIdx.x >> 6; r < rc; r += 4)
+                    cpart += t[(int64_t)(r0 + r) * nhh + j] * vt[(int64_t)(r0 + r) * nhh + j];
         }
         __syncthreads();
         // row sums of t v (one-body particle terms), FP64 in every mode: from
@@ -413,6 +428,7 @@ __global__ void __launch_bounds__(256) k_direct(DevPtrs d, int cur, uint32_t mas
                 const int tile = w + 4 * k;
                 if (tile < nt * nt) {
                     const int ti = tile / nt, tj = tile - ti * nt;
+#pragma unroll
                     for (int kk = 0; kk < kDirRows; kk += 4) {
                         E av = vs[kk + (lane >> 4)][ti * 16 + (lane & 15)];
                         E bv = ts[kk + (lane >> 4)][tj * 16 + (lane & 15)];
@@ -423,39 +439,75 @@ __global__ void __launch_bounds__(256) k_direct(DevPtrs d, int cur, uint32_t mas
             }
         }
     }
-    double* chh = d.chh + G.chh_base + g * G.n_chh + c.chh_off;
-    double* cols = d.colsum + G.cols_base + g * G.n_cols + c.col_off;
-    const double* lut = d.lut + G.lut_base + g * G.nlut;
-    const int32_t* st = d.st + G.st_off;
+    double* part = d.dpart + G.dpart_base + (int64_t)g * G.n_dpart + c.dpart_off + (int64_t)si * nhh * nhh;
+    double* colp = d.dcolp + G.dcolp_base + (int64_t)g * G.n_dcolp + c.dcolp_off + (int64_t)si * nhh;
+    if (quad) {
 #pragma unroll
-    for (int k = 0; k < 4; k++) {
-        const int tile = w + 4 * k;
-        if (tile < nt * nt) {
-            const int ti = tile / nt, tj = tile - ti * nt;
+        for (int k = 0; k < 4; k++) {
+            const int tile = w + 4 * k;
+            if (tile < nt * nt) {
+                const int ti = tile / nt, tj = tile - ti * nt;
 #pragma unroll
-            for (int q = 0; q < 4; q++) {
-                int kl = ti * 16 + orow<PM>(lane, q), ij = tj * 16 + (lane & 15);
-                if (kl < nhh && ij < nhh) {
-                    double qv = (double)acc[k][q];
-                    if (kl == ij && P == P_F64) cols[kl] = qv;
-                    double v = 0.0;
-                    if (mask & CCD_T_HH) {
-                        int32_t p1 = d.hh[c.hh_off + kl], p2 = d.hh[c.hh_off + ij];
-                        v = vas(lut, st[pa(p1)], st[pb(p1)], st[pa(p2)], st[pb(p2)]);
+                for (int q = 0; q < 4; q++) {
+                    int kl = ti * 16 + orow<PM>(lane, q), ij = tj * 16 + (lane & 15);
+                    if (kl < nhh && ij < nhh) {
+                        const double qv = (double)acc[k][q];
+                        part[kl * nhh + ij] = qv;
+                        if (P == P_F64 && kl == ij) colp[kl] = qv;
                     }
-                    chh[kl * nhh + ij] = v + ((mask & CCD_T_QHH) ? qv : 0.0);
                 }
             }
         }
     }
-    // column sums (hole one-body terms) in FP64 for the mixed modes
     if constexpr (P != P_F64) {
-        if ((mask & CCD_T_QHOLE) && threadIdx.x < nhh) {
-            double sum = 0.0;
-            for (int r = 0; r < npp; r++) sum += t[(int64_t)r * nhh + threadIdx.x] * vt[(int64_t)r * nhh + threadIdx.x];
-            cols[threadIdx.x] = sum;
+        if (mask & CCD_T_QHOLE) {
+            double* red = (double*)&vs[0][0];  // 4 x 64 doubles
+            __syncthreads();
+            red[threadIdx.x] = cpart;
+            __syncthreads();
+            if (threadIdx.x < nhh)
+                colp[threadIdx.x] = (red[threadIdx.x] + red[64 + threadIdx.x]) + (red[128 + threadIdx.x] + red[192 + threadIdx.x]);
         }
     }
+    }
+}
+
+// per (S_z = 0 channel, problem): chi_klij = <kl||ij> + sum of the product
+// items' parts, and the column sums, in item order
+__global__ void __launch_bounds__(256) k_dsum(DevPtrs d, uint32_t mask, int n_items) {
+    for (int bi = blockIdx.x; bi < n_items; bi += gridDim.x) {
+        const Item it = d.it_dsum[bi];
+        if (it.chan < 0) continue;
+        const DevChan c = d.chans[it.chan];
+        const DevGroup G = d.groups[c.group];
+        const int g = it.start;
+        if (!d.active[G.p0 + g]) continue;
+        const int nhh = c.nhh, nsub = c.dsub_n;
+        const double* part = d.dpart + G.dpart_base + (int64_t)g * G.n_dpart + c.dpart_off;
+        const double* colp = d.dcolp + G.dcolp_base + (int64_t)g * G.n_dcolp + c.dcolp_off;
+        double* chh = d.chh + G.chh_base + g * G.n_chh + c.chh_off;
+        double* cols = d.colsum + G.cols_base + g * G.n_cols + c.col_off;
+        const double* lut = d.lut + G.lut_base + g * G.nlut;
+        const int32_t* st = d.st + G.st_off;
+        for (int e = threadIdx.x; e < nhh * nhh; e += 256) {
+            const int kl = e / nhh, ij = e - kl * nhh;
+            double v = 0.0;
+            if (mask & CCD_T_HH) {
+                const int32_t p1 = d.hh[c.hh_off + kl], p2 = d.hh[c.hh_off + ij];
+                v = vas(lut, st[pa(p1)], st[pb(p1)], st[pa(p2)], st[pb(p2)]);
+            }
+            if (mask & CCD_T_QHH) {
+                double q = 0.0;
+                for (int s = 0; s < nsub; s++) q += part[(int64_t)s * nhh * nhh + e];
+                v += q;
+            }
+            chh[e] = v;
+        }
+        if ((mask & CCD_T_QHOLE) && threadIdx.x < nhh) {
+            double q = 0.0;
+            for (int s = 0; s < nsub; s++) q += colp[s * nhh + threadIdx.x];
+            cols[threadIdx.x] = q;
+        }
     }
 }
 
@@ -804,8 +856,8 @@ __global__ void __launch_bounds__(256) k_ladder(DevPtrs d, int cur, double alpha
     __shared__ ET lutS[kMaxLut];
     // t chunk: [k][16] for FP64 / FP32, transposed [16][k] for BF16
     __shared__ __attribute__((aligned(16))) char tks[P == P_F64 ? kKP * 16 * 8 : (P == P_F32 ? kKP * 16 * 4 : 16 * (kKP + 8) * 2)];
-    __shared__ int32_t cvec[kKP];
-    __shared__ int32_t cinfo[kKP];
+    // per staged column cd: (n_c packed as int8 x, y, z, 0; |n_c|^2 | |n_d|^2 << 10 | spin(c) << 20)
+    __shared__ int2 cvi[kKP];
     __shared__ double sh[4];
     for (int bi = blockIdx.x; bi < n_items; bi += gridDim.x) {
     const Item lg = d.it_lg[bi];
@@ -827,30 +879,39 @@ __global__ void __launch_bounds__(256) k_ladder(DevPtrs d, int cur, double alpha
     __syncthreads();  // the previous item's reads of lutS are done
     for (int e = threadIdx.x; e < G.nlut; e += 256) lutS[e] = (ET)d.lut[G.lut_base + g * G.nlut + e];
 
-    // generator row of this lane (A-operand row = lane % 16)
+    // generator row a of this lane (A-operand row = lane % 16); rows past the
+    // channel get a = 0, whose generated values are never stored
     const int ra = it.start + 16 * w + (lane & 15);
     const bool rav = ra < npp;
-    int ax = 0, ay = 0, az = 0, A2 = 0, AK = 0, sa = 0;
+    int32_t apack = 0;
+    int A2 = 0, AK = 0, sa = 0;
     if (rav) {
-        int32_t s1 = st[pa(d.pp[c.pp_off + ra])];
-        ax = s_x(s1); ay = s_y(s1); az = s_z(s1); sa = s_s(s1) > 0 ? 1 : 0;
+        const int32_t s1 = st[pa(d.pp[c.pp_off + ra])];
+        const int ax = s_x(s1), ay = s_y(s1), az = s_z(s1);
+        apack = s1 & 0x00ffffff;
+        sa = s_s(s1) > 0 ? 1 : 0;
         A2 = ax * ax + ay * ay + az * az;
         AK = A2 - 2 * (ax * c.kx + ay * c.ky + az * c.kz);
     }
-    // <ab||cd> for chunk column k (generator row fixed per lane)
+    // <ab||cd> for staged column k: with d = K - c and b = K - a,
+    //   |n_a - n_c|^2 = A2 + |n_c|^2 - 2 a.c,  |n_a - n_d|^2 = A2 - 2 a.K + |n_d|^2 + 2 a.c.
+    // Padding columns carry c = K, |n_d|^2 = 0: both indices stay inside the
+    // table (|n_b|^2 and A2) and their t rows are zero.
     auto gen = [&](int k) -> ET {
-        const int32_t vec = cvec[k], inf = cinfo[k];
-        const int ac = ax * s_x(vec) + ay * s_y(vec) + az * s_z(vec);
-        const bool valid = rav && ((inf >> 21) & 1);
-        const int m1 = valid ? A2 + (inf & 1023) - 2 * ac : 0;
-        const int m2 = valid ? AK + ((inf >> 10) & 1023) + 2 * ac : 0;
-        ET v = lutS[m1] + lutS[m2];
-        return valid ? ((((inf >> 20) & 1) == sa) ? v : -v) : (ET)0;
+        const int2 ci = cvi[k];
+        const int ac = __builtin_amdgcn_sdot4(apack, ci.x, 0, false);
+        const int m1 = A2 + (ci.y & 1023) - 2 * ac;
+        const int m2 = AK + ((ci.y >> 10) & 1023) + 2 * ac;
+        const ET v = lutS[m1] + lutS[m2];
+        return (((ci.y >> 20) & 1) == sa) ? v : -v;
     };
+    const int32_t kpack = (int32_t)((uint32_t)(uint8_t)(int8_t)c.kx | ((uint32_t)(uint8_t)(int8_t)c.ky << 8) |
+                                    ((uint32_t)(uint8_t)(int8_t)c.kz << 16));
+    const int K2 = c.kx * c.kx + c.ky * c.ky + c.kz * c.kz;
     double es = 0.0;
     for (int ct = 0; ct < nct; ct++) {
         const int col = ct * 16 + (lane & 15);
-        AT acc = {0, 0, 0, 0};
+        AT acc = {0, 0, 0, 0}, acc2 = {0, 0, 0, 0};
         if (pp_on) {
             for (int kp = 0; kp < npp; kp += kKP) {
                 const int kn = min(kKP, npp - kp);
@@ -863,18 +924,17 @@ __global__ void __launch_bounds__(256) k_ladder(DevPtrs d, int cur, double alpha
                     else ((__bf16*)tks)[jj * (kKP + 8) + kk] = (__bf16)v;
                 }
                 for (int kk = threadIdx.x; kk < kKP; kk += 256) {
-                    int32_t vec = 0, inf = 0;
+                    int2 ci = make_int2(kpack, K2);
                     if (kk < kn) {
-                        int32_t cd = d.pp[c.pp_off + kp + kk];
-                        int32_t sc = st[pa(cd)], sd = st[pb(cd)];
-                        int cx = s_x(sc), cy = s_y(sc), cz = s_z(sc);
-                        int dx = s_x(sd), dy = s_y(sd), dz = s_z(sd);
-                        vec = sc & 0x00ffffff;
-                        inf = (cx * cx + cy * cy + cz * cz) | ((dx * dx + dy * dy + dz * dz) << 10) |
-                              ((s_s(sc) > 0 ? 1 : 0) << 20) | (1 << 21);
+                        const int32_t cd = d.pp[c.pp_off + kp + kk];
+                        const int32_t sc = st[pa(cd)], sd = st[pb(cd)];
+                        const int cx = s_x(sc), cy = s_y(sc), cz = s_z(sc);
+                        const int dx = s_x(sd), dy = s_y(sd), dz = s_z(sd);
+                        ci.x = sc & 0x00ffffff;
+                        ci.y = (cx * cx + cy * cy + cz * cz) | ((dx * dx + dy * dy + dz * dz) << 10) |
+                               ((s_s(sc) > 0 ? 1 : 0) << 20);
                     }
-                    cvec[kk] = vec;
-                    cinfo[kk] = inf;
+                    cvi[kk] = ci;
                 }
                 __syncthreads();
                 if constexpr (P == P_BF16) {
@@ -888,27 +948,49 @@ __global__ void __launch_bounds__(256) k_ladder(DevPtrs d, int cur, double alpha
                         acc = mfmabf(av, bv, acc);
                     }
                 } else {
-                    const int ksteps = (kn + 3) & ~3;
-#pragma unroll 4
-                    for (int kk = 0; kk < ksteps; kk += 4) {
-                        const int k = kk + (lane >> 4);
-                        const ET v = gen(k);
-                        if constexpr (P == P_F64) acc = mfma64(v, ((const double*)tks)[k * 16 + (lane & 15)], acc);
-                        else acc = mfma32(v, ((const float*)tks)[k * 16 + (lane & 15)], acc);
+                    // eight MFMA steps per batch: all operands are produced first
+                    const int ksteps = (kn + 31) & ~31;
+                    for (int kk = 0; kk < ksteps; kk += 32) {
+                        ET va[8], vb[8];
+#pragma unroll
+                        for (int s = 0; s < 8; s++) {
+                            const int k = kk + 4 * s + (lane >> 4);
+                            va[s] = gen(k);
+                            vb[s] = ((const ET*)tks)[k * 16 + (lane & 15)];
+                        }
+#pragma unroll
+                        for (int s = 0; s < 8; s += 2) {
+                            if constexpr (P == P_F64) {
+                                acc = mfma64(va[s], vb[s], acc);
+                                acc2 = mfma64(va[s + 1], vb[s + 1], acc2);
+                            } else {
+                                acc = mfma32(va[s], vb[s], acc);
+                                acc2 = mfma32(va[s + 1], vb[s + 1], acc2);
+                            }
+                        }
                     }
                 }
             }
         }
         if (hh_on) {
             const double* xg = d.chh + G.chh_base + g * G.n_chh + c.chh_off;
-            for (int k0 = 0; k0 < nhh; k0 += 4) {
-                const int kq = k0 + (lane >> 4);
-                double a = (rav && kq < nhh) ? tcur[(int64_t)ra * nhh + kq] : 0.0;
-                double b = (kq < nhh && col < nhh) ? xg[kq * nhh + col] : 0.0;
-                if constexpr (P == P_F64) acc = mfma64(a, b, acc);
-                else acc = mfma32((float)a, (float)b, acc);
+            for (int k0 = 0; k0 < nhh; k0 += 16) {
+                double a[4], b[4];
+#pragma unroll
+                for (int s = 0; s < 4; s++) {
+                    const int kq = k0 + 4 * s + (lane >> 4);
+                    a[s] = (rav && kq < nhh) ? tcur[(int64_t)ra * nhh + kq] : 0.0;
+                    b[s] = (kq < nhh && col < nhh) ? xg[kq * nhh + col] : 0.0;
+                }
+#pragma unroll
+                for (int s = 0; s < 4; s++) {
+                    if constexpr (P == P_F64) acc = mfma64(a[s], b[s], acc);
+                    else acc = mfma32((float)a[s], (float)b[s], acc);
+                }
             }
         }
+#pragma unroll
+        for (int r = 0; r < 4; r++) acc[r] += acc2[r];
         // epilogue (FP64): this lane owns rows orow(lane, r) of the wave's 16 rows, column col
         const double* rowE = d.rowE + G.rowa_base + g * G.n_rows_all + c.rowa_off;
         const double* rowX = d.rowX + G.rowa_base + g * G.n_rows_all + c.rowa_off;
@@ -1031,7 +1113,9 @@ struct ccd_ctx {
     std::vector<DevPh> dph;
     std::vector<int32_t> st, hh, pp, phmem, phmap, zidx, csr_ptr, csr_idx, pgrp, pgi, it_sz0;
     std::vector<double> eps, lut, rowE, colE, pscale;
-    std::vector<Item> it_elem, it_nsz0, it_ladder, it_dchi, it_direct, it_ring_s, it_ring_b, it_lg, it_ng;
+    std::vector<Item> it_elem, it_nsz0, it_ladder, it_dchi, it_direct, it_ring_s, it_ring_b, it_lg, it_ng, it_dsub,
+        it_dsum;
+    int64_t n_dpart = 0, n_dcolp = 0;
     int ring_lo[4] = {0}, ring_n[4] = {0};  // big pair items by padded size n16 = 32, 48, 64, 80
     int64_t NZP = 0;                         // ring-result entries, all problems
     std::vector<int64_t> prob_t0;  // amplitude index of each problem (caller order)
@@ -1040,7 +1124,7 @@ struct ccd_ctx {
     int n_rows = 0, n_cols = 0, n_chh = 0, n_eps = 0, n_epart = 0, n_eparte = 0, max_ph = 0;
     // workspace
     Region r_static, r_t0, r_t1, r_vt, r_chh, r_rows, r_cols, r_dchi, r_zp, r_rowx, r_colx, r_epart, r_eparte,
-        r_ecorr, r_eprev, r_active, r_sweeps, r_ehist;
+        r_ecorr, r_eprev, r_active, r_sweeps, r_ehist, r_dpart, r_dcolp;
     size_t ws_bytes = 0;
     char* ws = nullptr;
     bool bound = false;
@@ -1069,7 +1153,8 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
     X(csr_ptr, int32_t)                                                   \
     X(csr_idx, int32_t) X(pgrp, int32_t) X(pgi, int32_t) X(pscale, double) \
     X(it_elem, Item) X(it_nsz0, Item) X(it_ladder, Item) X(it_sz0, int32_t) X(it_dchi, Item) \
-    X(it_direct, Item) X(it_ring_s, Item) X(it_ring_b, Item) X(it_lg, Item) X(it_ng, Item)
+    X(it_direct, Item) X(it_ring_s, Item) X(it_ring_b, Item) X(it_lg, Item) X(it_ng, Item) \
+    X(it_dsub, Item) X(it_dsum, Item)
 
 static DevPtrs make_ptrs(ccd_ctx* c) {
     DevPtrs d;
@@ -1081,7 +1166,7 @@ static DevPtrs make_ptrs(ccd_ctx* c) {
     const void* p_it_elem; const void* p_it_nsz0; const void* p_it_ladder; const void* p_it_sz0;
     const void* p_it_dchi; const void* p_it_direct; const void* p_it_ring_s; const void* p_it_ring_b;
     const void* p_it_lg; const void* p_it_ng; const void* p_zidx; const void* p_rowE; const void* p_colE;
-    const void* p_pscale;
+    const void* p_pscale; const void* p_it_dsub; const void* p_it_dsum;
 #define TAKE(name, T)             \
     p_##name = base + o;          \
     o += align256(c->name.size() * sizeof(T));
@@ -1100,6 +1185,9 @@ static DevPtrs make_ptrs(ccd_ctx* c) {
     d.it_ng = (const Item*)p_it_ng; d.zidx = (const int32_t*)p_zidx;
     d.rowE = (const double*)p_rowE; d.colE = (const double*)p_colE;
     d.pscale = (const double*)p_pscale;
+    d.it_dsub = (const Item*)p_it_dsub; d.it_dsum = (const Item*)p_it_dsum;
+    d.dpart = (double*)(base + c->r_dpart.off);
+    d.dcolp = (double*)(base + c->r_dcolp.off);
     d.t[0] = (double*)(base + c->r_t0.off);
     d.t[1] = (double*)(base + c->r_t1.off);
     d.vt = (double*)(base + c->r_vt.off);
@@ -1149,6 +1237,8 @@ static void layout(ccd_ctx* c) {
     region(c->r_t1, c->NT * 8);
     region(c->r_vt, c->NT * 8);
     region(c->r_chh, (size_t)c->n_chh * 8);
+    region(c->r_dpart, (size_t)c->n_dpart * 8);
+    region(c->r_dcolp, (size_t)c->n_dcolp * 8);
     region(c->r_rows, (size_t)c->n_rows * 8);
     region(c->r_cols, (size_t)c->n_cols * 8);
     region(c->r_dchi, (size_t)c->n_eps * 8);
@@ -1194,7 +1284,7 @@ static ccd_status assemble(ccd_ctx* c) {
     c->pgi.assign(P, 0);
     c->prob_t0.assign(P, 0);
     c->slot_of.assign(P, 0);
-    std::vector<std::pair<int, Item>> lg, ng, dir, rs, rb[4];
+    std::vector<std::pair<int, Item>> lg, ng, dir, dsum, rs, rb[4];
     int64_t t_base = 0, zp_base = 0;
     int gi = 0, slot0 = 0;
     for (auto& kv : by_structure) {
@@ -1225,7 +1315,7 @@ static ccd_status assemble(ccd_ctx* c) {
         const int hh0 = (int)c->hh.size(), pp0 = (int)c->pp.size();
         for (size_t k = 0; k < H.hh.size() / 2; k++) c->hh.push_back(pack_pair(H.hh[2 * k], H.hh[2 * k + 1]));
         for (size_t k = 0; k < H.pp.size() / 2; k++) c->pp.push_back(pack_pair(H.pp[2 * k], H.pp[2 * k + 1]));
-        int rows = 0, cols = 0, chh = 0;
+        int rows = 0, cols = 0, chh = 0, dpart = 0, dcolp = 0;
         std::vector<std::vector<int32_t>> lists(H.ns);
         D.ladder_lo = (int)c->it_ladder.size();
         D.elem_lo = (int)c->it_elem.size();
@@ -1256,7 +1346,18 @@ static ccd_status assemble(ccd_ctx* c) {
                 }
                 rows += h.npp; cols += h.nhh;
                 c->it_sz0.push_back(id);
-                for (int g = 0; g < D.G; g++) dir.push_back({slot0 + g, Item{id, g}});
+                dc.dsub_lo = (int)c->it_dsub.size();
+                dc.dpart_off = dpart;
+                dc.dcolp_off = dcolp;
+                for (int k0 = 0; k0 < h.npp; k0 += kDirSplit) {
+                    const int si = (int)c->it_dsub.size();
+                    c->it_dsub.push_back({id, k0});
+                    for (int g = 0; g < D.G; g++) dir.push_back({slot0 + g, Item{si, g}});
+                    dpart += h.nhh * h.nhh;
+                    dcolp += h.nhh;
+                }
+                dc.dsub_n = (int)c->it_dsub.size() - dc.dsub_lo;
+                for (int g = 0; g < D.G; g++) dsum.push_back({slot0 + g, Item{id, g}});
                 for (int r0 = 0; r0 < h.npp; r0 += kLadderRows) {
                     const int li = (int)c->it_ladder.size();
                     c->it_ladder.push_back({id, r0});
@@ -1277,6 +1378,9 @@ static ccd_status assemble(ccd_ctx* c) {
         D.ladder_hi = (int)c->it_ladder.size();
         D.elem_hi = (int)c->it_elem.size();
         D.n_rows = rows; D.n_cols = cols; D.n_chh = chh;
+        D.n_dpart = dpart; D.n_dcolp = dcolp;
+        D.dpart_base = c->n_dpart; D.dcolp_base = c->n_dcolp;
+        c->n_dpart += (int64_t)D.G * dpart; c->n_dcolp += (int64_t)D.G * dcolp;
         D.rows_base = c->n_rows; D.cols_base = c->n_cols; D.chh_base = c->n_chh;
         c->n_rows += D.G * rows; c->n_cols += D.G * cols; c->n_chh += D.G * chh;
         D.epart_base = c->n_epart;
@@ -1346,6 +1450,7 @@ static ccd_status assemble(ccd_ctx* c) {
     c->it_lg = xcd_order(lg);
     c->it_ng = xcd_order(ng);
     c->it_direct = xcd_order(dir);
+    c->it_dsum = xcd_order(dsum);
     c->it_ring_s = xcd_order(rs, 4);
     c->it_ring_b.clear();
     for (int k = 0; k < 4; k++) {
@@ -1435,9 +1540,11 @@ static int grid_for(const ccd_ctx* c, int slot, int nb) {
 
 template <int P>
 static ccd_status L_direct(ccd_ctx* c, const DevPtrs& d, int cur, uint32_t mask) {
-    const int n = (int)c->it_direct.size();
-    if (mask & (CCD_T_HH | CCD_T_QHH | CCD_T_QHOLE | CCD_T_QPART))
+    const int n = (int)c->it_direct.size(), ns = (int)c->it_dsum.size();
+    if (mask & (CCD_T_QHH | CCD_T_QHOLE | CCD_T_QPART))
         LAUNCH(F_DIRECT, k_direct<P>, grid_for(c, CCD_TUNE_DIRECT, n), 256, 0, d, cur, mask, n);
+    if (mask & (CCD_T_HH | CCD_T_QHH | CCD_T_QHOLE))
+        LAUNCH(F_DIRECT, k_dsum, ns, 256, 0, d, mask, ns);
     return CCD_OK;
 }
 

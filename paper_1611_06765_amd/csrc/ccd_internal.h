@@ -16,6 +16,7 @@ constexpr int kMaxHH = 64;        // hole pairs of one direct channel (ladder ti
 constexpr int kMaxPH = 80;        // pairs of one particle-hole channel (2 N^2 doubles in LDS)
 constexpr int kLadderRows = 64;   // particle-pair rows per ladder work item
 constexpr int kElemChunk = 1024;  // amplitudes per elementwise work item
+constexpr int kDirSplit = 128;    // particle-pair rows per work item of the chi_klij product
 constexpr int kMaxNmax2 = 64;     // cutoff limit: W(m) tables of 4 nmax2 + 1 entries live in LDS
 constexpr int kMaxLut = 4 * kMaxNmax2 + 1;
 
@@ -55,6 +56,8 @@ struct DevGroup {
     int32_t elem_lo, elem_hi;       // elementwise items of the group
     int32_t eelem_base;   // elementwise energy partial of (item, g)
     int32_t csr_off;      // one-body CSR row pointers of the group: csr_off + s
+    int32_t n_dpart, n_dcolp;       // partial chi_klij / column sums per problem
+    int64_t dpart_base, dcolp_base; // + g * n_dpart / n_dcolp
 };
 
 struct DevChan {
@@ -68,6 +71,8 @@ struct DevChan {
     int32_t col_off;      // local column id of column 0 (S_z = 0)
     int32_t kx, ky, kz;   // total momentum
     int32_t rowa_off, cola_off;     // first row / column of the block among all rows / columns
+    int32_t dsub_lo, dsub_n;        // S_z = 0: items of kDirSplit rows of the chi_klij product
+    int32_t dpart_off, dcolp_off;   // S_z = 0: local offsets of their partial sums
 };
 
 struct DevPh {

@@ -125,7 +125,7 @@ __device__ __forceinline__ float tile_predict(const float* f, const Lds& s, int 
     for (int ct = 0; ct < 8; ct++) acc[ct] = f4v{0.f, 0.f, 0.f, 0.f};
     if constexpr (BF16) {
         const __bf16* W2 = (const __bf16*)s.W2;
-#pragma unroll
+#pragma unroll 1
         for (int st = 0; st < 4; st++) {
             bf8v a;
 #pragma unroll
