@@ -95,6 +95,7 @@ struct DevPtrs {
     const DevPh* ph;
     const int32_t* hh;       // packed pairs (per structure)
     const int32_t* pp;
+    const int2* ppinfo;      // per particle pair (c, d): (n_c as int8 x, y, z, 0; |n_c|^2 | |n_d|^2 << 10 | spin(c) << 20)
     const int32_t* phmem;
     const int32_t* phmap;
     const int32_t* csr_ptr;
@@ -848,9 +849,9 @@ __global__ void __launch_bounds__(256) k_onebody(DevPtrs d) {
 // so the K loop has no barrier.  Then the hh ladder (MFMA), the ring term,
 // one-body terms, t_new = R / eps_ij^ab, mixing and the energy partial sum, all
 // in FP64.  P selects the precision of the two ladder contractions.
-constexpr int kKP = 256;  // particle-pair columns staged per barrier
+constexpr int kKP = 128;  // particle-pair columns staged per barrier
 template <int P>
-__global__ void __launch_bounds__(256) k_ladder(DevPtrs d, int cur, double alpha, uint32_t mask, int n_items) {
+__global__ void __launch_bounds__(256, 3) k_ladder(DevPtrs d, int cur, double alpha, uint32_t mask, int n_items) {
     using ET = typename AccT<P>::E;   // element type of the generated operand
     using AT = typename AccT<P>::T;   // accumulator
     __shared__ ET lutS[kMaxLut];
@@ -883,15 +884,17 @@ __global__ void __launch_bounds__(256) k_ladder(DevPtrs d, int cur, double alpha
     // channel get a = 0, whose generated values are never stored
     const int ra = it.start + 16 * w + (lane & 15);
     const bool rav = ra < npp;
+    const int32_t kpack = (int32_t)((uint32_t)(uint8_t)(int8_t)c.kx | ((uint32_t)(uint8_t)(int8_t)c.ky << 8) |
+                                    ((uint32_t)(uint8_t)(int8_t)c.kz << 16));
+    const int K2 = c.kx * c.kx + c.ky * c.ky + c.kz * c.kz;
     int32_t apack = 0;
     int A2 = 0, AK = 0, sa = 0;
     if (rav) {
-        const int32_t s1 = st[pa(d.pp[c.pp_off + ra])];
-        const int ax = s_x(s1), ay = s_y(s1), az = s_z(s1);
-        apack = s1 & 0x00ffffff;
-        sa = s_s(s1) > 0 ? 1 : 0;
-        A2 = ax * ax + ay * ay + az * az;
-        AK = A2 - 2 * (ax * c.kx + ay * c.ky + az * c.kz);
+        const int2 ri = d.ppinfo[c.pp_off + ra];
+        apack = ri.x;
+        sa = (ri.y >> 20) & 1;
+        A2 = ri.y & 1023;
+        AK = A2 - 2 * __builtin_amdgcn_sdot4(apack, kpack, 0, false);
     }
     // <ab||cd> for staged column k: with d = K - c and b = K - a,
     //   |n_a - n_c|^2 = A2 + |n_c|^2 - 2 a.c,  |n_a - n_d|^2 = A2 - 2 a.K + |n_d|^2 + 2 a.c.
@@ -905,38 +908,44 @@ __global__ void __launch_bounds__(256) k_ladder(DevPtrs d, int cur, double alpha
         const ET v = lutS[m1] + lutS[m2];
         return (((ci.y >> 20) & 1) == sa) ? v : -v;
     };
-    const int32_t kpack = (int32_t)((uint32_t)(uint8_t)(int8_t)c.kx | ((uint32_t)(uint8_t)(int8_t)c.ky << 8) |
-                                    ((uint32_t)(uint8_t)(int8_t)c.kz << 16));
-    const int K2 = c.kx * c.kx + c.ky * c.ky + c.kz * c.kz;
+    // one staged chunk: t rows kp .. kp + kKP - 1 of column tile ct (zero past
+    // the channel) and the column descriptors; loaded into registers one chunk
+    // ahead of the MFMA work on the previous one
+    constexpr int kPer = kKP * 16 / 256;
+    double tv[kPer];
+    int2 cv = make_int2(kpack, K2);
+    auto load_chunk = [&](int ct, int kp) {
+        const int kn = min(kKP, npp - kp);
+#pragma unroll
+        for (int i = 0; i < kPer; i++) {
+            const int e = threadIdx.x + 256 * i, kk = e >> 4, cc = ct * 16 + (e & 15);
+            tv[i] = (kk < kn && cc < nhh) ? tcur[(int64_t)(kp + kk) * nhh + cc] : 0.0;
+        }
+        cv = make_int2(kpack, K2);
+        if (threadIdx.x < kn) cv = d.ppinfo[c.pp_off + kp + threadIdx.x];
+    };
+    auto store_chunk = [&]() {
+#pragma unroll
+        for (int i = 0; i < kPer; i++) {
+            const int e = threadIdx.x + 256 * i, kk = e >> 4, jj = e & 15;
+            if constexpr (P == P_F64) ((double*)tks)[kk * 16 + jj] = tv[i];
+            else if constexpr (P == P_F32) ((float*)tks)[kk * 16 + jj] = (float)tv[i];
+            else ((__bf16*)tks)[jj * (kKP + 8) + kk] = (__bf16)tv[i];
+        }
+        if (threadIdx.x < kKP) cvi[threadIdx.x] = cv;
+    };
     double es = 0.0;
     for (int ct = 0; ct < nct; ct++) {
         const int col = ct * 16 + (lane & 15);
         AT acc = {0, 0, 0, 0}, acc2 = {0, 0, 0, 0};
         if (pp_on) {
+            load_chunk(ct, 0);
             for (int kp = 0; kp < npp; kp += kKP) {
                 const int kn = min(kKP, npp - kp);
                 __syncthreads();
-                for (int e = threadIdx.x; e < kKP * 16; e += 256) {
-                    const int kk = e >> 4, jj = e & 15, cc = ct * 16 + jj;
-                    const double v = (kk < kn && cc < nhh) ? tcur[(int64_t)(kp + kk) * nhh + cc] : 0.0;
-                    if constexpr (P == P_F64) ((double*)tks)[kk * 16 + jj] = v;
-                    else if constexpr (P == P_F32) ((float*)tks)[kk * 16 + jj] = (float)v;
-                    else ((__bf16*)tks)[jj * (kKP + 8) + kk] = (__bf16)v;
-                }
-                for (int kk = threadIdx.x; kk < kKP; kk += 256) {
-                    int2 ci = make_int2(kpack, K2);
-                    if (kk < kn) {
-                        const int32_t cd = d.pp[c.pp_off + kp + kk];
-                        const int32_t sc = st[pa(cd)], sd = st[pb(cd)];
-                        const int cx = s_x(sc), cy = s_y(sc), cz = s_z(sc);
-                        const int dx = s_x(sd), dy = s_y(sd), dz = s_z(sd);
-                        ci.x = sc & 0x00ffffff;
-                        ci.y = (cx * cx + cy * cy + cz * cz) | ((dx * dx + dy * dy + dz * dz) << 10) |
-                               ((s_s(sc) > 0 ? 1 : 0) << 20);
-                    }
-                    cvi[kk] = ci;
-                }
+                store_chunk();
                 __syncthreads();
+                if (kp + kKP < npp) load_chunk(ct, kp + kKP);
                 if constexpr (P == P_BF16) {
                     const int ksteps = (kn + 31) & ~31;
                     for (int kk = 0; kk < ksteps; kk += 32) {
@@ -1111,6 +1120,7 @@ struct ccd_ctx {
     std::vector<DevGroup> dgroups;
     std::vector<DevChan> dchans;
     std::vector<DevPh> dph;
+    std::vector<int32_t> ppinfo;
     std::vector<int32_t> st, hh, pp, phmem, phmap, zidx, csr_ptr, csr_idx, pgrp, pgi, it_sz0;
     std::vector<double> eps, lut, rowE, colE, pscale;
     std::vector<Item> it_elem, it_nsz0, it_ladder, it_dchi, it_direct, it_ring_s, it_ring_b, it_lg, it_ng, it_dsub,
@@ -1154,7 +1164,7 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
     X(csr_idx, int32_t) X(pgrp, int32_t) X(pgi, int32_t) X(pscale, double) \
     X(it_elem, Item) X(it_nsz0, Item) X(it_ladder, Item) X(it_sz0, int32_t) X(it_dchi, Item) \
     X(it_direct, Item) X(it_ring_s, Item) X(it_ring_b, Item) X(it_lg, Item) X(it_ng, Item) \
-    X(it_dsub, Item) X(it_dsum, Item)
+    X(it_dsub, Item) X(it_dsum, Item) X(ppinfo, int32_t)
 
 static DevPtrs make_ptrs(ccd_ctx* c) {
     DevPtrs d;
@@ -1166,7 +1176,7 @@ static DevPtrs make_ptrs(ccd_ctx* c) {
     const void* p_it_elem; const void* p_it_nsz0; const void* p_it_ladder; const void* p_it_sz0;
     const void* p_it_dchi; const void* p_it_direct; const void* p_it_ring_s; const void* p_it_ring_b;
     const void* p_it_lg; const void* p_it_ng; const void* p_zidx; const void* p_rowE; const void* p_colE;
-    const void* p_pscale; const void* p_it_dsub; const void* p_it_dsum;
+    const void* p_pscale; const void* p_it_dsub; const void* p_it_dsum; const void* p_ppinfo;
 #define TAKE(name, T)             \
     p_##name = base + o;          \
     o += align256(c->name.size() * sizeof(T));
@@ -1186,6 +1196,7 @@ static DevPtrs make_ptrs(ccd_ctx* c) {
     d.rowE = (const double*)p_rowE; d.colE = (const double*)p_colE;
     d.pscale = (const double*)p_pscale;
     d.it_dsub = (const Item*)p_it_dsub; d.it_dsum = (const Item*)p_it_dsum;
+    d.ppinfo = (const int2*)p_ppinfo;
     d.dpart = (double*)(base + c->r_dpart.off);
     d.dcolp = (double*)(base + c->r_dcolp.off);
     d.t[0] = (double*)(base + c->r_t0.off);
@@ -1314,7 +1325,14 @@ static ccd_status assemble(ccd_ctx* c) {
         // direct channels
         const int hh0 = (int)c->hh.size(), pp0 = (int)c->pp.size();
         for (size_t k = 0; k < H.hh.size() / 2; k++) c->hh.push_back(pack_pair(H.hh[2 * k], H.hh[2 * k + 1]));
-        for (size_t k = 0; k < H.pp.size() / 2; k++) c->pp.push_back(pack_pair(H.pp[2 * k], H.pp[2 * k + 1]));
+        for (size_t k = 0; k < H.pp.size() / 2; k++) {
+            const int a = H.pp[2 * k], b = H.pp[2 * k + 1];
+            c->pp.push_back(pack_pair(a, b));
+            const int A2 = H.nx[a] * H.nx[a] + H.ny[a] * H.ny[a] + H.nz[a] * H.nz[a];
+            const int B2 = H.nx[b] * H.nx[b] + H.ny[b] * H.ny[b] + H.nz[b] * H.nz[b];
+            c->ppinfo.push_back(pack_state(H.nx[a], H.ny[a], H.nz[a], 0));
+            c->ppinfo.push_back(A2 | (B2 << 10) | ((H.sz[a] > 0 ? 1 : 0) << 20));
+        }
         int rows = 0, cols = 0, chh = 0, dpart = 0, dcolp = 0;
         std::vector<std::vector<int32_t>> lists(H.ns);
         D.ladder_lo = (int)c->it_ladder.size();
