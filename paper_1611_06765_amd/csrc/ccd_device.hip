@@ -842,13 +842,13 @@ __global__ void __launch_bounds__(256) k_onebody(DevPtrs d) {
     }
 }
 
-// fused S_z = 0 update per (64-row tile of a channel, problem).  Wave w owns
-// rows 16w .. 16w+15 and one 16-column tile of hole pairs at a time.  The pp
-// ladder runs on MFMA with <ab||cd> generated per lane in the A-operand layout
-// from W(m) in LDS; up to 256 particle-pair rows of t are staged per barrier,
-// so the K loop has no barrier.  Then the hh ladder (MFMA), the ring term,
-// one-body terms, t_new = R / eps_ij^ab, mixing and the energy partial sum, all
-// in FP64.  P selects the precision of the two ladder contractions.
+// fused S_z = 0 update per (64-row tile, 16-column tile of a channel, problem).
+// Wave w owns rows 16w .. 16w+15 of the tile.  The pp ladder runs on MFMA with
+// <ab||cd> generated per lane in the A-operand layout from W(m) in LDS, over
+// chunks of kKP particle-pair rows of t staged through registers one chunk
+// ahead.  Then the hh ladder (MFMA), the ring term, one-body terms,
+// t_new = R / eps_ij^ab, mixing and the energy partial sum, all in FP64.  P
+// selects the precision of the two ladder contractions.
 constexpr int kKP = 128;  // particle-pair columns staged per barrier
 template <int P>
 __global__ void __launch_bounds__(256, 3) k_ladder(DevPtrs d, int cur, double alpha, uint32_t mask, int n_items) {
@@ -865,11 +865,11 @@ __global__ void __launch_bounds__(256, 3) k_ladder(DevPtrs d, int cur, double al
     if (lg.chan < 0) continue;
     const int litem = lg.chan, g = lg.start;
     const Item it = d.it_ladder[litem];
+    const int r0 = it.start & 0xfffff, ct0 = it.start >> 20;  // row tile and column tile of the item
     const DevChan c = d.chans[it.chan];
     const DevGroup G = d.groups[c.group];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int nhh = c.nhh, npp = c.npp, nct = (nhh + 15) >> 4;
-    const int32_t* st = d.st + G.st_off;
+    const int nhh = c.nhh, npp = c.npp;
     const bool act = d.active[G.p0 + g] != 0;
     const bool pp_on = act && (mask & CCD_T_PP) != 0;
     const bool hh_on = act && (mask & (CCD_T_HH | CCD_T_QHH)) != 0;
@@ -882,7 +882,7 @@ __global__ void __launch_bounds__(256, 3) k_ladder(DevPtrs d, int cur, double al
 
     // generator row a of this lane (A-operand row = lane % 16); rows past the
     // channel get a = 0, whose generated values are never stored
-    const int ra = it.start + 16 * w + (lane & 15);
+    const int ra = r0 + 16 * w + (lane & 15);
     const bool rav = ra < npp;
     const int32_t kpack = (int32_t)((uint32_t)(uint8_t)(int8_t)c.kx | ((uint32_t)(uint8_t)(int8_t)c.ky << 8) |
                                     ((uint32_t)(uint8_t)(int8_t)c.kz << 16));
@@ -935,7 +935,7 @@ __global__ void __launch_bounds__(256, 3) k_ladder(DevPtrs d, int cur, double al
         if (threadIdx.x < kKP) cvi[threadIdx.x] = cv;
     };
     double es = 0.0;
-    for (int ct = 0; ct < nct; ct++) {
+    for (int ct = ct0; ct < ct0 + 1; ct++) {
         const int col = ct * 16 + (lane & 15);
         AT acc = {0, 0, 0, 0}, acc2 = {0, 0, 0, 0};
         if (pp_on) {
@@ -1010,7 +1010,7 @@ __global__ void __launch_bounds__(256, 3) k_ladder(DevPtrs d, int cur, double al
         }
 #pragma unroll
         for (int r = 0; r < 4; r++) {
-            const int row = it.start + 16 * w + orow<P>(lane, r);
+            const int row = r0 + 16 * w + orow<P>(lane, r);
             if (row < npp && col < nhh) {
                 const int64_t e = (int64_t)row * nhh + col;
                 const double tc = tcur[e], v = d.vt[T0 + e];
@@ -1285,6 +1285,33 @@ static std::vector<Item> xcd_order(std::vector<std::pair<int, Item>> v, int u = 
     return out;
 }
 
+// The same for items of uneven cost: the eight pieces are cut at equal shares
+// of the total cost (still contiguous in problem order), and inside a piece the
+// costliest items come first, so long items do not start last.
+static std::vector<Item> xcd_order_cost(const std::vector<std::pair<int, Item>>& v, const std::vector<double>& cost) {
+    std::vector<size_t> idx(v.size());
+    for (size_t k = 0; k < idx.size(); k++) idx[k] = k;
+    std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return v[a].first < v[b].first; });
+    double total = 0.0;
+    for (double x : cost) total += x;
+    std::vector<std::vector<size_t>> piece(8);
+    double run = 0.0;
+    for (size_t k : idx) {
+        const int x = total > 0.0 ? std::min(7, (int)(8.0 * run / total)) : 0;
+        piece[x].push_back(k);
+        run += cost[k];
+    }
+    size_t per = 0;
+    for (auto& pc : piece) {
+        std::stable_sort(pc.begin(), pc.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
+        per = std::max(per, pc.size());
+    }
+    std::vector<Item> out(per * 8, Item{-1, 0});
+    for (int x = 0; x < 8; x++)
+        for (size_t j = 0; j < piece[x].size(); j++) out[j * 8 + x] = v[piece[x][j]].second;
+    return out;
+}
+
 // group the problems by structure and lay out the device tables
 static ccd_status assemble(ccd_ctx* c) {
     std::map<std::pair<int, int>, std::vector<int>> by_structure;
@@ -1296,6 +1323,7 @@ static ccd_status assemble(ccd_ctx* c) {
     c->prob_t0.assign(P, 0);
     c->slot_of.assign(P, 0);
     std::vector<std::pair<int, Item>> lg, ng, dir, dsum, rs, rb[4];
+    std::vector<double> lg_cost;
     int64_t t_base = 0, zp_base = 0;
     int gi = 0, slot0 = 0;
     for (auto& kv : by_structure) {
@@ -1376,11 +1404,15 @@ static ccd_status assemble(ccd_ctx* c) {
                 }
                 dc.dsub_n = (int)c->it_dsub.size() - dc.dsub_lo;
                 for (int g = 0; g < D.G; g++) dsum.push_back({slot0 + g, Item{id, g}});
-                for (int r0 = 0; r0 < h.npp; r0 += kLadderRows) {
-                    const int li = (int)c->it_ladder.size();
-                    c->it_ladder.push_back({id, r0});
-                    for (int g = 0; g < D.G; g++) lg.push_back({slot0 + g, Item{li, g}});
-                }
+                for (int r0 = 0; r0 < h.npp; r0 += kLadderRows)
+                    for (int ct = 0; ct < (h.nhh + 15) / 16; ct++) {
+                        const int li = (int)c->it_ladder.size();
+                        c->it_ladder.push_back({id, r0 | (ct << 20)});
+                        for (int g = 0; g < D.G; g++) {
+                            lg.push_back({slot0 + g, Item{li, g}});
+                            lg_cost.push_back((double)h.npp);  // MFMA steps of the item
+                        }
+                    }
             }
             const int nel = h.nhh * h.npp;
             for (int e0 = 0; e0 < nel; e0 += kElemChunk) {
@@ -1465,7 +1497,7 @@ static ccd_status assemble(ccd_ctx* c) {
     c->NT = t_base;
     c->NZP = zp_base;
     if (c->csr_idx.empty()) c->csr_idx.push_back(0);
-    c->it_lg = xcd_order(lg);
+    c->it_lg = xcd_order_cost(lg, lg_cost);
     c->it_ng = xcd_order(ng);
     c->it_direct = xcd_order(dir);
     c->it_dsum = xcd_order(dsum);
