@@ -1151,6 +1151,11 @@ struct ccd_ctx {
     int32_t tune[CCD_TUNE_LEN] = {0};
     // replayable sweep graphs
     hipStream_t cap_stream = nullptr;
+    // three more streams for the ring size buckets, forked from and joined back
+    // into the caller's stream with events (default priority)
+    hipStream_t aux[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t ev_fork = nullptr, ev_join[3] = {nullptr, nullptr, nullptr};
+    bool aux_ok = false;
     std::vector<GraphEntry> graphs;
 };
 
@@ -1654,12 +1659,52 @@ static ccd_status L_update(ccd_ctx* c, const DevPtrs& d, int cur, double alpha, 
     return CCD_OK;
 }
 
+// launches made while it lives go to stream `to` instead of the context's stream
+struct StreamSwap {
+    ccd_ctx* c;
+    hipStream_t saved;
+    StreamSwap(ccd_ctx* cc, hipStream_t to) : c(cc), saved(cc->stream) { c->stream = to; }
+    ~StreamSwap() { c->stream = saved; }
+};
+
+// The ring reads only t[cur] and static tables, and writes only the pair
+// blocks, so its size buckets run on the three auxiliary streams beside the
+// chi_klij product and the one-body terms; the ladder, which reads all of
+// them, waits for the join.  With kernel timing on, everything stays on the
+// context's stream so that the per-family event times are not overlapped.
 template <int P>
 static ccd_status launch_contractions(ccd_ctx* c, const DevPtrs& d, int cur, double alpha, uint32_t mask) {
-    ccd_status s = L_direct<P>(c, d, cur, mask);
-    if (s == CCD_OK) s = L_dchi(c, d, mask);
-    if (s == CCD_OK) s = L_ring_small<P>(c, d, cur, mask);
-    if (s == CCD_OK) s = L_ring<P>(c, d, cur, mask);
+    const bool fork = c->aux_ok && !c->timing && (mask & (CCD_T_RING | CCD_T_QRING)) != 0;
+    ccd_status s = CCD_OK;
+    if (fork) {
+        HIP_TRY(hipEventRecord(c->ev_fork, c->stream));
+        for (int k = 0; k < 3; k++) HIP_TRY(hipStreamWaitEvent(c->aux[k], c->ev_fork, 0));
+        {
+            StreamSwap sw(c, c->aux[0]);
+            s = L_ring<P>(c, d, cur, mask, 2);
+            if (s == CCD_OK) s = L_ring<P>(c, d, cur, mask, 3);
+        }
+        if (s == CCD_OK) {
+            StreamSwap sw(c, c->aux[1]);
+            s = L_ring<P>(c, d, cur, mask, 1);
+            if (s == CCD_OK) s = L_ring<P>(c, d, cur, mask, 0);
+        }
+        if (s == CCD_OK) {
+            StreamSwap sw(c, c->aux[2]);
+            s = L_ring_small<P>(c, d, cur, mask);
+        }
+        if (s == CCD_OK) s = L_direct<P>(c, d, cur, mask);
+        if (s == CCD_OK) s = L_dchi(c, d, mask);
+        for (int k = 0; k < 3; k++) {
+            HIP_TRY(hipEventRecord(c->ev_join[k], c->aux[k]));
+            HIP_TRY(hipStreamWaitEvent(c->stream, c->ev_join[k], 0));
+        }
+    } else {
+        s = L_direct<P>(c, d, cur, mask);
+        if (s == CCD_OK) s = L_dchi(c, d, mask);
+        if (s == CCD_OK) s = L_ring_small<P>(c, d, cur, mask);
+        if (s == CCD_OK) s = L_ring<P>(c, d, cur, mask);
+    }
     if (s == CCD_OK) s = L_ladder<P>(c, d, cur, alpha, mask);
     return s;
 }
@@ -1875,6 +1920,13 @@ ccd_status ccd_bind_workspace(ccd_ctx* c, void* ptr, size_t bytes) {
     if (bytes < c->ws_bytes) { set_error("workspace too small"); return CCD_EINVAL; }
     if (((uintptr_t)ptr) & 255) { set_error("workspace must be 256-byte aligned"); return CCD_EINVAL; }
     c->ws = (char*)ptr;
+    if (!c->aux_ok) {
+        bool ok = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) == hipSuccess;
+        for (int k = 0; k < 3 && ok; k++)
+            ok = hipStreamCreateWithFlags(&c->aux[k], hipStreamNonBlocking) == hipSuccess &&
+                 hipEventCreateWithFlags(&c->ev_join[k], hipEventDisableTiming) == hipSuccess;
+        c->aux_ok = ok;  // without them the ring stays on the caller's stream
+    }
     HIP_TRY(set_ring_attrs<P_F64>());
     HIP_TRY(set_ring_attrs<P_F32>());
     HIP_TRY(set_ring_attrs<P_BF16>());
@@ -2232,9 +2284,17 @@ ccd_status ccd_kernel_times(ccd_ctx* c, double* ms, int64_t* launches, int32_t r
 
 void ccd_destroy(ccd_ctx* c) {
     if (!c) return;
-    if (!c->graphs.empty() || c->cap_stream) (void)hipStreamSynchronize(c->stream);
+    if (!c->graphs.empty() || c->cap_stream || c->aux_ok) (void)hipStreamSynchronize(c->stream);
     for (GraphEntry& g : c->graphs) (void)hipGraphExecDestroy(g.exec);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    for (int k = 0; k < 3; k++) {
+        if (c->aux[k]) {
+            (void)hipStreamSynchronize(c->aux[k]);
+            (void)hipStreamDestroy(c->aux[k]);
+        }
+        if (c->ev_join[k]) (void)hipEventDestroy(c->ev_join[k]);
+    }
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
     if (!c->ev_pool.empty()) {
         if (!c->pending.empty()) (void)hipStreamSynchronize(c->stream);
         for (auto e : c->ev_pool) (void)hipEventDestroy(e);
