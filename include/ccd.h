@@ -103,6 +103,13 @@ typedef struct {
     double tol_rel;        /* relative part of the stop test: a problem stops when
                               |dE_n - dE_(n-1)| < tol + tol_rel |dE_n|; both <= 0
                               run exactly max_iter sweeps */
+    int32_t stop_rule;     /* 0: the test above (the paper's).  1: additionally the
+                              estimate of the remaining change of a linearly
+                              converging iteration, |dE_n| r / (1 - r) with
+                              r = |dE_n| / |dE_(n-1)|, must pass the same threshold
+                              (and r < 1), in two consecutive sweeps; this bounds
+                              the distance to the limit when a slow mode dominates
+                              or E_n passes a turning point. */
 } ccd_solver_opts;
 
 typedef struct ccd_ctx ccd_ctx; /* opaque */

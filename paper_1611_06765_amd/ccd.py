@@ -49,7 +49,7 @@ class ccd_solver_opts(C.Structure):
     _fields_ = [("mixing", C.c_double), ("tol", C.c_double), ("max_iter", C.c_int32),
                 ("precision", C.c_int32), ("refine_sweeps", C.c_int32), ("terms", C.c_uint32),
                 ("mixed_tol", C.c_double), ("check_every", C.c_int32), ("use_graph", C.c_int32),
-                ("tol_rel", C.c_double)]
+                ("tol_rel", C.c_double), ("stop_rule", C.c_int32)]
 
 
 class ccd_info(C.Structure):
@@ -194,9 +194,10 @@ class Context:
         return self
 
     def iterate(self, mixing=1.0, tol=0.0, max_iter=1, precision=CCD_PREC_FP64, refine_sweeps=0,
-                terms=CCD_T_ALL, history=False, mixed_tol=0.0, check_every=1, graph=False, tol_rel=0.0):
+                terms=CCD_T_ALL, history=False, mixed_tol=0.0, check_every=1, graph=False, tol_rel=0.0,
+                stop_rule=0):
         o = ccd_solver_opts(mixing, tol, max_iter, precision, refine_sweeps, terms, mixed_tol,
-                            check_every, int(bool(graph)), tol_rel)
+                            check_every, int(bool(graph)), tol_rel, stop_rule)
         sweeps = np.zeros(self.n, dtype=np.int32)
         hist = np.zeros(self.n * max_iter) if history else None
         st = _lib.ccd_iterate(self._h, C.byref(o), sweeps.ctypes.data_as(_ip),

@@ -136,6 +136,8 @@ struct DevPtrs {
     int32_t* active;
     int32_t* sweeps;
     double* ehist;           // per problem: energies of the last kHistCap sweeps (ring)
+    double* dprev;           // per problem: |dE| of the previous sweep (0 = none yet)
+    int32_t* streak;         // per problem: consecutive sweeps that passed the tail test
 };
 
 constexpr int kHistCap = 64;  // sweeps between two host reads of the energy history
@@ -316,7 +318,7 @@ __global__ void __launch_bounds__(256) k_features(DevPtrs d, int cur, int gi, in
 // of four amplitudes go through the network (W2 staged once per block) and
 // the decoded amplitudes replace the current ones
 template <bool BF16>
-__global__ void __launch_bounds__(256) k_warm(DevPtrs d, int cur, const float* __restrict__ P, int n_items) {
+__global__ void __launch_bounds__(256, 3) k_warm(DevPtrs d, int cur, const float* __restrict__ P, int n_items) {
     extern __shared__ __attribute__((aligned(16))) char lds[];
     const mlp::Lds s = mlp::lds_carve<BF16>(lds);
     mlp::lds_load<BF16>(P, s, threadIdx.x, 256);
@@ -1069,7 +1071,11 @@ __global__ void __launch_bounds__(256) k_update(DevPtrs d, int cur, double alpha
 }
 
 // per-problem energy after a sweep, convergence test, divergence flag
-__global__ void __launch_bounds__(256) k_energy(DevPtrs d, double tol, double tol_rel) {
+// rule 0: stop when |dE_n| < tol + tol_rel |E_n| (the paper's test); rule 1:
+// the geometric-tail estimate |dE_n| r / (1 - r), r = |dE_n / dE_(n-1)|, of the
+// remaining change must also be below the same threshold (r < 1), in two
+// consecutive sweeps (a turning point of E_n makes one |dE| small)
+__global__ void __launch_bounds__(256) k_energy(DevPtrs d, double tol, double tol_rel, int rule) {
     __shared__ double sh[4];
     const int p = blockIdx.x;
     const DevGroup G = d.groups[d.pgrp[p]];
@@ -1085,7 +1091,18 @@ __global__ void __launch_bounds__(256) k_energy(DevPtrs d, double tol, double to
         d.ehist[(size_t)p * kHistCap + d.sweeps[p] % kHistCap] = e;
         d.sweeps[p] += 1;
         if (!isfinite(e)) d.active[p] = 0;
-        else if ((tol > 0.0 || tol_rel > 0.0) && fabs(e - old) < tol + tol_rel * fabs(e)) d.active[p] = 0;
+        else if (tol > 0.0 || tol_rel > 0.0) {
+            const double de = fabs(e - old), thr = tol + tol_rel * fabs(e), dp = d.dprev[p];
+            bool stop = de < thr;
+            if (rule == 1) {
+                const double r = dp > 0.0 ? de / dp : 1.0;
+                const bool pass = stop && r < 1.0 && de * r < thr * (1.0 - r);
+                d.streak[p] = pass ? d.streak[p] + 1 : 0;
+                stop = d.streak[p] >= 2;
+            }
+            if (stop) d.active[p] = 0;
+        }
+        d.dprev[p] = fabs(e - old);
     }
 }
 
@@ -1102,13 +1119,13 @@ struct Region {
 
 // a captured run of n sweeps and the arguments it was captured with
 struct GraphEntry {
-    int prec, cur, n;
+    int prec, cur, n, rule;
     uint32_t mask;
     double alpha, tol, tol_rel;
     int32_t tune[CCD_TUNE_LEN];
     hipGraphExec_t exec;
-    bool same(int p, int c0, int n0, uint32_t m, double a, double t, double tr, const int32_t* tu) const {
-        return prec == p && cur == c0 && n == n0 && mask == m && alpha == a && tol == t && tol_rel == tr &&
+    bool same(int p, int c0, int n0, uint32_t m, double a, double t, double tr, int ru, const int32_t* tu) const {
+        return prec == p && cur == c0 && n == n0 && mask == m && alpha == a && tol == t && tol_rel == tr && rule == ru &&
                std::memcmp(tune, tu, sizeof(tune)) == 0;
     }
 };
@@ -1134,7 +1151,7 @@ struct ccd_ctx {
     int n_rows = 0, n_cols = 0, n_chh = 0, n_eps = 0, n_epart = 0, n_eparte = 0, max_ph = 0;
     // workspace
     Region r_static, r_t0, r_t1, r_vt, r_chh, r_rows, r_cols, r_dchi, r_zp, r_rowx, r_colx, r_epart, r_eparte,
-        r_ecorr, r_eprev, r_active, r_sweeps, r_ehist, r_dpart, r_dcolp;
+        r_ecorr, r_eprev, r_active, r_sweeps, r_ehist, r_dpart, r_dcolp, r_dprev, r_streak;
     size_t ws_bytes = 0;
     char* ws = nullptr;
     bool bound = false;
@@ -1221,6 +1238,8 @@ static DevPtrs make_ptrs(ccd_ctx* c) {
     d.active = (int32_t*)(base + c->r_active.off);
     d.sweeps = (int32_t*)(base + c->r_sweeps.off);
     d.ehist = (double*)(base + c->r_ehist.off);
+    d.dprev = (double*)(base + c->r_dprev.off);
+    d.streak = (int32_t*)(base + c->r_streak.off);
     return d;
 }
 
@@ -1268,6 +1287,8 @@ static void layout(ccd_ctx* c) {
     region(c->r_active, P * 4);
     region(c->r_sweeps, P * 4);
     region(c->r_ehist, P * kHistCap * 8);
+    region(c->r_dprev, P * 8);
+    region(c->r_streak, P * 4);
     c->ws_bytes = o;
 }
 
@@ -1727,7 +1748,7 @@ static hipError_t set_ring_attrs() {
     return set_ring_attr_pair<P, 80, 16, 9>();
 }
 
-static ccd_status sweep(ccd_ctx* c, double alpha, double tol, double tol_rel, uint32_t mask, int prec) {
+static ccd_status sweep(ccd_ctx* c, double alpha, double tol, double tol_rel, int rule, uint32_t mask, int prec) {
     DevPtrs d = make_ptrs(c);
     const int cur = c->cur;
     ccd_status s = prec == CCD_PREC_BF16 ? launch_contractions<P_BF16>(c, d, cur, alpha, mask)
@@ -1736,7 +1757,7 @@ static ccd_status sweep(ccd_ctx* c, double alpha, double tol, double tol_rel, ui
     if (s != CCD_OK) return s;
     s = L_update(c, d, cur, alpha, mask);
     if (s != CCD_OK) return s;
-    LAUNCH(F_ENERGY, k_energy, (int)c->probs.size(), 256, 0, d, tol, tol_rel);
+    LAUNCH(F_ENERGY, k_energy, (int)c->probs.size(), 256, 0, d, tol, tol_rel, rule);
     c->cur ^= 1;
     return CCD_OK;
 }
@@ -1744,18 +1765,18 @@ static ccd_status sweep(ccd_ctx* c, double alpha, double tol, double tol_rel, ui
 // n sweeps: launched one by one, or (graph) as one replay of a captured graph
 // of the same n sweeps; kernel timing disables the graph
 static constexpr size_t kMaxGraphs = 4;
-static ccd_status run_sweeps(ccd_ctx* c, int n, double alpha, double tol, double tol_rel, uint32_t mask, int prec,
-                             bool graph) {
+static ccd_status run_sweeps(ccd_ctx* c, int n, double alpha, double tol, double tol_rel, int rule, uint32_t mask,
+                             int prec, bool graph) {
     if (!graph || c->timing) {
         for (int k = 0; k < n; k++) {
-            ccd_status s = sweep(c, alpha, tol, tol_rel, mask, prec);
+            ccd_status s = sweep(c, alpha, tol, tol_rel, rule, mask, prec);
             if (s != CCD_OK) return s;
         }
         return CCD_OK;
     }
     GraphEntry* ge = nullptr;
     for (GraphEntry& g : c->graphs)
-        if (g.same(prec, c->cur, n, mask, alpha, tol, tol_rel, c->tune)) ge = &g;
+        if (g.same(prec, c->cur, n, mask, alpha, tol, tol_rel, rule, c->tune)) ge = &g;
     if (!ge) {
         // captured on a private stream (the caller's may be the null stream),
         // replayed on the caller's stream in order with its other work
@@ -1765,7 +1786,7 @@ static ccd_status run_sweeps(ccd_ctx* c, int n, double alpha, double tol, double
         HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
         c->stream = c->cap_stream;
         ccd_status s = CCD_OK;
-        for (int k = 0; k < n && s == CCD_OK; k++) s = sweep(c, alpha, tol, tol_rel, mask, prec);
+        for (int k = 0; k < n && s == CCD_OK; k++) s = sweep(c, alpha, tol, tol_rel, rule, mask, prec);
         hipGraph_t gr = nullptr;
         const hipError_t ec = hipStreamEndCapture(c->cap_stream, &gr);
         c->stream = user;
@@ -1791,6 +1812,7 @@ static ccd_status run_sweeps(ccd_ctx* c, int n, double alpha, double tol, double
         }
         GraphEntry e;
         e.prec = prec; e.cur = cur0; e.n = n; e.mask = mask; e.alpha = alpha; e.tol = tol; e.tol_rel = tol_rel;
+        e.rule = rule;
         std::memcpy(e.tune, c->tune, sizeof(e.tune));
         e.exec = ex;
         c->graphs.push_back(e);
@@ -1950,7 +1972,7 @@ ccd_status ccd_bind_workspace(ccd_ctx* c, void* ptr, size_t bytes) {
 // per-problem sweep counters, active flags and the device energy history.
 // min_sweeps: sweeps run before the convergence test may stop a problem.
 static ccd_status run_phase(ccd_ctx* c, const ccd_solver_opts* o, int prec, double tol_phase, double rel_phase,
-                            int budget, int min_sweeps, double* e_hist, int& used) {
+                            int rule, int budget, int min_sweeps, double* e_hist, int& used) {
     const int P = (int)c->probs.size();
     std::vector<int32_t> ones(P, 1);
     HIP_TRY(hipMemcpyAsync(c->ws + c->r_active.off, ones.data(), P * 4, hipMemcpyHostToDevice, c->stream));
@@ -1977,7 +1999,7 @@ static ccd_status run_phase(ccd_ctx* c, const ccd_solver_opts* o, int prec, doub
             tol = tol_phase;
             rel = rel_phase;
         }
-        ccd_status st = run_sweeps(c, n, o->mixing, tol, rel, o->terms, prec, graph);
+        ccd_status st = run_sweeps(c, n, o->mixing, tol, rel, rule, o->terms, prec, graph);
         if (st != CCD_OK) return st;
         used += n;
         if (check) {
@@ -2012,26 +2034,31 @@ ccd_status ccd_iterate(ccd_ctx* c, const ccd_solver_opts* o, int32_t* sweeps_don
         set_error("ccd_iterate: unknown precision");
         return CCD_EINVAL;
     }
-    if (o->refine_sweeps < 0 || o->check_every < 0) {
-        set_error("ccd_iterate: refine_sweeps and check_every must be >= 0");
+    if (o->refine_sweeps < 0 || o->check_every < 0 || o->stop_rule < 0 || o->stop_rule > 1) {
+        set_error("ccd_iterate: refine_sweeps and check_every must be >= 0, stop_rule 0 or 1");
         return CCD_EINVAL;
     }
     const int P = (int)c->probs.size();
     std::vector<int32_t> zeros(P, 0);
+    std::vector<double> dzero(P, 0.0);
     HIP_TRY(hipMemcpyAsync(c->ws + c->r_sweeps.off, zeros.data(), P * 4, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->ws + c->r_dprev.off, dzero.data(), P * 8, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->ws + c->r_streak.off, zeros.data(), P * 4, hipMemcpyHostToDevice, c->stream));
     if (e_hist)
         for (size_t k = 0; k < (size_t)P * o->max_iter; k++) e_hist[k] = NAN;
     int used = 0;
     const bool mixed = o->precision != CCD_PREC_FP64;
     const bool own = mixed && o->mixed_tol > 0.0;  // the mixed phase has its own (absolute) criterion
-    ccd_status st = run_phase(c, o, o->precision, own ? o->mixed_tol : o->tol, own ? 0.0 : o->tol_rel, o->max_iter,
-                              1, e_hist, used);
+    // a mixed phase with its own criterion uses the plain |dE| test: near its
+    // rounding floor the ratio of successive changes hovers around 1
+    ccd_status st = run_phase(c, o, o->precision, own ? o->mixed_tol : o->tol, own ? 0.0 : o->tol_rel,
+                              own ? 0 : o->stop_rule, o->max_iter, 1, e_hist, used);
     if (st != CCD_OK) return st;
     if (mixed && used < o->max_iter) {
         // FP64 refinement: continue the FP64 iteration from the mixed-precision iterate
         int used2 = 0;
-        st = run_phase(c, o, CCD_PREC_FP64, o->tol, o->tol_rel, o->max_iter - used, std::max(1, o->refine_sweeps),
-                       e_hist, used2);
+        st = run_phase(c, o, CCD_PREC_FP64, o->tol, o->tol_rel, o->stop_rule, o->max_iter - used,
+                       std::max(1, o->refine_sweeps), e_hist, used2);
         if (st != CCD_OK) return st;
     }
     std::vector<int32_t> sw(P), act(P);

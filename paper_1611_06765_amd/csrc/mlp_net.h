@@ -44,9 +44,11 @@ __device__ __forceinline__ f4v mfma_bf16(bf8v a, bf8v b, f4v c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-__device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
+// sigmoid through the hardware reciprocal (about 1 ulp); silu(z) = z sigmoid(z)
+__device__ __forceinline__ float sigm(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
+__device__ __forceinline__ float silu(float z) { return z * sigm(z); }
 __device__ __forceinline__ float dsilu(float z) {
-    const float s = 1.0f / (1.0f + __expf(-z));
+    const float s = sigm(z);
     return s * (1.0f + z * (1.0f - s));
 }
 
@@ -64,11 +66,18 @@ __device__ __forceinline__ void variant_inputs(const float* f, int k, float* x) 
 }
 __device__ __forceinline__ float variant_sign(int k) { return (k == 1 || k == 2) ? -1.0f : 1.0f; }
 
-// first-layer pre-activation of unit c for inputs x (W1, b1 in LDS)
+// first-layer pre-activation of unit c for inputs x (W1 rows of 8 floats and
+// b1 in LDS; two 16-byte reads per row)
 __device__ __forceinline__ float layer1(const float* W1s, const float* b1s, int c, const float* x) {
+    const float4 w0 = *(const float4*)&W1s[c * kPack], w1 = *(const float4*)&W1s[c * kPack + 4];
     float z = b1s[c];
-#pragma unroll
-    for (int q = 0; q < 7; q++) z += W1s[c * kPack + q] * x[q];
+    z += w0.x * x[0];
+    z += w0.y * x[1];
+    z += w0.z * x[2];
+    z += w0.w * x[3];
+    z += w1.x * x[4];
+    z += w1.y * x[5];
+    z += w1.z * x[6];
     return z;
 }
 

@@ -152,3 +152,26 @@ def test_c4_mixed_batched_converges_to_fp64():
     for p in range(len(probs)):
         e64, em = ref.energy(p)[2], mix.energy(p)[2]
         assert abs(em - e64) <= 1e-6 * abs(e64), (p, em, e64)
+
+
+def test_extrapolated_stop_rule_bounds_the_error():
+    """stop_rule 1: from the MBPT2 start and from a perturbed start (which
+    excites every mode), stopping at tol_rel = 1e-7 leaves each energy within
+    1e-6 of the converged one; the plain |dE| test is never stricter."""
+    probs = [ccd.problem(66, 20, 0.16), ccd.problem(38, 12, 0.06)]
+    ref = _ctx(probs)
+    ref.iterate(mixing=0.5, tol=1e-11, max_iter=2000, check_every=16)
+    e_ref = [ref.energy(p)[2] for p in range(2)]
+    for scale in (1.0, 1.6):
+        a = _ctx(probs)
+        b = _ctx(probs)
+        for c in (a, b):
+            if scale != 1.0:
+                for p in range(2):
+                    c.set_amplitudes(c.get_amplitudes(p) * scale, p)
+        ra = a.iterate(mixing=0.5, tol=0.0, tol_rel=1e-7, stop_rule=1, max_iter=2000)
+        rb = b.iterate(mixing=0.5, tol=0.0, tol_rel=1e-7, stop_rule=0, max_iter=2000)
+        assert ra["status"] == rb["status"] == ccd.CCD_OK
+        assert np.all(ra["sweeps"] >= rb["sweeps"])
+        for p in range(2):
+            assert abs(a.energy(p)[2] - e_ref[p]) <= 1e-6 * abs(e_ref[p]), (scale, p)
