@@ -551,10 +551,13 @@ __global__ void __launch_bounds__(256) k_dchi(DevPtrs d, uint32_t mask, int n_it
 //   M_Q   = <kb||cj>_Q + 1/2 A B      (the transpose of chi_kbcj for the ring of P)
 //   Out   = A chi_P + M_Q A  =  Z_Q[u][y] + Z_P[y][u]
 // i.e. the sum of the two P(ij)P(ab) ring terms (with their common sign) that
-// land on one canonical amplitude.  Out is written in the pair block's own
-// order (coalesced); the amplitude update reads it back through the
-// (p, h) -> (channel, position) tables.  All four products run on FP64 MFMA
-// from LDS (matrices padded to n16, row stride n16 + 1).
+// land on one canonical amplitude.  The two halves of A B A combine, so
+//   Out = X A + A V_P,  X = A B + V_Q,  V = <kb||cj>
+// takes three products instead of four.  Out is written in the pair block's
+// own order (coalesced); the amplitude update reads it back through the
+// (p, h) -> (channel, position) tables.  The products run on MFMA from LDS
+// (matrices padded to n16, row stride n16 + 1), their K loops cut at the
+// block order rounded up to the MFMA K step.
 struct PairCtx {
     const int32_t* map;    // position map of Q
     const double* t;       // amplitudes of the problem
@@ -649,25 +652,45 @@ __device__ __forceinline__ void pair_store(const PairCtx& r, AT acc, int tu, int
     }
 }
 
-// products of one 16x16 output tile, k from 0 to kmax (FP64 / FP32: 16x16x4)
+// products of one 16x16 output tile, k from 0 to kmax (a multiple of 4; FP64 /
+// FP32: 16x16x4); operands of four steps are loaded before their MFMAs
 template <int P, typename E, typename AT>
 __device__ __forceinline__ AT mm4(const E* X, const E* Y, int lda, int tx, int ty, int kmax, int lane, AT acc) {
-    for (int k0 = 0; k0 < kmax; k0 += 4) {
-        const E a = X[(tx * 16 + (lane & 15)) * lda + k0 + (lane >> 4)];
-        const E b = Y[(k0 + (lane >> 4)) * lda + ty * 16 + (lane & 15)];
-        if constexpr (P == P_F64) acc = mfma64(a, b, acc);
-        else acc = mfma32(a, b, acc);
+    const E* xr = X + (tx * 16 + (lane & 15)) * lda + (lane >> 4);
+    const E* yc = Y + (lane >> 4) * lda + ty * 16 + (lane & 15);
+    int k0 = 0;
+    for (; k0 + 16 <= kmax; k0 += 16) {
+        E a[4], b[4];
+#pragma unroll
+        for (int s = 0; s < 4; s++) {
+            a[s] = xr[k0 + 4 * s];
+            b[s] = yc[(k0 + 4 * s) * lda];
+        }
+#pragma unroll
+        for (int s = 0; s < 4; s++) {
+            if constexpr (P == P_F64) acc = mfma64(a[s], b[s], acc);
+            else acc = mfma32(a[s], b[s], acc);
+        }
+    }
+    for (; k0 < kmax; k0 += 4) {
+        if constexpr (P == P_F64) acc = mfma64(xr[k0], yc[k0 * lda], acc);
+        else acc = mfma32(xr[k0], yc[k0 * lda], acc);
     }
     return acc;
 }
 // BF16: X row-major, Yt = Y^T row-major, k from 0 to kmax (a multiple of 32)
 __device__ __forceinline__ f4 mmbf(const __bf16* X, const __bf16* Yt, int lda, int tx, int ty, int kmax,
                                    int lane, f4 acc) {
-    for (int k0 = 0; k0 < kmax; k0 += 32) {
-        const bf8 a = *(const bf8*)&X[(tx * 16 + (lane & 15)) * lda + k0 + 8 * (lane >> 4)];
-        const bf8 b = *(const bf8*)&Yt[(ty * 16 + (lane & 15)) * lda + k0 + 8 * (lane >> 4)];
-        acc = mfmabf(a, b, acc);
+    const __bf16* xr = X + (tx * 16 + (lane & 15)) * lda + 8 * (lane >> 4);
+    const __bf16* yr = Yt + (ty * 16 + (lane & 15)) * lda + 8 * (lane >> 4);
+    int k0 = 0;
+    for (; k0 + 64 <= kmax; k0 += 64) {
+        const bf8 a0 = *(const bf8*)&xr[k0], b0 = *(const bf8*)&yr[k0];
+        const bf8 a1 = *(const bf8*)&xr[k0 + 32], b1 = *(const bf8*)&yr[k0 + 32];
+        acc = mfmabf(a0, b0, acc);
+        acc = mfmabf(a1, b1, acc);
     }
+    if (k0 < kmax) acc = mfmabf(*(const bf8*)&xr[k0], *(const bf8*)&yr[k0], acc);
     return acc;
 }
 
@@ -712,43 +735,23 @@ __device__ __forceinline__ void pair_body(const DevPtrs& d, const Item it, int c
     __syncthreads();
     if (live) pair_fill<E, n16, lda, 64 * NW, P == P_BF16>(r, qs, ps, lutS, A, B, At, Bt, tid, qring);
     __syncthreads();
-    AT x1[TPW], x2[TPW];
+    // K extent of the products: the block order rounded up to the MFMA K step
+    const int kq = P == P_BF16 ? ((r.n + 31) & ~31) : ((r.n + 3) & ~3);
+    // X = A B for this wave's tiles (quadratic ring)
+    AT xq[TPW];
 #pragma unroll
     for (int k = 0; k < TPW; k++) {
-        x1[k] = AT{0, 0, 0, 0};
-        x2[k] = x1[k];
+        xq[k] = AT{0, 0, 0, 0};
         const int tile = w + NW * k;
         if (live && qring && tile < ntt) {
             const int tx = tile / nt, ty = tile - tx * nt;
-            if constexpr (P == P_BF16) {
-                x1[k] = mmbf(B, At, lda, tx, ty, kpad, lane, x1[k]);  // B A
-                x2[k] = mmbf(A, Bt, lda, tx, ty, kpad, lane, x2[k]);  // A B
-            } else {
-                x1[k] = mm4<P>(B, A, lda, tx, ty, n16, lane, x1[k]);
-                x2[k] = mm4<P>(A, B, lda, tx, ty, n16, lane, x2[k]);
-            }
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < TPW; k++) {
-        const int tile = w + NW * k;
-        if (live && tile < ntt) {
-            const int tx = tile / nt, ty = tile - tx * nt;
-#pragma unroll
-            for (int q = 0; q < 4; q++) {
-                int x = tx * 16 + orow<P>(lane, q), y = ty * 16 + (lane & 15);
-                double v1 = 0.5 * (double)x1[k][q], v2 = 0.5 * (double)x2[k][q];
-                if (ring && x < r.n && y < r.n) {
-                    v1 += pair_vph(ps, lutS, x, y);
-                    v2 += pair_vph(qs, lutS, x, y);
-                }
-                x1[k][q] = v1;
-                x2[k][q] = v2;
-            }
+            if constexpr (P == P_BF16) xq[k] = mmbf(A, Bt, lda, tx, ty, kq, lane, xq[k]);
+            else xq[k] = mm4<P>(A, B, lda, tx, ty, kq, lane, xq[k]);
         }
     }
     __syncthreads();  // every wave has finished reading B (and Bt)
-    // chi_P goes to C (as its transpose for BF16, in Bt's place), M_Q into B
+    // X = A B + V_Q into B's place; V_P into C (FP64 / FP32) or its transpose
+    // into Bt's place (BF16); zero outside the block
     E* C = P == P_BF16 ? Bt : At;
 #pragma unroll
     for (int k = 0; k < TPW; k++) {
@@ -758,13 +761,19 @@ __device__ __forceinline__ void pair_body(const DevPtrs& d, const Item it, int c
 #pragma unroll
             for (int q = 0; q < 4; q++) {
                 const int x = tx * 16 + orow<P>(lane, q), y = ty * 16 + (lane & 15);
-                if constexpr (P == P_BF16) C[y * lda + x] = (E)(float)x1[k][q];
-                else C[x * lda + y] = (E)x1[k][q];
-                B[x * lda + y] = (E)x2[k][q];
+                double xv = (double)xq[k][q], vp = 0.0;
+                if (ring && x < r.n && y < r.n) {
+                    xv += pair_vph(qs, lutS, x, y);
+                    vp = pair_vph(ps, lutS, x, y);
+                }
+                B[x * lda + y] = (E)xv;
+                if constexpr (P == P_BF16) C[y * lda + x] = (E)(float)vp;
+                else C[x * lda + y] = (E)vp;
             }
         }
     }
     __syncthreads();
+    // Out = X A + A V_P
 #pragma unroll
     for (int k = 0; k < TPW; k++) {
         const int tile = w + NW * k;
@@ -772,11 +781,11 @@ __device__ __forceinline__ void pair_body(const DevPtrs& d, const Item it, int c
             const int tu = tile / nt, ty = tile - tu * nt;
             AT acc = {0, 0, 0, 0};
             if constexpr (P == P_BF16) {
-                acc = mmbf(A, C, lda, tu, ty, kpad, lane, acc);   // A chi_P
-                acc = mmbf(B, At, lda, tu, ty, kpad, lane, acc);  // M_Q A
+                acc = mmbf(B, At, lda, tu, ty, kq, lane, acc);  // X A
+                acc = mmbf(A, C, lda, tu, ty, kq, lane, acc);   // A V_P
             } else {
-                acc = mm4<P>(A, C, lda, tu, ty, n16, lane, acc);
-                acc = mm4<P>(B, A, lda, tu, ty, n16, lane, acc);
+                acc = mm4<P>(B, A, lda, tu, ty, kq, lane, acc);
+                acc = mm4<P>(A, C, lda, tu, ty, kq, lane, acc);
             }
             pair_store<P>(r, acc, tu, ty, lane);
         }
