@@ -174,7 +174,7 @@ def form_batched_c4(ccd, stream):
     return out
 
 
-def form_learned_c5(ccd, stream, epochs=8, batch=16384, lr=2e-3):
+def form_learned_c5(ccd, stream, epochs=24, batch=16384, lr=2e-3):
     """Train the warm-start network on the method's converged amplitudes
     (N=66, n^2<=20, 24 seeded densities), then solve 16 held-out densities at
     n^2<=36 from the MBPT2 start and from the network (BF16 inference)."""
