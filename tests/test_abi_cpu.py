@@ -197,3 +197,18 @@ def test_build_step_does_not_need_the_library():
     code = ("import sys, paper_1611_06765_amd.build_lib as b; "
             "assert 'paper_1611_06765_amd.ccd' not in sys.modules; print(b.LIB)")
     subprocess.check_call([sys.executable, "-c", code], cwd=ROOT)
+
+
+def test_size_limits():
+    """The largest cutoff the W table supports (n^2 <= 64) plans; N = 114 has
+    particle-hole blocks beyond the ring kernels' 80 and is refused with a
+    reason; a cutoff beyond 64 is refused."""
+    c = _ctx(66, 64, 0.16)
+    i = c.info()
+    assert i["n_states"] == 4218 and i["lut_size"] == 257 and i["max_ph"] <= 80
+    with pytest.raises(ccd.CCDError) as e:
+        _ctx(114, 20, 0.16)
+    assert e.value.status == ccd.CCD_EINVAL and "particle-hole" in str(e.value)
+    with pytest.raises(ccd.CCDError) as e:
+        _ctx(66, 65, 0.16)
+    assert e.value.status == ccd.CCD_EINVAL

@@ -177,3 +177,19 @@ def test_status_and_sweep_counts():
         n = int(res["sweeps"][p])
         assert np.all(np.isfinite(h[p, :n])) and np.all(np.isnan(h[p, n:]))
         assert abs(h[p, n - 1] - (h[p, n - 2] if n > 1 else np.nan)) < 1e-8 or n == 1
+
+
+def test_maximum_cutoff():
+    """N = 66 at the largest supported cutoff (n^2 <= 64, 4218 states, W table
+    of 257 entries): the MBPT2 start equals the oracle's, and FP64 sweeps stay
+    finite and bit-identical between a single context and a batched one."""
+    from oracle import oracle
+    spec = (66, 64, 0.16)
+    ctx = _gpu_ctx([ccd.problem(*spec)])
+    o3 = oracle.O3(oracle.PNM(*spec))
+    _assert_energy(ctx.energy()[1], o3.emp2, "E_MBPT2 at n^2 <= 64")
+    h1 = ctx.iterate(mixing=0.5, tol=0.0, max_iter=3, history=True)["history"][0]
+    big = _gpu_ctx([ccd.problem(38, 12, 0.1), ccd.problem(*spec)])
+    h2 = big.iterate(mixing=0.5, tol=0.0, max_iter=3, history=True, graph=True, check_every=3)["history"][1]
+    assert np.all(np.isfinite(h1)) and np.array_equal(h1, h2)
+    assert np.all(h1 < 0.0)
