@@ -354,13 +354,14 @@ __global__ void __launch_bounds__(256, 3) k_warm(DevPtrs d, int cur, const float
 
 // per (item of kDirSplit particle-pair rows of an S_z = 0 channel, problem):
 // row sums of t v, the item's part of 1/2 sum_cd <kl||cd> t_ij^cd on MFMA over
-// LDS-staged 32-row chunks, and its part of the column sums (the diagonal of
-// that product in FP64; summed in FP64 from memory in the mixed modes).
+// LDS-staged 32-row chunks (FP64 in LDS, converted at the MFMA in the mixed
+// modes), and its part of the column sums (the diagonal of that product in
+// FP64; summed from the staged chunk in the mixed modes).
 // k_dsum adds the parts in a fixed order.  Wave w owns output tiles w, w+4, ...
 constexpr int kDirRows = 32;
 template <int P>
 __global__ void __launch_bounds__(256) k_direct(DevPtrs d, int cur, uint32_t mask, int n_items) {
-    using E = typename std::conditional<P == P_F64, double, float>::type;
+    using E = double;
     using AT = typename std::conditional<P == P_F64, d4, f4>::type;
     constexpr int PM = P == P_F64 ? P_F64 : P_F32;   // contraction precision used here
     __shared__ __attribute__((aligned(16))) E vs[kDirRows][kMaxHH + 1];
@@ -400,30 +401,18 @@ __global__ void __launch_bounds__(256) k_direct(DevPtrs d, int cur, uint32_t mas
             vs[r][j] = (E)0;
             ts[r][j] = (E)0;
         }
+        __syncthreads();
+        // row sums of t v (one-body particle terms), FP64 in every mode
+        if ((mask & CCD_T_QPART) && threadIdx.x < rc) {
+            double sum = 0.0;
+            for (int j = 0; j < nhh; j++) sum += ts[threadIdx.x][j] * vs[threadIdx.x][j];
+            rows[r0 + threadIdx.x] = sum;
+        }
+        // mixed modes: this thread's share of a column sum, rows phase, phase + 4, ...
         if constexpr (P != P_F64) {
             const int j = threadIdx.x & 63;
             if ((mask & CCD_T_QHOLE) && j < nhh)
-                for (int r = threadIdx.x >> 6; r < rc; r += 4)
-                    cpart += t[(int64_t)(r0 + r) * nhh + j] * vt[(int64_t)(r0 + r) * nhh + j];
-        }
-        __syncthreads();
-        // row sums of t v (one-body particle terms), FP64 in every mode: from
-        // the staged chunk in FP64, straight from memory (a wave per row) else
-        if (mask & CCD_T_QPART) {
-            if constexpr (P == P_F64) {
-                if (threadIdx.x < rc) {
-                    double sum = 0.0;
-                    for (int j = 0; j < nhh; j++) sum += ts[threadIdx.x][j] * vs[threadIdx.x][j];
-                    rows[r0 + threadIdx.x] = sum;
-                }
-            } else {
-                for (int r = w; r < rc; r += 4) {
-                    const int64_t o = (int64_t)(r0 + r) * nhh;
-                    double sum = lane < nhh ? t[o + lane] * vt[o + lane] : 0.0;
-                    sum = wave_sum(sum);
-                    if (lane == 0) rows[r0 + r] = sum;
-                }
-            }
+                for (int r = threadIdx.x >> 6; r < rc; r += 4) cpart += ts[r][j] * vs[r][j];
         }
         if (quad) {
 #pragma unroll
@@ -436,7 +425,7 @@ __global__ void __launch_bounds__(256) k_direct(DevPtrs d, int cur, uint32_t mas
                         E av = vs[kk + (lane >> 4)][ti * 16 + (lane & 15)];
                         E bv = ts[kk + (lane >> 4)][tj * 16 + (lane & 15)];
                         if constexpr (P == P_F64) acc[k] = mfma64(av, bv, acc[k]);
-                        else acc[k] = mfma32(av, bv, acc[k]);
+                        else acc[k] = mfma32((float)av, (float)bv, acc[k]);
                     }
                 }
             }
