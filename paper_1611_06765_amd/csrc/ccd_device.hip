@@ -510,10 +510,10 @@ __global__ void __launch_bounds__(256) k_dchi(DevPtrs d, uint32_t mask, int n_it
     const Item it = d.it_dchi[bi];
     const DevGroup G = d.groups[it.chan];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int s = it.start + w;
+    const int s = (it.start & 0xffff) + w, g = it.start >> 16;  // state of this wave, problem
     if (s >= G.ns) continue;
     const int x0 = d.csr_ptr[G.csr_off + s], x1 = d.csr_ptr[G.csr_off + s + 1];
-    for (int g = 0; g < G.G; g++) {
+    {
         if (!d.active[G.p0 + g]) continue;
         const double* rows = d.rowsum + G.rows_base + g * G.n_rows;
         const double* cols = d.colsum + G.cols_base + g * G.n_cols;
@@ -1468,7 +1468,8 @@ static ccd_status assemble(ccd_ctx* c) {
             c->csr_idx.insert(c->csr_idx.end(), l.begin(), l.end());
             c->csr_ptr.push_back((int32_t)c->csr_idx.size());
         }
-        for (int s0 = 0; s0 < H.ns; s0 += 4) c->it_dchi.push_back({gi, s0});
+        for (int g = 0; g < D.G; g++)
+            for (int s0 = 0; s0 < H.ns; s0 += 4) c->it_dchi.push_back({gi, s0 | (g << 16)});
         // per-row / per-column Fock sums of every problem, ring indices
         D.pp0 = pp0; D.hh0 = hh0;
         D.n_rows_all = (int)H.pp.size() / 2;
