@@ -100,7 +100,7 @@ struct DevPtrs {
     const int32_t* phmap;
     const int32_t* csr_ptr;
     const int32_t* csr_idx;
-    const int32_t* zidx;     // per amplitude: the two ring entries (shared by a group)
+    const int32_t* zs;       // per pair-block position: ring slot << 1 | sign, or -1 (shared by a group)
     const double* rowE;      // per particle-pair row: eps_a + eps_b (per problem)
     const double* colE;      // per hole-pair column: eps_i + eps_j (per problem)
     const int32_t* pgrp;     // per problem: group
@@ -126,7 +126,7 @@ struct DevPtrs {
     double* rowsum;
     double* colsum;
     double* dchi;
-    double* zp;              // ring result per pair block {Q, -Q}
+    double* zc;              // ring result: two slots per amplitude, canonical order
     double* rowX;            // per row: one-body intermediates of a and b
     double* colX;            // per column: one-body intermediates of i and j
     double* epart;
@@ -542,15 +542,16 @@ __global__ void __launch_bounds__(256) k_dchi(DevPtrs d, uint32_t mask, int n_it
 // i.e. the sum of the two P(ij)P(ab) ring terms (with their common sign) that
 // land on one canonical amplitude.  The two halves of A B A combine, so
 //   Out = X A + A V_P,  X = A B + V_Q,  V = <kb||cj>
-// takes three products instead of four.  Out is written in the pair block's
-// own order (coalesced); the amplitude update reads it back through the
-// (p, h) -> (channel, position) tables.  The products run on MFMA from LDS
-// (matrices padded to n16, row stride n16 + 1), their K loops cut at the
-// block order rounded up to the MFMA K step.
+// takes three products instead of four.  Each entry of Out is stored once,
+// to the ring slot (2e + k) of the amplitude e it feeds (k = which of its two
+// ring terms), so the amplitude update reads its two slots with one 16-byte
+// load.  The products run on MFMA from LDS (matrices padded to n16, row stride
+// n16 + 1), their K loops cut at the block order rounded up to the MFMA K step.
 struct PairCtx {
     const int32_t* map;    // position map of Q
     const double* t;       // amplitudes of the problem
-    double* zp;            // pair block of the problem
+    double* zc;            // ring slots of the problem
+    const int32_t* zs;     // position -> slot table of the pair block
     int n;
     bool self;             // Q is its own partner
 };
@@ -562,7 +563,8 @@ __device__ __forceinline__ bool pair_ctx(const DevPtrs& d, const Item it, int cu
     const int g = it.start;
     r.map = d.phmap + q.map_off;
     r.t = d.t[cur] + G.t_base + g * G.n_amp;
-    r.zp = d.zp + G.zp_base + g * G.n_zp + q.zp_off;
+    r.zc = d.zc + 2 * (G.t_base + g * G.n_amp);
+    r.zs = d.zs + G.zidx_off + q.zp_off;
     r.n = q.n;
     r.self = q.partner == it.chan;
     memQ = q.mem_off;
@@ -633,10 +635,11 @@ __device__ __forceinline__ void pair_store(const PairCtx& r, AT acc, int tu, int
     for (int q = 0; q < 4; q++) {
         int u = tu * 16 + orow<P>(lane, q), y = ty * 16 + (lane & 15);
         if (u < r.n && y < r.n) {
-            int m = r.map[u * r.n + y];
-            // a self pair holds both orders of one amplitude: keep the p < p' one
+            // the position's ring slot (a self pair holds both orders of one
+            // amplitude; only the p < p' one has a slot)
+            const int32_t z = r.zs[u * r.n + y];
             const double v = (double)acc[q];
-            if (m >= 0 && !(r.self && ((m >> 2) & 1))) r.zp[u * r.n + y] = (m & 1) ? -v : v;
+            if (z >= 0) r.zc[z >> 1] = (z & 1) ? -v : v;
         }
     }
 }
@@ -701,7 +704,7 @@ __device__ __forceinline__ void pair_body(const DevPtrs& d, const Item it, int c
     constexpr int lda = P == P_BF16 ? kpad + 8 : N16 + 1;
     constexpr int rows = P == P_BF16 ? kpad : N16;  // rows allocated per matrix
     PairCtx r;
-    r.n = 0; r.self = false; r.map = nullptr; r.t = nullptr; r.zp = nullptr;
+    r.n = 0; r.self = false; r.map = nullptr; r.t = nullptr; r.zc = nullptr; r.zs = nullptr;
     int32_t memQ = 0, memP = 0, lo = 0;
     // every wave reaches every barrier below; only the work is guarded by live
     const bool live = it.chan >= 0 && pair_ctx(d, it, cur, r, memQ, memP, lo);
@@ -816,11 +819,10 @@ __global__ void __launch_bounds__(64 * NW) k_ringp(DevPtrs d, int cur, uint32_t 
     }
 }
 
-// the ring contribution to amplitude e of problem g: two pair-block entries
+// the ring contribution to amplitude e of problem g: its two ring slots
 __device__ __forceinline__ double ring_term(const DevPtrs& d, const DevGroup& G, int g, int64_t e) {
-    const double* zp = d.zp + G.zp_base + g * G.n_zp;
-    const int32_t* zi = d.zidx + G.zidx_off + 2 * e;
-    return zp[zi[0]] + zp[zi[1]];
+    const double2 z = *(const double2*)(d.zc + 2 * (G.t_base + g * G.n_amp + e));
+    return z.x + z.y;
 }
 
 // one-body sums per row (delta chi_a + delta chi_b) and column (delta chi_i +
@@ -1136,19 +1138,18 @@ struct ccd_ctx {
     std::vector<DevChan> dchans;
     std::vector<DevPh> dph;
     std::vector<int32_t> ppinfo;
-    std::vector<int32_t> st, hh, pp, phmem, phmap, zidx, csr_ptr, csr_idx, pgrp, pgi, it_sz0;
+    std::vector<int32_t> st, hh, pp, phmem, phmap, zs, csr_ptr, csr_idx, pgrp, pgi, it_sz0;
     std::vector<double> eps, lut, rowE, colE, pscale;
     std::vector<Item> it_elem, it_nsz0, it_ladder, it_dchi, it_direct, it_ring_s, it_ring_b, it_lg, it_ng, it_dsub,
         it_dsum;
     int64_t n_dpart = 0, n_dcolp = 0;
     int ring_lo[4] = {0}, ring_n[4] = {0};  // big pair items by padded size n16 = 32, 48, 64, 80
-    int64_t NZP = 0;                         // ring-result entries, all problems
     std::vector<int64_t> prob_t0;  // amplitude index of each problem (caller order)
     std::vector<int> slot_of;      // caller problem -> slot (group order) of the device flags
     int64_t NT = 0;
     int n_rows = 0, n_cols = 0, n_chh = 0, n_eps = 0, n_epart = 0, n_eparte = 0, max_ph = 0;
     // workspace
-    Region r_static, r_t0, r_t1, r_vt, r_chh, r_rows, r_cols, r_dchi, r_zp, r_rowx, r_colx, r_epart, r_eparte,
+    Region r_static, r_t0, r_t1, r_vt, r_chh, r_rows, r_cols, r_dchi, r_zc, r_rowx, r_colx, r_epart, r_eparte,
         r_ecorr, r_eprev, r_active, r_sweeps, r_ehist, r_dpart, r_dcolp, r_dprev, r_streak;
     size_t ws_bytes = 0;
     char* ws = nullptr;
@@ -1179,7 +1180,7 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 #define STATIC_TABLES(X)                                                  \
     X(st, int32_t) X(eps, double) X(lut, double) X(dgroups, DevGroup)     \
     X(dchans, DevChan) X(dph, DevPh) X(hh, int32_t) X(pp, int32_t)        \
-    X(phmem, int32_t) X(phmap, int32_t) X(zidx, int32_t) X(rowE, double) X(colE, double) \
+    X(phmem, int32_t) X(phmap, int32_t) X(zs, int32_t) X(rowE, double) X(colE, double) \
     X(csr_ptr, int32_t)                                                   \
     X(csr_idx, int32_t) X(pgrp, int32_t) X(pgi, int32_t) X(pscale, double) \
     X(it_elem, Item) X(it_nsz0, Item) X(it_ladder, Item) X(it_sz0, int32_t) X(it_dchi, Item) \
@@ -1195,7 +1196,7 @@ static DevPtrs make_ptrs(ccd_ctx* c) {
     const void* p_csr_ptr; const void* p_csr_idx; const void* p_pgrp; const void* p_pgi;
     const void* p_it_elem; const void* p_it_nsz0; const void* p_it_ladder; const void* p_it_sz0;
     const void* p_it_dchi; const void* p_it_direct; const void* p_it_ring_s; const void* p_it_ring_b;
-    const void* p_it_lg; const void* p_it_ng; const void* p_zidx; const void* p_rowE; const void* p_colE;
+    const void* p_it_lg; const void* p_it_ng; const void* p_zs; const void* p_rowE; const void* p_colE;
     const void* p_pscale; const void* p_it_dsub; const void* p_it_dsum; const void* p_ppinfo;
 #define TAKE(name, T)             \
     p_##name = base + o;          \
@@ -1212,7 +1213,7 @@ static DevPtrs make_ptrs(ccd_ctx* c) {
     d.it_dchi = (const Item*)p_it_dchi;
     d.it_direct = (const Item*)p_it_direct; d.it_ring_s = (const Item*)p_it_ring_s;
     d.it_ring_b = (const Item*)p_it_ring_b; d.it_lg = (const Item*)p_it_lg;
-    d.it_ng = (const Item*)p_it_ng; d.zidx = (const int32_t*)p_zidx;
+    d.it_ng = (const Item*)p_it_ng; d.zs = (const int32_t*)p_zs;
     d.rowE = (const double*)p_rowE; d.colE = (const double*)p_colE;
     d.pscale = (const double*)p_pscale;
     d.it_dsub = (const Item*)p_it_dsub; d.it_dsum = (const Item*)p_it_dsum;
@@ -1226,7 +1227,7 @@ static DevPtrs make_ptrs(ccd_ctx* c) {
     d.rowsum = (double*)(base + c->r_rows.off);
     d.colsum = (double*)(base + c->r_cols.off);
     d.dchi = (double*)(base + c->r_dchi.off);
-    d.zp = (double*)(base + c->r_zp.off);
+    d.zc = (double*)(base + c->r_zc.off);
     d.rowX = (double*)(base + c->r_rowx.off);
     d.colX = (double*)(base + c->r_colx.off);
     d.epart = (double*)(base + c->r_epart.off);
@@ -1275,7 +1276,7 @@ static void layout(ccd_ctx* c) {
     region(c->r_rows, (size_t)c->n_rows * 8);
     region(c->r_cols, (size_t)c->n_cols * 8);
     region(c->r_dchi, (size_t)c->n_eps * 8);
-    region(c->r_zp, (size_t)c->NZP * 8);
+    region(c->r_zc, (size_t)c->NT * 16);
     region(c->r_rowx, c->rowE.size() * 8);
     region(c->r_colx, c->colE.size() * 8);
     region(c->r_epart, (size_t)c->n_epart * 8);
@@ -1348,7 +1349,7 @@ static ccd_status assemble(ccd_ctx* c) {
     c->slot_of.assign(P, 0);
     std::vector<std::pair<int, Item>> lg, ng, dir, dsum, rs, rb[4];
     std::vector<double> lg_cost;
-    int64_t t_base = 0, zp_base = 0;
+    int64_t t_base = 0;
     int gi = 0, slot0 = 0;
     for (auto& kv : by_structure) {
         const std::vector<int>& members = kv.second;
@@ -1481,8 +1482,8 @@ static ccd_status assemble(ccd_ctx* c) {
             for (size_t k = 0; k < H.pp.size() / 2; k++) c->rowE.push_back(Hg.eps[H.pp[2 * k]] + Hg.eps[H.pp[2 * k + 1]]);
             for (size_t k = 0; k < H.hh.size() / 2; k++) c->colE.push_back(Hg.eps[H.hh[2 * k]] + Hg.eps[H.hh[2 * k + 1]]);
         }
-        D.zidx_off = (int64_t)c->zidx.size();
-        c->zidx.insert(c->zidx.end(), H.zidx.begin(), H.zidx.end());
+        D.zidx_off = (int64_t)c->zs.size();
+        c->zs.insert(c->zs.end(), H.zs.begin(), H.zs.end());
         // cross channels and their pairs {Q, -Q}; the lower index is the primary
         const int ph0 = (int)c->dph.size(), mem0 = (int)c->phmem.size();
         const int64_t map0 = (int64_t)c->phmap.size();
@@ -1512,15 +1513,13 @@ static ccd_status assemble(ccd_ctx* c) {
         D.phq_off = 0;
         D.ph_base = (int)map0;
         D.n_zp = nzp;
-        D.zp_base = zp_base;
-        zp_base += (int64_t)D.G * nzp;
         c->dgroups.push_back(D);
         t_base += (int64_t)D.G * H.n_amp;
         slot0 += D.G;
         gi++;
     }
     c->NT = t_base;
-    c->NZP = zp_base;
+
     if (c->csr_idx.empty()) c->csr_idx.push_back(0);
     c->it_lg = xcd_order_cost(lg, lg_cost);
     c->it_ng = xcd_order(ng);

@@ -36,9 +36,8 @@ inline int32_t pack_pair(int p, int q) { return (int32_t)((uint32_t)p | ((uint32
 struct DevGroup {
     int64_t n_amp;        // canonical amplitudes per problem
     int64_t t_base;       // amplitude index of the group's first problem
-    int64_t n_zp;         // ring-result entries per problem (pair blocks)
-    int64_t zp_base;      // ring result of problem g at zp_base + g * n_zp
-    int64_t zidx_off;     // per-amplitude ring indices (shared), 2 per amplitude
+    int64_t n_zp;         // pair-block positions per problem
+    int64_t zidx_off;     // pair-block position -> ring slot table (shared)
     int32_t phq_off;      // (p, h) -> cross channel / position tables (shared)
     int32_t n_rows_all, n_cols_all; // particle-pair rows / hole-pair columns of all channels
     int32_t rowa_base, cola_base;   // per-row / per-column arrays: + g * n_rows_all / n_cols_all
@@ -126,7 +125,8 @@ struct HostProblem {
     int64_t n_zp = 0;                    // entries of the pair blocks
     // per canonical amplitude: the two pair-block entries that hold its ring
     // term, positions (a,i)(b,j) and (a,j)(b,i)
-    std::vector<int32_t> zidx;           // 2 per amplitude
+    std::vector<int32_t> zidx;           // 2 per amplitude: the pair-block positions of its ring terms
+    std::vector<int32_t> zs;             // per pair-block position: (ring slot 2e + k) << 1 | sign, or -1
     int max_hh = 0, max_pp = 0, max_ph = 0;
     double flops_pp = 0, flops_hh = 0, flops_ring = 0, flops_ordered = 0;
 };

@@ -253,7 +253,7 @@ ccd_status build_problem(const ccd_problem& par, HostProblem& P, std::string& er
             P.n_zp += (int64_t)c.n * c.n;
         }
     }
-    if (P.n_zp >= ((int64_t)1 << 31)) { err = "too many ring entries"; return CCD_EINVAL; }
+    if (P.n_zp >= ((int64_t)1 << 31) || P.n_amp >= ((int64_t)1 << 29)) { err = "too many ring entries"; return CCD_EINVAL; }
     auto zpos = [&](int p, int h, int p2, int h2) -> int64_t {
         size_t x1 = (size_t)(p - P.nh) * P.nh + h, x2 = (size_t)(p2 - P.nh) * P.nh + h2;
         const PhChan& c = P.ph[P.phq[x1]];
@@ -271,6 +271,27 @@ ccd_status build_problem(const ccd_problem& par, HostProblem& P, std::string& er
                 P.zidx[2 * e + 1] = (int32_t)zpos(a, j, b, i);
             }
         }
+    // inverse: each written pair-block position feeds one ring slot 2e + k of one
+    // amplitude (zidx[2e + k] is that position); zs = (2e + k) << 1 | sign
+    P.zs.assign((size_t)P.n_zp, -1);
+    int64_t assigned = 0;
+    for (const PhChan& c : P.ph) {
+        if (c.zp_off < 0) continue;
+        const bool self = c.partner == (int)(&c - P.ph.data());
+        for (int u = 0; u < c.n; u++)
+            for (int y = 0; y < c.n; y++) {
+                const int32_t m = P.phmap[(size_t)c.z_off + (size_t)u * c.n + y];
+                if (m < 0 || (self && ((m >> 2) & 1))) continue;
+                const int64_t e = m >> 3, pos = c.zp_off + (int64_t)u * c.n + y;
+                int k = -1;
+                if (P.zidx[2 * e] == pos) k = 0;
+                else if (P.zidx[2 * e + 1] == pos) k = 1;
+                if (k < 0 || P.zs[pos] != -1) { err = "internal: ring position without a unique slot"; return CCD_EINVAL; }
+                P.zs[pos] = (int32_t)(((2 * e + k) << 1) | (m & 1));
+                assigned++;
+            }
+    }
+    if (assigned != 2 * P.n_amp) { err = "internal: ring slots not covered"; return CCD_EINVAL; }
     return CCD_OK;
 }
 
