@@ -81,15 +81,18 @@ typedef struct {
 } ccd_adam_opts;
 
 /* floor(n_order / batch) Adam steps; step s uses the amplitudes
- * dev_order[s*batch .. (s+1)*batch) (indices into dev_feat / dev_target, e.g.
- * a seeded permutation).  dev_m, dev_v: Adam moments (CCD_MLP_NPARAM each,
- * zero before the first step).  *step (host) is Adam's t before the call and
- * is advanced by the number of steps.  mean_loss (host, nullable): mean of the
- * minibatch losses; synchronises the stream.  The work buffer must hold
- * ccd_mlp_work_size(batch) bytes. */
+ * dev_order[s*batch .. (s+1)*batch), indices into the n_rows rows of dev_feat
+ * ([n_rows][8]) and dev_target ([n_rows]), e.g. a seeded permutation.  An
+ * index outside [0, n_rows) is skipped (its amplitude counts as absent) and
+ * the call returns CCD_EINVAL after the steps.  dev_m, dev_v: Adam moments
+ * (CCD_MLP_NPARAM each, zero before the first step).  *step (host) is Adam's t
+ * before the call and is advanced by the number of steps.  mean_loss (host,
+ * nullable): mean of the minibatch losses.  Synchronises the stream once at
+ * the end.  The work buffer must hold ccd_mlp_work_size(batch) bytes. */
 ccd_status ccd_mlp_train(float* dev_params, float* dev_m, float* dev_v, int64_t* step, const float* dev_feat,
-                         const float* dev_target, const int32_t* dev_order, int64_t n_order, const ccd_adam_opts* opts,
-                         void* dev_work, size_t work_bytes, double* mean_loss, void* hip_stream);
+                         const float* dev_target, int64_t n_rows, const int32_t* dev_order, int64_t n_order,
+                         const ccd_adam_opts* opts, void* dev_work, size_t work_bytes, double* mean_loss,
+                         void* hip_stream);
 
 /* Warm start of every problem of the context: features computed on the fly,
  * prediction on MFMA (CCD_PREC_BF16 or CCD_PREC_FP32), amplitudes

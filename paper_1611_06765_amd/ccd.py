@@ -86,7 +86,7 @@ _SIGS = {
     "ccd_mlp_forward": (_i32, [_vp, _vp, C.c_int64, _i32, _vp, _vp]),
     "ccd_mlp_work_size": (_i32, [C.c_int64, C.POINTER(_sz)]),
     "ccd_mlp_loss_grad": (_i32, [_vp, _vp, _vp, C.c_int64, _vp, _dp, _vp, _sz, _vp]),
-    "ccd_mlp_train": (_i32, [_vp, _vp, _vp, C.POINTER(C.c_int64), _vp, _vp, _vp, C.c_int64,
+    "ccd_mlp_train": (_i32, [_vp, _vp, _vp, C.POINTER(C.c_int64), _vp, _vp, C.c_int64, _vp, C.c_int64,
                              C.POINTER(ccd_adam_opts), _vp, _sz, _dp, _vp]),
     "ccd_warm_start": (_i32, [_vp, _vp, _i32, _ip]),
     "ccd_autotune": (_i32, [_vp, _i32, _i32, _dp]),
@@ -297,7 +297,7 @@ def mlp_forward(params, feat, precision=CCD_PREC_BF16):
     return y
 
 
-def _work(n, device):
+def mlp_work_buffer(n, device):
     import torch
     nb = _sz()
     _check(_lib.ccd_mlp_work_size(n, C.byref(nb)), "ccd_mlp_work_size")
@@ -311,7 +311,7 @@ def mlp_loss_grad(params, feat, target):
     import torch
     n = feat.shape[0]
     g = torch.empty(CCD_MLP_NPARAM, dtype=torch.float32, device=feat.device)
-    w, ptr, nb = _work(n, feat.device)
+    w, ptr, nb = mlp_work_buffer(n, feat.device)
     loss = C.c_double()
     _check(_lib.ccd_mlp_loss_grad(_vp(params.data_ptr()), _vp(feat.data_ptr()), _vp(target.data_ptr()), n,
                                   _vp(g.data_ptr()), C.byref(loss), _vp(ptr), nb, _stream_of(feat)),
@@ -335,11 +335,11 @@ def mlp_train(params, state, feat, target, order, batch, lr, beta1=0.9, beta2=0.
     (int32 device tensor of row indices); returns the mean minibatch loss."""
     o = ccd_adam_opts(lr, beta1, beta2, eps, batch)
     if work is None:
-        work = _work(batch, feat.device)
+        work = mlp_work_buffer(batch, feat.device)
     _, ptr, nb = work
     loss = C.c_double()
     _check(_lib.ccd_mlp_train(_vp(params.data_ptr()), _vp(state.m.data_ptr()), _vp(state.v.data_ptr()),
-                              C.byref(state.step), _vp(feat.data_ptr()), _vp(target.data_ptr()),
+                              C.byref(state.step), _vp(feat.data_ptr()), _vp(target.data_ptr()), feat.shape[0],
                               _vp(order.data_ptr()), order.shape[0], C.byref(o), _vp(ptr), nb, C.byref(loss),
                               _stream_of(feat)), "ccd_mlp_train")
     return loss.value

@@ -68,10 +68,13 @@ __host__ __device__ constexpr size_t grad_lds_bytes() {
     return lds_bytes<false>() + (size_t)2 * 32 * kLdH * 4 + (size_t)(8 * kPack + 8 + 8 + 2 * 32) * 4;
 }
 
+// Indices of `order` outside [0, n_rows) are skipped (the amplitude counts as
+// absent) and counted in *bad.
 __global__ void __launch_bounds__(256) k_mlp_grad(const float* __restrict__ P, const float* __restrict__ feat,
                                                   const float* __restrict__ target, const int32_t* __restrict__ order,
-                                                  int64_t base, int64_t n, float inv_m, float* __restrict__ work,
-                                                  float* __restrict__ work_loss) {
+                                                  int64_t base, int64_t n, int64_t n_rows, float inv_m,
+                                                  float* __restrict__ work, float* __restrict__ work_loss,
+                                                  int32_t* __restrict__ bad) {
     extern __shared__ __attribute__((aligned(16))) char lds[];
     const Lds s = lds_carve<false>(lds);
     float* H1 = (float*)(lds + lds_bytes<false>());  // [32][kLdH]
@@ -104,8 +107,12 @@ __global__ void __launch_bounds__(256) k_mlp_grad(const float* __restrict__ P, c
         if (tid < 8 * kPack) {
             const int el = tid >> 3, q = tid & 7;
             const int64_t li = e0 + cb * 8 + el;
-            const bool ok = li < n;
-            const int64_t gi = ok ? (order ? (int64_t)order[base + li] : base + li) : 0;
+            int64_t gi = li < n ? (order ? (int64_t)order[base + li] : base + li) : -1;
+            if (li < n && (gi < 0 || gi >= n_rows)) {
+                if (q == 0) atomicAdd(bad, 1);
+                gi = -1;
+            }
+            const bool ok = gi >= 0;
             Fs[el * kPack + q] = ok ? feat[gi * kPack + q] : 0.f;
             if (q == 0) {
                 Ys[el] = ok ? target[gi] : 0.f;
@@ -302,12 +309,16 @@ __global__ void __launch_bounds__(256) k_mlp_reduce(const float* __restrict__ wo
     }
 }
 
-__global__ void k_mlp_zero(double* acc) { acc[0] = 0.0; }
+__global__ void k_mlp_zero(double* acc, int32_t* bad) {
+    acc[0] = 0.0;
+    bad[0] = 0;
+}
 
 struct Work {
     float* part;
     float* loss;
     double* acc;
+    int32_t* bad;   // count of out-of-range indices
 };
 
 size_t work_bytes_for(int64_t n) {
@@ -321,6 +332,7 @@ Work carve(void* w, int64_t n) {
     k.part = (float*)w;
     k.loss = k.part + (size_t)nblk * kParams;
     k.acc = (double*)((char*)w + work_bytes_for(n) - 256);
+    k.bad = (int32_t*)(k.acc + 1);
     return k;
 }
 
@@ -391,9 +403,9 @@ ccd_status ccd_mlp_loss_grad(const float* params, const float* feat, const float
     const Work k = carve(work, n);
     const int nblk = (int)((n + kEPB - 1) / kEPB);
     hipStream_t st = (hipStream_t)stream;
-    hipLaunchKernelGGL(k_mlp_zero, dim3(1), dim3(1), 0, st, k.acc);
+    hipLaunchKernelGGL(k_mlp_zero, dim3(1), dim3(1), 0, st, k.acc, k.bad);
     hipLaunchKernelGGL(k_mlp_grad, dim3(nblk), dim3(256), grad_lds_bytes(), st, params, feat, target,
-                       (const int32_t*)nullptr, (int64_t)0, n, 1.0f / (float)n, k.part, k.loss);
+                       (const int32_t*)nullptr, (int64_t)0, n, n, 1.0f / (float)n, k.part, k.loss, k.bad);
     hipLaunchKernelGGL(k_mlp_reduce, dim3((kParams + 255) / 256), dim3(256), 0, st, k.part, k.loss, nblk, 0, grad,
                        (float*)nullptr, (float*)nullptr, (float*)nullptr, 0.f, 0.f, 0.f, 0.f, 1.f, 1.f, k.acc);
     MLP_TRY(hipGetLastError());
@@ -405,10 +417,10 @@ ccd_status ccd_mlp_loss_grad(const float* params, const float* feat, const float
 }
 
 ccd_status ccd_mlp_train(float* params, float* adam_m, float* adam_v, int64_t* step, const float* feat,
-                         const float* target, const int32_t* order, int64_t n_order, const ccd_adam_opts* o,
-                         void* work, size_t work_bytes, double* mean_loss, void* stream) {
-    if (!params || !adam_m || !adam_v || !step || !feat || !target || !order || !o || !work) {
-        ccd::set_error("ccd_mlp_train: NULL argument");
+                         const float* target, int64_t n_rows, const int32_t* order, int64_t n_order,
+                         const ccd_adam_opts* o, void* work, size_t work_bytes, double* mean_loss, void* stream) {
+    if (!params || !adam_m || !adam_v || !step || !feat || !target || !order || !o || !work || n_rows < 1) {
+        ccd::set_error("ccd_mlp_train: NULL argument or n_rows < 1");
         return CCD_EINVAL;
     }
     if (o->batch < 1 || n_order < o->batch || !(o->lr > 0.f) || !(o->beta1 >= 0.f && o->beta1 < 1.f) ||
@@ -426,24 +438,28 @@ ccd_status ccd_mlp_train(float* params, float* adam_m, float* adam_v, int64_t* s
     const int nblk = (int)((o->batch + kEPB - 1) / kEPB);
     const int64_t nsteps = n_order / o->batch;
     hipStream_t st = (hipStream_t)stream;
-    hipLaunchKernelGGL(k_mlp_zero, dim3(1), dim3(1), 0, st, k.acc);
+    hipLaunchKernelGGL(k_mlp_zero, dim3(1), dim3(1), 0, st, k.acc, k.bad);
     for (int64_t q = 0; q < nsteps; q++) {
         const int64_t t = *step + 1;
         const float bc1 = (float)(1.0 - std::pow((double)o->beta1, (double)t));
         const float bc2 = (float)(1.0 - std::pow((double)o->beta2, (double)t));
         hipLaunchKernelGGL(k_mlp_grad, dim3(nblk), dim3(256), grad_lds_bytes(), st, params, feat, target, order,
-                           q * o->batch, (int64_t)o->batch, 1.0f / (float)o->batch, k.part, k.loss);
+                           q * o->batch, (int64_t)o->batch, n_rows, 1.0f / (float)o->batch, k.part, k.loss, k.bad);
         hipLaunchKernelGGL(k_mlp_reduce, dim3((kParams + 255) / 256), dim3(256), 0, st, k.part, k.loss, nblk, 1,
                            (float*)nullptr, params, adam_m, adam_v, o->lr, o->beta1, o->beta2, o->eps, bc1, bc2,
                            k.acc);
         MLP_TRY(hipGetLastError());
         *step = t;
     }
-    if (mean_loss) {
-        double acc = 0.0;
-        MLP_TRY(hipMemcpyAsync(&acc, k.acc, 8, hipMemcpyDeviceToHost, st));
-        MLP_TRY(hipStreamSynchronize(st));
-        *mean_loss = acc / (double)nsteps;
+    double acc = 0.0;
+    int32_t bad = 0;
+    MLP_TRY(hipMemcpyAsync(&acc, k.acc, 8, hipMemcpyDeviceToHost, st));
+    MLP_TRY(hipMemcpyAsync(&bad, k.bad, 4, hipMemcpyDeviceToHost, st));
+    MLP_TRY(hipStreamSynchronize(st));
+    if (mean_loss) *mean_loss = acc / (double)nsteps;
+    if (bad) {
+        ccd::set_error("ccd_mlp_train: " + std::to_string(bad) + " indices of order outside [0, n_rows) were skipped");
+        return CCD_EINVAL;
     }
     return CCD_OK;
 }

@@ -44,7 +44,7 @@ def train(feat, target, epochs, batch=4096, lr=2e-3, seed=inputs.MLP_SEED, param
         params = torch.tensor(inputs.mlp_init(seed), device=dev)
     state = ccd.AdamState(params)
     rng = np.random.default_rng(seed)
-    work = ccd._work(batch, dev)
+    work = ccd.mlp_work_buffer(batch, dev)
     n = feat.shape[0]
     losses = []
     for ep in range(epochs):

@@ -202,3 +202,22 @@ def test_learned_start_shortens_heldout_solves():
         e0, e1 = base.energy(p)[2], warm.energy(p)[2]
         assert abs(e0 - e1) <= 1e-6 * abs(e0)
     assert rw["sweeps"].sum() < rb["sweeps"].sum(), (rw["sweeps"], rb["sweeps"])
+
+
+def test_training_rejects_out_of_range_indices():
+    """An order entry outside [0, n_rows) is skipped on the device and the
+    call reports CCD_EINVAL; the other amplitudes of the step still train."""
+    torch = _torch()
+    n = 256
+    F = _dev(_rand_feats(n, seed=21))
+    Y = _dev(np.random.default_rng(22).normal(0, 0.1, n).astype(np.float32))
+    P = _dev(_params(seed=23))
+    p0 = P.clone()
+    st = ccd.AdamState(P)
+    order = torch.arange(n, dtype=torch.int32, device="cuda")
+    order[17] = n + 5
+    order[40] = -3
+    with pytest.raises(ccd.CCDError) as e:
+        ccd.mlp_train(P, st, F, Y, order, n, 1e-3)
+    assert e.value.status == ccd.CCD_EINVAL and "outside" in str(e.value)
+    assert st.step.value == 1 and not torch.equal(P, p0)
