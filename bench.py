@@ -325,11 +325,11 @@ def main():
     for v in kernels.values():
         v["share"] = v["ms_per_step"] / total_ms
     # useful FP64 flops of one step, per family (unordered pairs, as executed)
-    fam_flops = {"ladder_update": nsolve * (info["flops_pp"] + info["flops_hh"] / 2),
+    fam_flops = {"ladder": nsolve * (info["flops_pp"] + info["flops_hh"] / 2),
                  "direct": nsolve * info["flops_hh"] / 2,
                  "ring": nsolve * info["flops_ring"]}
     ring_ms = sum(kernels.get(k, {}).get("ms_per_step", 0.0) for k in ("ring", "ring_small"))
-    fam_ms = {"ladder_update": kernels.get("ladder_update", {}).get("ms_per_step", 0.0),
+    fam_ms = {"ladder": kernels.get("ladder", {}).get("ms_per_step", 0.0),
               "direct": kernels.get("direct", {}).get("ms_per_step", 0.0), "ring": ring_ms}
     for k in fam_ms:
         if fam_ms[k] > 0:
@@ -337,10 +337,10 @@ def main():
     # dominant kernel: the longest average launch (the ring family is four
     # launches of separate kernels, the ladder one launch)
     per_launch = {k: fam_ms[k] / max(1.0, kernels.get(k, {}).get("launches_per_step", 1.0))
-                  for k in ("ladder_update", "direct") if fam_ms[k] > 0}
+                  for k in ("ladder", "direct") if fam_ms[k] > 0}
     dom = max(per_launch, key=lambda k: per_launch[k])
     achieved = fam_flops[dom] / (per_launch[dom] * 1e-3) / 1e12
-    roof = {"kernel": "k_ladder" if dom == "ladder_update" else "k_direct", "bound": "mfma",
+    roof = {"kernel": "k_ladder" if dom == "ladder" else "k_direct", "bound": "mfma",
             "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP64_TFLOPS, "traffic": measured_traffic(dom),
             "ms_per_launch": per_launch[dom], "flops_per_launch": fam_flops[dom]}

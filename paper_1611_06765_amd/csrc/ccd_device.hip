@@ -107,7 +107,6 @@ struct DevPtrs {
     const int32_t* pgi;      // per problem: index inside the group
     const double* pscale;    // per problem: rho, 2 pi / L, L^3 / 1000 (network features)
     const Item* it_elem;     // elementwise items, all channels
-    const Item* it_nsz0;     // elementwise items, S_z != 0 channels
     const Item* it_ladder;   // ladder items (S_z = 0)
     const int32_t* it_sz0;   // S_z = 0 channel ids
     const Item* it_dchi;     // (group, first state)
@@ -117,7 +116,7 @@ struct DevPtrs {
     const Item* it_ring_s;   // (primary cross channel with n <= 16, problem in group)
     const Item* it_ring_b;   // (primary cross channel with n > 16, problem in group)
     const Item* it_lg;       // (ladder item, problem in group)
-    const Item* it_ng;       // (S_z != 0 elementwise item, problem in group)
+    const Item* it_ue;       // (elementwise item, problem in group): the update
     double* t[2];
     double* vt;              // <ab||ij>
     double* chh;
@@ -129,7 +128,7 @@ struct DevPtrs {
     double* zc;              // ring result: two slots per amplitude, canonical order
     double* rowX;            // per row: one-body intermediates of a and b
     double* colX;            // per column: one-body intermediates of i and j
-    double* epart;
+    double* rmm;             // ladder sums of the S_z = 0 amplitudes (t layout)
     double* epart_elem;
     double* ecorr;
     double* eprev;
@@ -844,16 +843,16 @@ __global__ void __launch_bounds__(256) k_onebody(DevPtrs d) {
     }
 }
 
-// fused S_z = 0 update per (64-row tile, 16-column tile of a channel, problem).
-// Wave w owns rows 16w .. 16w+15 of the tile.  The pp ladder runs on MFMA with
+// ladder sums per (64-row tile, 16-column tile of an S_z = 0 channel, problem):
+// 1/2 sum_cd <ab||cd> t_ij^cd + 1/2 sum_kl t_kl^ab chi_klij into rmm.  Wave w
+// owns rows 16w .. 16w+15 of the tile.  The pp ladder runs on MFMA with
 // <ab||cd> generated per lane in the A-operand layout from W(m) in LDS, over
 // chunks of kKP particle-pair rows of t staged through registers one chunk
-// ahead.  Then the hh ladder (MFMA), the ring term, one-body terms,
-// t_new = R / eps_ij^ab, mixing and the energy partial sum, all in FP64.  P
-// selects the precision of the two ladder contractions.
+// ahead; then the hh ladder on MFMA.  It needs t and chi_klij only, so it runs
+// beside the ring.  P selects the precision of the two contractions.
 constexpr int kKP = 128;  // particle-pair columns staged per barrier
 template <int P>
-__global__ void __launch_bounds__(256, 3) k_ladder(DevPtrs d, int cur, double alpha, uint32_t mask, int n_items) {
+__global__ void __launch_bounds__(256, 3) k_ladder(DevPtrs d, int cur, uint32_t mask, int n_items) {
     using ET = typename AccT<P>::E;   // element type of the generated operand
     using AT = typename AccT<P>::T;   // accumulator
     __shared__ ET lutS[kMaxLut];
@@ -861,7 +860,6 @@ __global__ void __launch_bounds__(256, 3) k_ladder(DevPtrs d, int cur, double al
     __shared__ __attribute__((aligned(16))) char tks[P == P_F64 ? kKP * 16 * 8 : (P == P_F32 ? kKP * 16 * 4 : 16 * (kKP + 8) * 2)];
     // per staged column cd: (n_c packed as int8 x, y, z, 0; |n_c|^2 | |n_d|^2 << 10 | spin(c) << 20)
     __shared__ int2 cvi[kKP];
-    __shared__ double sh[4];
     for (int bi = blockIdx.x; bi < n_items; bi += gridDim.x) {
     const Item lg = d.it_lg[bi];
     if (lg.chan < 0) continue;
@@ -875,7 +873,6 @@ __global__ void __launch_bounds__(256, 3) k_ladder(DevPtrs d, int cur, double al
     const bool act = d.active[G.p0 + g] != 0;
     const bool pp_on = act && (mask & CCD_T_PP) != 0;
     const bool hh_on = act && (mask & (CCD_T_HH | CCD_T_QHH)) != 0;
-    const bool ring_on = (mask & (CCD_T_RING | CCD_T_QRING)) != 0;
     const int64_t T0 = G.t_base + g * G.n_amp + c.t_off;
     const double* tcur = d.t[cur] + T0;
 
@@ -936,7 +933,6 @@ __global__ void __launch_bounds__(256, 3) k_ladder(DevPtrs d, int cur, double al
         }
         if (threadIdx.x < kKP) cvi[threadIdx.x] = cv;
     };
-    double es = 0.0;
     for (int ct = ct0; ct < ct0 + 1; ct++) {
         const int col = ct * 16 + (lane & 15);
         AT acc = {0, 0, 0, 0}, acc2 = {0, 0, 0, 0};
@@ -1002,71 +998,61 @@ __global__ void __launch_bounds__(256, 3) k_ladder(DevPtrs d, int cur, double al
         }
 #pragma unroll
         for (int r = 0; r < 4; r++) acc[r] += acc2[r];
-        // epilogue (FP64): this lane owns rows orow(lane, r) of the wave's 16 rows, column col
-        const double* rowE = d.rowE + G.rowa_base + g * G.n_rows_all + c.rowa_off;
-        const double* rowX = d.rowX + G.rowa_base + g * G.n_rows_all + c.rowa_off;
-        double cE = 0.0, cX = 0.0;
-        if (col < nhh) {
-            cE = d.colE[G.cola_base + g * G.n_cols_all + c.cola_off + col];
-            cX = d.colX[G.cola_base + g * G.n_cols_all + c.cola_off + col];
-        }
+        // this lane owns rows orow(lane, r) of the wave's 16 rows, column col
+        if (act) {
 #pragma unroll
-        for (int r = 0; r < 4; r++) {
-            const int row = r0 + 16 * w + orow<P>(lane, r);
-            if (row < npp && col < nhh) {
-                const int64_t e = (int64_t)row * nhh + col;
-                const double tc = tcur[e], v = d.vt[T0 + e];
-                double tm = tc;
-                if (act) {
-                    double R = v + (double)acc[r];
-                    if (ring_on) R += ring_term(d, G, g, c.t_off + e);
-                    R += (rowX[row] - cX) * tc;
-                    tm = alpha * (R / (cE - rowE[row])) + (1.0 - alpha) * tc;
-                }
-                d.t[cur ^ 1][T0 + e] = tm;
-                es += v * tm;
+            for (int r = 0; r < 4; r++) {
+                const int row = r0 + 16 * w + orow<P>(lane, r);
+                if (row < npp && col < nhh) d.rmm[T0 + (int64_t)row * nhh + col] = (double)acc[r];
             }
         }
     }
-    double s = block_sum256(es, sh);
-    const int nitem = G.ladder_hi - G.ladder_lo;
-    if (threadIdx.x == 0) d.epart[G.epart_base + g * nitem + (litem - G.ladder_lo)] = s;
     }
 }
 
-// update of the S_z = +-1 blocks: only the ring and one-body terms survive
+// the update of every amplitude per (elementwise item, problem):
+// R = <ab||ij> + ladder sums (S_z = 0) + ring slots + one-body terms,
+// t_new = R / eps_ij^ab, mixing, and the energy partial of the item
 __global__ void __launch_bounds__(256) k_update(DevPtrs d, int cur, double alpha, uint32_t mask, int n_items) {
-    for (int bi = blockIdx.x; bi < n_items; bi += gridDim.x) {
-    const Item ig = d.it_ng[bi];
-    if (ig.chan < 0) continue;
-    const Item it = d.it_nsz0[ig.chan];
-    const int g = ig.start;
-    const DevChan c = d.chans[it.chan];
-    const DevGroup G = d.groups[c.group];
+    __shared__ double sh[4];
     const bool ring_on = (mask & (CCD_T_RING | CCD_T_QRING)) != 0;
-    const int nel = c.nhh * c.npp;
-    const bool act = d.active[G.p0 + g] != 0;
-    const int64_t T0 = G.t_base + g * G.n_amp + c.t_off;
-    const double* rowE = d.rowE + G.rowa_base + g * G.n_rows_all + c.rowa_off;
-    const double* rowX = d.rowX + G.rowa_base + g * G.n_rows_all + c.rowa_off;
-    const double* colE = d.colE + G.cola_base + g * G.n_cols_all + c.cola_off;
-    const double* colX = d.colX + G.cola_base + g * G.n_cols_all + c.cola_off;
-    for (int k = 0; k < kElemChunk / 256; k++) {
-        int e = it.start + threadIdx.x + 256 * k;
-        if (e < nel && e < it.start + kElemChunk) {
-            const int64_t E = T0 + e;
-            double tc = d.t[cur][E];
-            double tm = tc;
-            if (act) {
-                int r = e / c.nhh, col = e - r * c.nhh;
-                double R = d.vt[E];
-                if (ring_on) R += ring_term(d, G, g, c.t_off + e);
-                R += (rowX[r] - colX[col]) * tc;
-                tm = alpha * (R / (colE[col] - rowE[r])) + (1.0 - alpha) * tc;
+    const bool lad_on = (mask & (CCD_T_PP | CCD_T_HH | CCD_T_QHH)) != 0;
+    for (int bi = blockIdx.x; bi < n_items; bi += gridDim.x) {
+        const Item ig = d.it_ue[bi];
+        if (ig.chan < 0) continue;
+        const int item = ig.chan, g = ig.start;
+        const Item it = d.it_elem[item];
+        const DevChan c = d.chans[it.chan];
+        const DevGroup G = d.groups[c.group];
+        const int nel = c.nhh * c.npp;
+        const bool act = d.active[G.p0 + g] != 0;
+        const bool lad = lad_on && c.sz == 0;
+        const int64_t T0 = G.t_base + g * G.n_amp + c.t_off;
+        const double* rowE = d.rowE + G.rowa_base + g * G.n_rows_all + c.rowa_off;
+        const double* rowX = d.rowX + G.rowa_base + g * G.n_rows_all + c.rowa_off;
+        const double* colE = d.colE + G.cola_base + g * G.n_cols_all + c.cola_off;
+        const double* colX = d.colX + G.cola_base + g * G.n_cols_all + c.cola_off;
+        double es = 0.0;
+        for (int k = 0; k < kElemChunk / 256; k++) {
+            const int e = it.start + threadIdx.x + 256 * k;
+            if (e < nel && e < it.start + kElemChunk) {
+                const int64_t E = T0 + e;
+                const double tc = d.t[cur][E], v = d.vt[E];
+                double tm = tc;
+                if (act) {
+                    const int r = e / c.nhh, col = e - r * c.nhh;
+                    double R = v;
+                    if (lad) R += d.rmm[E];
+                    if (ring_on) R += ring_term(d, G, g, c.t_off + e);
+                    R += (rowX[r] - colX[col]) * tc;
+                    tm = alpha * (R / (colE[col] - rowE[r])) + (1.0 - alpha) * tc;
+                }
+                d.t[cur ^ 1][E] = tm;
+                es += v * tm;
             }
-            d.t[cur ^ 1][E] = tm;
         }
-    }
+        const double s = block_sum256(es, sh);
+        if (threadIdx.x == 0) d.epart_elem[G.eelem_base + g * (G.elem_hi - G.elem_lo) + (item - G.elem_lo)] = s;
     }
 }
 
@@ -1079,8 +1065,8 @@ __global__ void __launch_bounds__(256) k_energy(DevPtrs d, double tol, double to
     __shared__ double sh[4];
     const int p = blockIdx.x;
     const DevGroup G = d.groups[d.pgrp[p]];
-    const int g = d.pgi[p], n = G.ladder_hi - G.ladder_lo;
-    const double* part = d.epart + G.epart_base + g * n;
+    const int g = d.pgi[p], n = G.elem_hi - G.elem_lo;
+    const double* part = d.epart_elem + G.eelem_base + g * n;
     double s = 0.0;
     for (int x = threadIdx.x; x < n; x += 256) s += part[x];
     double e = block_sum256(s, sh);
@@ -1110,8 +1096,10 @@ __global__ void __launch_bounds__(256) k_energy(DevPtrs d, double tol, double to
 // context
 // --------------------------------------------------------------------------
 enum Family { F_INIT = 0, F_DIRECT, F_DCHI, F_RING_S, F_RING_B, F_LADDER, F_UPDATE, F_ENERGY, F_NUM };
-static const char* kFamilyNames[F_NUM] = {"init", "direct", "dchi", "ring_small", "ring", "ladder_update",
-                                          "update_sz1", "energy"};
+// one name per family, in the order above (the ladder family is the pp + hh
+// ladder sums; update covers every amplitude)
+static const char* kFamilyNames[F_NUM] = {"init", "direct", "dchi", "ring_small", "ring", "ladder",
+                                          "update", "energy"};
 
 struct Region {
     size_t off = 0, bytes = 0;
@@ -1140,16 +1128,16 @@ struct ccd_ctx {
     std::vector<int32_t> ppinfo;
     std::vector<int32_t> st, hh, pp, phmem, phmap, zs, csr_ptr, csr_idx, pgrp, pgi, it_sz0;
     std::vector<double> eps, lut, rowE, colE, pscale;
-    std::vector<Item> it_elem, it_nsz0, it_ladder, it_dchi, it_direct, it_ring_s, it_ring_b, it_lg, it_ng, it_dsub,
+    std::vector<Item> it_elem, it_ladder, it_dchi, it_direct, it_ring_s, it_ring_b, it_lg, it_ue, it_dsub,
         it_dsum;
     int64_t n_dpart = 0, n_dcolp = 0;
     int ring_lo[4] = {0}, ring_n[4] = {0};  // big pair items by padded size n16 = 32, 48, 64, 80
     std::vector<int64_t> prob_t0;  // amplitude index of each problem (caller order)
     std::vector<int> slot_of;      // caller problem -> slot (group order) of the device flags
     int64_t NT = 0;
-    int n_rows = 0, n_cols = 0, n_chh = 0, n_eps = 0, n_epart = 0, n_eparte = 0, max_ph = 0;
+    int n_rows = 0, n_cols = 0, n_chh = 0, n_eps = 0, n_eparte = 0, max_ph = 0;
     // workspace
-    Region r_static, r_t0, r_t1, r_vt, r_chh, r_rows, r_cols, r_dchi, r_zc, r_rowx, r_colx, r_epart, r_eparte,
+    Region r_static, r_t0, r_t1, r_vt, r_chh, r_rows, r_cols, r_dchi, r_zc, r_rowx, r_colx, r_rmm, r_eparte,
         r_ecorr, r_eprev, r_active, r_sweeps, r_ehist, r_dpart, r_dcolp, r_dprev, r_streak;
     size_t ws_bytes = 0;
     char* ws = nullptr;
@@ -1167,10 +1155,10 @@ struct ccd_ctx {
     int32_t tune[CCD_TUNE_LEN] = {0};
     // replayable sweep graphs
     hipStream_t cap_stream = nullptr;
-    // three more streams for the ring size buckets, forked from and joined back
-    // into the caller's stream with events (default priority)
+    // three more streams (ring size buckets, ladder sums), forked from and
+    // joined back into the caller's stream with events (default priority)
     hipStream_t aux[3] = {nullptr, nullptr, nullptr};
-    hipEvent_t ev_fork = nullptr, ev_join[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t ev_fork = nullptr, ev_mid = nullptr, ev_join[3] = {nullptr, nullptr, nullptr};
     bool aux_ok = false;
     std::vector<GraphEntry> graphs;
 };
@@ -1183,8 +1171,8 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
     X(phmem, int32_t) X(phmap, int32_t) X(zs, int32_t) X(rowE, double) X(colE, double) \
     X(csr_ptr, int32_t)                                                   \
     X(csr_idx, int32_t) X(pgrp, int32_t) X(pgi, int32_t) X(pscale, double) \
-    X(it_elem, Item) X(it_nsz0, Item) X(it_ladder, Item) X(it_sz0, int32_t) X(it_dchi, Item) \
-    X(it_direct, Item) X(it_ring_s, Item) X(it_ring_b, Item) X(it_lg, Item) X(it_ng, Item) \
+    X(it_elem, Item) X(it_ladder, Item) X(it_sz0, int32_t) X(it_dchi, Item) \
+    X(it_direct, Item) X(it_ring_s, Item) X(it_ring_b, Item) X(it_lg, Item) X(it_ue, Item) \
     X(it_dsub, Item) X(it_dsum, Item) X(ppinfo, int32_t)
 
 static DevPtrs make_ptrs(ccd_ctx* c) {
@@ -1194,9 +1182,9 @@ static DevPtrs make_ptrs(ccd_ctx* c) {
     const void* p_st; const void* p_eps; const void* p_lut; const void* p_dgroups; const void* p_dchans;
     const void* p_dph; const void* p_hh; const void* p_pp; const void* p_phmem; const void* p_phmap;
     const void* p_csr_ptr; const void* p_csr_idx; const void* p_pgrp; const void* p_pgi;
-    const void* p_it_elem; const void* p_it_nsz0; const void* p_it_ladder; const void* p_it_sz0;
+    const void* p_it_elem; const void* p_it_ladder; const void* p_it_sz0;
     const void* p_it_dchi; const void* p_it_direct; const void* p_it_ring_s; const void* p_it_ring_b;
-    const void* p_it_lg; const void* p_it_ng; const void* p_zs; const void* p_rowE; const void* p_colE;
+    const void* p_it_lg; const void* p_it_ue; const void* p_zs; const void* p_rowE; const void* p_colE;
     const void* p_pscale; const void* p_it_dsub; const void* p_it_dsum; const void* p_ppinfo;
 #define TAKE(name, T)             \
     p_##name = base + o;          \
@@ -1208,12 +1196,12 @@ static DevPtrs make_ptrs(ccd_ctx* c) {
     d.hh = (const int32_t*)p_hh; d.pp = (const int32_t*)p_pp; d.phmem = (const int32_t*)p_phmem;
     d.phmap = (const int32_t*)p_phmap; d.csr_ptr = (const int32_t*)p_csr_ptr;
     d.csr_idx = (const int32_t*)p_csr_idx; d.pgrp = (const int32_t*)p_pgrp; d.pgi = (const int32_t*)p_pgi;
-    d.it_elem = (const Item*)p_it_elem; d.it_nsz0 = (const Item*)p_it_nsz0;
+    d.it_elem = (const Item*)p_it_elem;
     d.it_ladder = (const Item*)p_it_ladder; d.it_sz0 = (const int32_t*)p_it_sz0;
     d.it_dchi = (const Item*)p_it_dchi;
     d.it_direct = (const Item*)p_it_direct; d.it_ring_s = (const Item*)p_it_ring_s;
     d.it_ring_b = (const Item*)p_it_ring_b; d.it_lg = (const Item*)p_it_lg;
-    d.it_ng = (const Item*)p_it_ng; d.zs = (const int32_t*)p_zs;
+    d.it_ue = (const Item*)p_it_ue; d.zs = (const int32_t*)p_zs;
     d.rowE = (const double*)p_rowE; d.colE = (const double*)p_colE;
     d.pscale = (const double*)p_pscale;
     d.it_dsub = (const Item*)p_it_dsub; d.it_dsum = (const Item*)p_it_dsum;
@@ -1230,7 +1218,7 @@ static DevPtrs make_ptrs(ccd_ctx* c) {
     d.zc = (double*)(base + c->r_zc.off);
     d.rowX = (double*)(base + c->r_rowx.off);
     d.colX = (double*)(base + c->r_colx.off);
-    d.epart = (double*)(base + c->r_epart.off);
+    d.rmm = (double*)(base + c->r_rmm.off);
     d.epart_elem = (double*)(base + c->r_eparte.off);
     d.ecorr = (double*)(base + c->r_ecorr.off);
     d.eprev = (double*)(base + c->r_eprev.off);
@@ -1279,7 +1267,7 @@ static void layout(ccd_ctx* c) {
     region(c->r_zc, (size_t)c->NT * 16);
     region(c->r_rowx, c->rowE.size() * 8);
     region(c->r_colx, c->colE.size() * 8);
-    region(c->r_epart, (size_t)c->n_epart * 8);
+    region(c->r_rmm, (size_t)c->NT * 8);
     region(c->r_eparte, (size_t)c->n_eparte * 8);
     region(c->r_ecorr, P * 8);
     region(c->r_eprev, P * 8);
@@ -1347,7 +1335,7 @@ static ccd_status assemble(ccd_ctx* c) {
     c->pgi.assign(P, 0);
     c->prob_t0.assign(P, 0);
     c->slot_of.assign(P, 0);
-    std::vector<std::pair<int, Item>> lg, ng, dir, dsum, rs, rb[4];
+    std::vector<std::pair<int, Item>> lg, ue, dir, dsum, rs, rb[4];
     std::vector<double> lg_cost;
     int64_t t_base = 0;
     int gi = 0, slot0 = 0;
@@ -1441,12 +1429,9 @@ static ccd_status assemble(ccd_ctx* c) {
             }
             const int nel = h.nhh * h.npp;
             for (int e0 = 0; e0 < nel; e0 += kElemChunk) {
+                const int ei = (int)c->it_elem.size();
                 c->it_elem.push_back({id, e0});
-                if (h.Sz != 0) {
-                    const int ei = (int)c->it_nsz0.size();
-                    c->it_nsz0.push_back({id, e0});
-                    for (int g = 0; g < D.G; g++) ng.push_back({slot0 + g, Item{ei, g}});
-                }
+                for (int g = 0; g < D.G; g++) ue.push_back({slot0 + g, Item{ei, g}});
             }
             c->dchans.push_back(dc);
         }
@@ -1458,8 +1443,6 @@ static ccd_status assemble(ccd_ctx* c) {
         c->n_dpart += (int64_t)D.G * dpart; c->n_dcolp += (int64_t)D.G * dcolp;
         D.rows_base = c->n_rows; D.cols_base = c->n_cols; D.chh_base = c->n_chh;
         c->n_rows += D.G * rows; c->n_cols += D.G * cols; c->n_chh += D.G * chh;
-        D.epart_base = c->n_epart;
-        c->n_epart += D.G * (D.ladder_hi - D.ladder_lo);
         D.eelem_base = c->n_eparte;
         c->n_eparte += D.G * (D.elem_hi - D.elem_lo);
         // one-body CSR
@@ -1522,7 +1505,7 @@ static ccd_status assemble(ccd_ctx* c) {
 
     if (c->csr_idx.empty()) c->csr_idx.push_back(0);
     c->it_lg = xcd_order_cost(lg, lg_cost);
-    c->it_ng = xcd_order(ng);
+    c->it_ue = xcd_order(ue);
     c->it_direct = xcd_order(dir);
     c->it_dsum = xcd_order(dsum);
     c->it_ring_s = xcd_order(rs, 4);
@@ -1666,14 +1649,15 @@ static ccd_status L_ring(ccd_ctx* c, const DevPtrs& d, int cur, uint32_t mask, i
 }
 
 template <int P>
-static ccd_status L_ladder(ccd_ctx* c, const DevPtrs& d, int cur, double alpha, uint32_t mask) {
+static ccd_status L_ladder(ccd_ctx* c, const DevPtrs& d, int cur, uint32_t mask) {
     const int n = (int)c->it_lg.size();
-    LAUNCH(F_LADDER, k_ladder<P>, grid_for(c, CCD_TUNE_LADDER, n), 256, 0, d, cur, alpha, mask, n);
+    if (mask & (CCD_T_PP | CCD_T_HH | CCD_T_QHH))
+        LAUNCH(F_LADDER, k_ladder<P>, grid_for(c, CCD_TUNE_LADDER, n), 256, 0, d, cur, mask, n);
     return CCD_OK;
 }
 
 static ccd_status L_update(ccd_ctx* c, const DevPtrs& d, int cur, double alpha, uint32_t mask) {
-    const int n = (int)c->it_ng.size();
+    const int n = (int)c->it_ue.size();
     LAUNCH(F_UPDATE, k_update, grid_for(c, CCD_TUNE_UPDATE, n), 256, 0, d, cur, alpha, mask, n);
     return CCD_OK;
 }
@@ -1686,33 +1670,38 @@ struct StreamSwap {
     ~StreamSwap() { c->stream = saved; }
 };
 
-// The ring reads only t[cur] and static tables, and writes only the pair
-// blocks, so its size buckets run on the three auxiliary streams beside the
-// chi_klij product and the one-body terms; the ladder, which reads all of
-// them, waits for the join.  With kernel timing on, everything stays on the
-// context's stream so that the per-family event times are not overlapped.
+// The ring reads only t[cur] and static tables and writes only the ring
+// slots; the ladder sums read t[cur] and chi_klij and write only rmm.  So the
+// ring size buckets run on two auxiliary streams from the start of the sweep,
+// the ladder on a third once chi_klij is complete, and the one-body sums on
+// the context's stream; the update waits for all of them.  With kernel timing
+// on, everything stays on the context's stream so that the per-family event
+// times are not overlapped.
 template <int P>
-static ccd_status launch_contractions(ccd_ctx* c, const DevPtrs& d, int cur, double alpha, uint32_t mask) {
-    const bool fork = c->aux_ok && !c->timing && (mask & (CCD_T_RING | CCD_T_QRING)) != 0;
+static ccd_status launch_contractions(ccd_ctx* c, const DevPtrs& d, int cur, uint32_t mask) {
+    const bool fork = c->aux_ok && !c->timing;
     ccd_status s = CCD_OK;
     if (fork) {
         HIP_TRY(hipEventRecord(c->ev_fork, c->stream));
-        for (int k = 0; k < 3; k++) HIP_TRY(hipStreamWaitEvent(c->aux[k], c->ev_fork, 0));
+        for (int k = 0; k < 2; k++) HIP_TRY(hipStreamWaitEvent(c->aux[k], c->ev_fork, 0));
         {
             StreamSwap sw(c, c->aux[0]);
             s = L_ring<P>(c, d, cur, mask, 2);
             if (s == CCD_OK) s = L_ring<P>(c, d, cur, mask, 3);
+            if (s == CCD_OK) s = L_ring_small<P>(c, d, cur, mask);
         }
         if (s == CCD_OK) {
             StreamSwap sw(c, c->aux[1]);
             s = L_ring<P>(c, d, cur, mask, 1);
             if (s == CCD_OK) s = L_ring<P>(c, d, cur, mask, 0);
         }
-        if (s == CCD_OK) {
-            StreamSwap sw(c, c->aux[2]);
-            s = L_ring_small<P>(c, d, cur, mask);
-        }
         if (s == CCD_OK) s = L_direct<P>(c, d, cur, mask);
+        if (s == CCD_OK) {
+            HIP_TRY(hipEventRecord(c->ev_mid, c->stream));
+            HIP_TRY(hipStreamWaitEvent(c->aux[2], c->ev_mid, 0));
+            StreamSwap sw(c, c->aux[2]);
+            s = L_ladder<P>(c, d, cur, mask);
+        }
         if (s == CCD_OK) s = L_dchi(c, d, mask);
         for (int k = 0; k < 3; k++) {
             HIP_TRY(hipEventRecord(c->ev_join[k], c->aux[k]));
@@ -1723,8 +1712,8 @@ static ccd_status launch_contractions(ccd_ctx* c, const DevPtrs& d, int cur, dou
         if (s == CCD_OK) s = L_dchi(c, d, mask);
         if (s == CCD_OK) s = L_ring_small<P>(c, d, cur, mask);
         if (s == CCD_OK) s = L_ring<P>(c, d, cur, mask);
+        if (s == CCD_OK) s = L_ladder<P>(c, d, cur, mask);
     }
-    if (s == CCD_OK) s = L_ladder<P>(c, d, cur, alpha, mask);
     return s;
 }
 
@@ -1749,9 +1738,9 @@ static hipError_t set_ring_attrs() {
 static ccd_status sweep(ccd_ctx* c, double alpha, double tol, double tol_rel, int rule, uint32_t mask, int prec) {
     DevPtrs d = make_ptrs(c);
     const int cur = c->cur;
-    ccd_status s = prec == CCD_PREC_BF16 ? launch_contractions<P_BF16>(c, d, cur, alpha, mask)
-                 : prec == CCD_PREC_FP32 ? launch_contractions<P_F32>(c, d, cur, alpha, mask)
-                                         : launch_contractions<P_F64>(c, d, cur, alpha, mask);
+    ccd_status s = prec == CCD_PREC_BF16 ? launch_contractions<P_BF16>(c, d, cur, mask)
+                 : prec == CCD_PREC_FP32 ? launch_contractions<P_F32>(c, d, cur, mask)
+                                         : launch_contractions<P_F64>(c, d, cur, mask);
     if (s != CCD_OK) return s;
     s = L_update(c, d, cur, alpha, mask);
     if (s != CCD_OK) return s;
@@ -1848,7 +1837,7 @@ static ccd_status autotune_impl(ccd_ctx* c, int reps, double* best_ms, hipEvent_
     const int cur = c->cur;
     const uint32_t mask = CCD_T_ALL;
     const double alpha = 0.5;
-    ccd_status s = launch_contractions<P>(c, d, cur, alpha, mask);
+    ccd_status s = launch_contractions<P>(c, d, cur, mask);
     if (s == CCD_OK) s = L_update(c, d, cur, alpha, mask);
     if (s != CCD_OK) return s;
     struct Spec {
@@ -1865,7 +1854,7 @@ static ccd_status autotune_impl(ccd_ctx* c, int reps, double* best_ms, hipEvent_
         {CCD_TUNE_RING_NW64, 2, {0, 1}, [&] { return L_ring<P>(c, d, cur, mask, 2); }},
         {CCD_TUNE_RING_NW80, 2, {0, 1}, [&] { return L_ring<P>(c, d, cur, mask, 3); }},
         {CCD_TUNE_RING, 4, {0, 1, 2, 4}, [&] { return L_ring<P>(c, d, cur, mask); }},
-        {CCD_TUNE_LADDER, 4, {0, 1, 2, 4}, [&] { return L_ladder<P>(c, d, cur, alpha, mask); }},
+        {CCD_TUNE_LADDER, 4, {0, 1, 2, 4}, [&] { return L_ladder<P>(c, d, cur, mask); }},
         {CCD_TUNE_UPDATE, 4, {0, 1, 2, 4}, [&] { return L_update(c, d, cur, alpha, mask); }},
     };
     for (const Spec& sp : specs) {
@@ -1941,7 +1930,8 @@ ccd_status ccd_bind_workspace(ccd_ctx* c, void* ptr, size_t bytes) {
     if (((uintptr_t)ptr) & 255) { set_error("workspace must be 256-byte aligned"); return CCD_EINVAL; }
     c->ws = (char*)ptr;
     if (!c->aux_ok) {
-        bool ok = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) == hipSuccess;
+        bool ok = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) == hipSuccess &&
+                  hipEventCreateWithFlags(&c->ev_mid, hipEventDisableTiming) == hipSuccess;
         for (int k = 0; k < 3 && ok; k++)
             ok = hipStreamCreateWithFlags(&c->aux[k], hipStreamNonBlocking) == hipSuccess &&
                  hipEventCreateWithFlags(&c->ev_join[k], hipEventDisableTiming) == hipSuccess;
@@ -2320,6 +2310,7 @@ void ccd_destroy(ccd_ctx* c) {
         if (c->ev_join[k]) (void)hipEventDestroy(c->ev_join[k]);
     }
     if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_mid) (void)hipEventDestroy(c->ev_mid);
     if (!c->ev_pool.empty()) {
         if (!c->pending.empty()) (void)hipStreamSynchronize(c->stream);
         for (auto e : c->ev_pool) (void)hipEventDestroy(e);

@@ -51,7 +51,6 @@ struct DevGroup {
     int32_t n_rows, n_cols, n_chh;  // S_z = 0 rows, columns, chi_klij entries per problem
     int32_t rows_base, cols_base, chh_base;  // + g * n_rows / n_cols / n_chh
     int32_t ladder_lo, ladder_hi;   // ladder items of the group
-    int32_t epart_base;   // energy partial of (item, g): epart_base + g * n_items + local item
     int32_t elem_lo, elem_hi;       // elementwise items of the group
     int32_t eelem_base;   // elementwise energy partial of (item, g)
     int32_t csr_off;      // one-body CSR row pointers of the group: csr_off + s
