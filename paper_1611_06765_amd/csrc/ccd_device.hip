@@ -586,7 +586,7 @@ __device__ __forceinline__ void pair_stage(const DevPtrs& d, const Item it, int 
 }
 
 // A = gathered T~_Q (signed), B = Vbar, zero padded; gathers issued 8 at a time.
-// With TR set (BF16), the transposes At = A^T and Bt = B^T are written too.
+// With TR set (BF16), A, At = A^T and Bt = B^T are written instead of A and B.
 template <typename E, int n16, int lda, int stride, bool TR>
 __device__ __forceinline__ void pair_fill(const PairCtx& r, const int32_t* qs, const int32_t* ps,
                                           const double* lutS, E* A, E* B, E* At, E* Bt, int t0, bool qring) {
@@ -613,10 +613,11 @@ __device__ __forceinline__ void pair_fill(const PairCtx& r, const int32_t* qs, c
                     b = vas(lutS, ps[2 * u + 1], qs[2 * x + 1], ps[2 * u], qs[2 * x]);
                 const E av = (E)((m[j] & 1) ? -tv[j] : tv[j]), bv = (E)b;
                 A[u * lda + x] = av;
-                B[u * lda + x] = bv;
                 if constexpr (TR) {
                     At[x * lda + u] = av;
                     Bt[x * lda + u] = bv;
+                } else {
+                    B[u * lda + x] = bv;
                 }
             }
         }
@@ -711,16 +712,18 @@ __device__ __forceinline__ void pair_body(const DevPtrs& d, const Item it, int c
     double* lutS = (double*)lds;
     int32_t* qs = (int32_t*)(lutS + kMaxLut);
     int32_t* ps = qs + 2 * kMaxPH;
+    // FP64 / FP32: A and B (B later holds X, then V_P);
+    // BF16: A, At = A^T and Bt = B^T (Bt later holds X, then V_P^T)
     E* A = (E*)(lds + pair_mat_off());
     E* B = A + rows * lda;
-    E* At = B + rows * lda;  // C for FP64 / FP32; A^T for BF16
-    E* Bt = At + rows * lda; // BF16 only
+    E* At = B;                // BF16 only (same storage as B)
+    E* Bt = At + rows * lda;  // BF16 only
     const bool qring = (mask & CCD_T_QRING) != 0, ring = (mask & CCD_T_RING) != 0;
     if (live) {
         pair_stage(d, it, memQ, memP, lo, r.n, qs, ps, lutS, tid, 64 * NW);
         if constexpr (P == P_BF16) {
-            // zero the K padding (rows and columns n16 .. kpad) of all four matrices
-            for (int e = tid; e < 4 * rows * lda; e += 64 * NW) A[e] = (E)0.0f;
+            // zero the K padding (rows and columns n16 .. kpad) of all three matrices
+            for (int e = tid; e < 3 * rows * lda; e += 64 * NW) A[e] = (E)0.0f;
         }
     }
     __syncthreads();
@@ -740,10 +743,9 @@ __device__ __forceinline__ void pair_body(const DevPtrs& d, const Item it, int c
             else xq[k] = mm4<P>(A, B, lda, tx, ty, kq, lane, xq[k]);
         }
     }
-    __syncthreads();  // every wave has finished reading B (and Bt)
-    // X = A B + V_Q into B's place; V_P into C (FP64 / FP32) or its transpose
-    // into Bt's place (BF16); zero outside the block
-    E* C = P == P_BF16 ? Bt : At;
+    __syncthreads();  // every wave has finished reading B (Bt)
+    // X = A B + V_Q replaces B (FP64 / FP32) or Bt (BF16), row-major; zero outside the block
+    E* XB = P == P_BF16 ? Bt : B;
 #pragma unroll
     for (int k = 0; k < TPW; k++) {
         const int tile = w + NW * k;
@@ -752,33 +754,51 @@ __device__ __forceinline__ void pair_body(const DevPtrs& d, const Item it, int c
 #pragma unroll
             for (int q = 0; q < 4; q++) {
                 const int x = tx * 16 + orow<P>(lane, q), y = ty * 16 + (lane & 15);
-                double xv = (double)xq[k][q], vp = 0.0;
-                if (ring && x < r.n && y < r.n) {
-                    xv += pair_vph(qs, lutS, x, y);
-                    vp = pair_vph(ps, lutS, x, y);
-                }
-                B[x * lda + y] = (E)xv;
-                if constexpr (P == P_BF16) C[y * lda + x] = (E)(float)vp;
-                else C[x * lda + y] = (E)vp;
+                double xv = (double)xq[k][q];
+                if (ring && x < r.n && y < r.n) xv += pair_vph(qs, lutS, x, y);
+                XB[x * lda + y] = (E)xv;
             }
         }
     }
     __syncthreads();
-    // Out = X A + A V_P
+    // Out = X A, accumulators kept across the next barrier
+    AT acc[TPW];
+#pragma unroll
+    for (int k = 0; k < TPW; k++) {
+        acc[k] = AT{0, 0, 0, 0};
+        const int tile = w + NW * k;
+        if (live && tile < ntt) {
+            const int tu = tile / nt, ty = tile - tu * nt;
+            if constexpr (P == P_BF16) acc[k] = mmbf(XB, At, lda, tu, ty, kq, lane, acc[k]);
+            else acc[k] = mm4<P>(XB, A, lda, tu, ty, kq, lane, acc[k]);
+        }
+    }
+    __syncthreads();  // every wave has finished reading X
+    // V_P replaces X: row-major for FP64 / FP32, transposed for BF16
+#pragma unroll
+    for (int k = 0; k < TPW; k++) {
+        const int tile = w + NW * k;
+        if (live && tile < ntt) {
+            const int tx = tile / nt, ty = tile - tx * nt;
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const int x = tx * 16 + orow<P>(lane, q), y = ty * 16 + (lane & 15);
+                const double vp = (ring && x < r.n && y < r.n) ? pair_vph(ps, lutS, x, y) : 0.0;
+                if constexpr (P == P_BF16) XB[y * lda + x] = (E)(float)vp;
+                else XB[x * lda + y] = (E)vp;
+            }
+        }
+    }
+    __syncthreads();
+    // Out += A V_P
 #pragma unroll
     for (int k = 0; k < TPW; k++) {
         const int tile = w + NW * k;
         if (live && tile < ntt) {
             const int tu = tile / nt, ty = tile - tu * nt;
-            AT acc = {0, 0, 0, 0};
-            if constexpr (P == P_BF16) {
-                acc = mmbf(B, At, lda, tu, ty, kq, lane, acc);  // X A
-                acc = mmbf(A, C, lda, tu, ty, kq, lane, acc);   // A V_P
-            } else {
-                acc = mm4<P>(B, A, lda, tu, ty, kq, lane, acc);
-                acc = mm4<P>(A, C, lda, tu, ty, kq, lane, acc);
-            }
-            pair_store<P>(r, acc, tu, ty, lane);
+            if constexpr (P == P_BF16) acc[k] = mmbf(A, XB, lda, tu, ty, kq, lane, acc[k]);
+            else acc[k] = mm4<P>(A, XB, lda, tu, ty, kq, lane, acc[k]);
+            pair_store<P>(r, acc[k], tu, ty, lane);
         }
     }
 }
@@ -788,7 +808,7 @@ template <int P> __host__ __device__ constexpr size_t pair_lds(int n16) {
     const size_t kpad = P == P_BF16 ? ((n16 + 31) & ~31) : n16;
     const size_t lda = P == P_BF16 ? kpad + 8 : n16 + 1;
     const size_t rows = P == P_BF16 ? kpad : n16;
-    const size_t mats = P == P_BF16 ? 4 : 3;
+    const size_t mats = P == P_BF16 ? 3 : 2;
     return pair_mat_off() + mats * rows * lda * es;
 }
 
