@@ -297,6 +297,9 @@ def main():
         del x, y
 
     ctx.iterate(mixing=MIXING, tol=0.0, max_iter=max(1, args.warmup))
+    # launch shapes tuned on this workload (outside the timed region)
+    tuning, _ = ctx.autotune(ccd.CCD_PREC_FP64, reps=5)
+    ctx.iterate(mixing=MIXING, tol=0.0, max_iter=2)
     torch.cuda.synchronize()
 
     # timed region
@@ -362,7 +365,7 @@ def main():
         "config": {"workload": "PNM CCD sweep, N=66, n^2<=20 (778 states), Minnesota, "
                                "10 densities 0.02-0.20 fm^-3 batched, FP64, mixing 0.5",
                    "solves_per_step": nsolve, "states": info["n_states"],
-                   "amplitudes_per_solve": info["n_amplitudes"]},
+                   "amplitudes_per_solve": info["n_amplitudes"], "tuning": [int(x) for x in tuning]},
         "tflops_effective_ordered": flops_ord / (ms_step * 1e-3) / 1e12,
         "tflops_executed": flops_exec / (ms_step * 1e-3) / 1e12,
         "ms_per_step_with_events": el_ev * 1e3 / args.steps,
