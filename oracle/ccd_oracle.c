@@ -14,6 +14,10 @@
  *     spherical cutoff, holes = lowest N states            (sec. "Single-particle
  *     basis for infinite matter"; the model-space loop of sec. "Developing a CCD
  *     code for infinite matter")
+ *   - twisted boundary conditions: momenta k = (2 pi n + theta) / L, states
+ *     ordered by energy and the lowest N filled for each twist  (the
+ *     twist-averaging passage and its algorithm, sec. "Developing a CCD code
+ *     for infinite matter")
  *   - Minnesota interaction from its operator form, with the spin-exchange
  *     algebra evaluated as explicit 4x4 matrices in two-spin space and the
  *     Gaussian Fourier transform                         (sec. "Two-body
@@ -65,6 +69,7 @@ typedef struct {
     int ns;        /* number of single-particle states */
     int R;         /* floor(sqrt(nmax2)) */
     double rho, L, hb2m; /* density (fm^-3), box side (fm), hbar^2/m (MeV fm^2) */
+    double theta[3];     /* twist angles (radians); 0 = periodic, pi = antiperiodic */
     double Va[3], ka[3]; /* Minnesota strengths / ranges, channels R, T, S */
     double Oa[3][4][4];  /* spin operators of the three channels, two-spin basis */
     int *nx, *ny, *nz, *sz; /* sz = -1 or +1 (twice s_z) */
@@ -145,18 +150,28 @@ void orc_pnm_free(orc_pnm* h) {
 double orc_pnm_vas_direct(const orc_pnm* h, int p, int q, int r, int s);
 
 /* Model space: the loop over shells, then n_x, n_y, n_z, then s_z = -1/2, +1/2,
- * of sec. "Developing a CCD code for infinite matter"; the first N states are
- * holes.  Box side from rho = N / L^3, momenta k = 2 pi n / L, kinetic energy
- * hbar^2 k^2 / 2m (sec. "Single-particle basis for infinite matter").
- * Returns NULL if N does not close a shell or leaves no particle states. */
-orc_pnm* orc_pnm_new(int nmax2, int nparticles, double rho, double hb2m,
-                     double VR, double kR, double VT, double kT, double VS, double kS) {
-    if (nmax2 < 0 || nparticles <= 0 || rho <= 0.0) return NULL;
+ * of sec. "Developing a CCD code for infinite matter".  Box side from
+ * rho = N / L^3, momenta k = (2 pi n + theta) / L, kinetic energy
+ * hbar^2 k^2 / 2m (sec. "Single-particle basis for infinite matter" and the
+ * twist-averaging passage).  The states are then ordered by single-particle
+ * energy and the first N are holes ("Order States by Energy and Fill Holes").
+ * The order is decided on the exact-shaped key |n|^2 + 2 n.phi, phi = theta/2pi
+ * (the kinetic energy is (hbar^2/2m)(2pi/L)^2 (key + |phi|^2)), evaluated in
+ * FP64 left to right; equal keys keep the loop order.  Without a twist the key
+ * is the integer shell, so the loop order is kept as it is.
+ * Returns NULL if N leaves no particle states, if N is odd, or, without a
+ * twist, if N does not close a shell. */
+orc_pnm* orc_pnm_new_twist(int nmax2, int nparticles, double rho, double hb2m,
+                           double VR, double kR, double VT, double kT, double VS, double kS,
+                           double thx, double thy, double thz) {
+    if (nmax2 < 0 || nparticles <= 0 || rho <= 0.0 || (nparticles & 1)) return NULL;
     orc_pnm* h = (orc_pnm*)calloc(1, sizeof(orc_pnm));
     h->nmax2 = nmax2;
     h->nh = nparticles;
     h->rho = rho;
     h->hb2m = hb2m;
+    h->theta[0] = thx; h->theta[1] = thy; h->theta[2] = thz;
+    const int twisted = thx != 0.0 || thy != 0.0 || thz != 0.0;
     h->Va[0] = VR; h->ka[0] = kR;
     h->Va[1] = VT; h->ka[1] = kT;
     h->Va[2] = VS; h->ka[2] = kS;
@@ -178,14 +193,39 @@ orc_pnm* orc_pnm_new(int nmax2, int nparticles, double rho, double hb2m,
                     for (int s = -1; s <= 1; s += 2)
                         if (x * x + y * y + z * z == shell) {
                             h->nx[n] = x; h->ny[n] = y; h->nz[n] = z; h->sz[n] = s;
-                            int W = 2 * R + 1;
-                            h->grid[((((x + R) * W) + (y + R)) * W + (z + R)) * 2 + (s > 0)] = n;
                             n++;
                         }
     h->ns = n;
-    /* closed shell: last hole and first particle lie in different shells */
     if (nparticles >= n) { orc_pnm_free(h); return NULL; }
+    /* order by energy: insertion sort on the key, stable */
     {
+        const double phx = thx / (2.0 * M_PI), phy = thy / (2.0 * M_PI), phz = thz / (2.0 * M_PI);
+        double* key = (double*)malloc(sizeof(double) * n);
+        for (int p = 0; p < n; p++) {
+            int n2 = h->nx[p] * h->nx[p] + h->ny[p] * h->ny[p] + h->nz[p] * h->nz[p];
+            key[p] = (double)n2 + 2.0 * ((double)h->nx[p] * phx + (double)h->ny[p] * phy + (double)h->nz[p] * phz);
+        }
+        for (int p = 1; p < n; p++) {
+            double k = key[p];
+            int x = h->nx[p], y = h->ny[p], z = h->nz[p], s = h->sz[p];
+            int q = p - 1;
+            while (q >= 0 && key[q] > k) {
+                key[q + 1] = key[q];
+                h->nx[q + 1] = h->nx[q]; h->ny[q + 1] = h->ny[q]; h->nz[q + 1] = h->nz[q]; h->sz[q + 1] = h->sz[q];
+                q--;
+            }
+            key[q + 1] = k;
+            h->nx[q + 1] = x; h->ny[q + 1] = y; h->nz[q + 1] = z; h->sz[q + 1] = s;
+        }
+        free(key);
+    }
+    for (int p = 0; p < n; p++) {
+        int W = 2 * R + 1;
+        h->grid[((((h->nx[p] + R) * W) + (h->ny[p] + R)) * W + (h->nz[p] + R)) * 2 + (h->sz[p] > 0)] = p;
+    }
+    /* periodic box: closed shell, i.e. last hole and first particle lie in
+     * different shells */
+    if (!twisted) {
         int a = nparticles - 1, b = nparticles;
         int sa = h->nx[a] * h->nx[a] + h->ny[a] * h->ny[a] + h->nz[a] * h->nz[a];
         int sb = h->nx[b] * h->nx[b] + h->ny[b] * h->ny[b] + h->nz[b] * h->nz[b];
@@ -193,12 +233,14 @@ orc_pnm* orc_pnm_new(int nmax2, int nparticles, double rho, double hb2m,
     }
     build_spin_operators(h);
     h->tkin = (double*)malloc(sizeof(double) * n);
-    double dk = 2.0 * M_PI / h->L;
     for (int p = 0; p < n; p++) {
-        double kx = dk * h->nx[p], ky = dk * h->ny[p], kz = dk * h->nz[p];
+        double kx = (2.0 * M_PI * h->nx[p] + thx) / h->L;
+        double ky = (2.0 * M_PI * h->ny[p] + thy) / h->L;
+        double kz = (2.0 * M_PI * h->nz[p] + thz) / h->L;
         h->tkin[p] = 0.5 * hb2m * (kx * kx + ky * ky + kz * kz);
     }
-    /* exp cache for the fast element used by O3: index m = |n_p-n_q-n_r+n_s|^2 */
+    /* exp cache for the fast element used by O3: index m = |n_p-n_q-n_r+n_s|^2
+     * (the twist cancels in that combination of momenta) */
     h->mcache = 16 * 3 * R * R + 1;
     for (int a = 0; a < 3; a++) {
         h->gcache[a] = (double*)malloc(sizeof(double) * h->mcache);
@@ -218,18 +260,26 @@ orc_pnm* orc_pnm_new(int nmax2, int nparticles, double rho, double hb2m,
     return h;
 }
 
+/* periodic boundary conditions: no twist */
+orc_pnm* orc_pnm_new(int nmax2, int nparticles, double rho, double hb2m,
+                     double VR, double kR, double VT, double kT, double VS, double kS) {
+    return orc_pnm_new_twist(nmax2, nparticles, rho, hb2m, VR, kR, VT, kT, VS, kS, 0.0, 0.0, 0.0);
+}
+
 /* Non-antisymmetrised element <pq|v|rs> of the Minnesota interaction:
  * V_a/L^3 (pi/kappa_a)^{3/2} exp(-q^2 / 4 kappa_a) delta_{k_p+k_q, k_r+k_s}
  * with q = (k_p - k_q - k_r + k_s)/2, times the spin matrix element of each
  * channel's operator (sec. "Two-body interaction"). */
+static double kmom(const orc_pnm* h, int n, int d) { return (2.0 * M_PI * n + h->theta[d]) / h->L; }
+
 static double v_direct(const orc_pnm* h, int p, int q, int r, int s) {
+    /* k_p + k_q = k_r + k_s: the twists of both sides are equal */
     if (h->nx[p] + h->nx[q] != h->nx[r] + h->nx[s]) return 0.0;
     if (h->ny[p] + h->ny[q] != h->ny[r] + h->ny[s]) return 0.0;
     if (h->nz[p] + h->nz[q] != h->nz[r] + h->nz[s]) return 0.0;
-    double c = M_PI / h->L; /* (2 pi / L) * 1/2 */
-    double qx = c * (h->nx[p] - h->nx[q] - h->nx[r] + h->nx[s]);
-    double qy = c * (h->ny[p] - h->ny[q] - h->ny[r] + h->ny[s]);
-    double qz = c * (h->nz[p] - h->nz[q] - h->nz[r] + h->nz[s]);
+    double qx = 0.5 * (kmom(h, h->nx[p], 0) - kmom(h, h->nx[q], 0) - kmom(h, h->nx[r], 0) + kmom(h, h->nx[s], 0));
+    double qy = 0.5 * (kmom(h, h->ny[p], 1) - kmom(h, h->ny[q], 1) - kmom(h, h->ny[r], 1) + kmom(h, h->ny[s], 1));
+    double qz = 0.5 * (kmom(h, h->nz[p], 2) - kmom(h, h->nz[q], 2) - kmom(h, h->nz[r], 2) + kmom(h, h->nz[s], 2));
     double q2 = qx * qx + qy * qy + qz * qz;
     double L3 = h->L * h->L * h->L;
     int bra = sidx(h->sz[p], h->sz[q]), ket = sidx(h->sz[r], h->sz[s]);

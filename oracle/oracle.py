@@ -52,6 +52,7 @@ def lib():
         dp, ip = C.POINTER(C.c_double), C.POINTER(C.c_int)
         sig = {
             "orc_pnm_new": (vp, [i, i, d, d, d, d, d, d, d, d]),
+            "orc_pnm_new_twist": (vp, [i, i, d, d, d, d, d, d, d, d, d, d, d]),
             "orc_pnm_free": (None, [vp]),
             "orc_pnm_vas_direct": (d, [vp, i, i, i, i]),
             "orc_pnm_vas_fast": (d, [vp, i, i, i, i]),
@@ -98,17 +99,21 @@ def _ip(a):
 
 
 class PNM:
-    """Pure neutron matter model space and Minnesota interaction."""
+    """Pure neutron matter model space and Minnesota interaction; `twist` =
+    (theta_x, theta_y, theta_z) in radians gives momenta (2 pi n + theta) / L
+    and the holes filled by energy for that twist."""
 
     def __init__(self, n_particles: int, nmax2: int, rho: float,
-                 hbar2_over_m: float = HBAR2_OVER_M, **pot):
+                 hbar2_over_m: float = HBAR2_OVER_M, twist=(0.0, 0.0, 0.0), **pot):
         p = dict(MINNESOTA)
         p.update(pot)
         self.N, self.nmax2, self.rho = n_particles, nmax2, rho
-        self.h = lib().orc_pnm_new(nmax2, n_particles, rho, hbar2_over_m,
-                                   p["VR"], p["kR"], p["VT"], p["kT"], p["VS"], p["kS"])
+        self.twist = tuple(float(x) for x in twist)
+        self.h = lib().orc_pnm_new_twist(nmax2, n_particles, rho, hbar2_over_m,
+                                         p["VR"], p["kR"], p["VT"], p["kT"], p["VS"], p["kS"],
+                                         *self.twist)
         if not self.h:
-            raise ValueError("N does not close a shell of the basis, or no particle states")
+            raise ValueError("N is odd, leaves no particle states, or (untwisted) does not close a shell")
         self.ns = lib().orc_pnm_nstates(self.h)
         self.L = lib().orc_pnm_L(self.h)
 
@@ -242,3 +247,20 @@ def pairing_model(g: float, delta: float = 1.0, nlevels: int = 4):
                 for s in range(n):
                     v[p, q, r, s] = -0.5 * g * sig(p, q) * sig(r, s)
     return h, v
+
+
+def twist_grid(n_per_dir: int):
+    """Gauss-Legendre twist angles on [0, pi] in each direction and the weights
+    w_x w_y w_z / pi^3 of the twist average (they sum to 1), from numpy's
+    Gauss-Legendre rule (the twist-averaging algorithm)."""
+    x, w = np.polynomial.legendre.leggauss(n_per_dir)
+    th = 0.5 * np.pi * (x + 1.0)
+    wt = 0.5 * np.pi * w
+    thetas, weights = [], []
+    for a in range(n_per_dir):
+        for b in range(n_per_dir):
+            for c in range(n_per_dir):
+                thetas.append((th[a], th[b], th[c]))
+                weights.append(wt[a] * wt[b] * wt[c] / np.pi ** 3)
+    return np.array(thetas), np.array(weights)
+
