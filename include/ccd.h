@@ -53,7 +53,14 @@ typedef enum {
 
 /* One PNM problem (sec. "Single-particle basis for infinite matter" and
  * sec. "Two-body interaction").  The Minnesota triplet channel does not act
- * between two neutrons, so only its R and S channels are parameters. */
+ * between two neutrons, so only its R and S channels are parameters.
+ *
+ * twist (the twist-averaging passage of sec. "Developing a CCD code for
+ * infinite matter"): phi(x + L) = e^{i theta} phi(x) in each direction, so
+ * k = (2 pi n + theta) / L; all zero is the periodic box, pi antiperiodic.
+ * With a twist the states of the same basis are ordered by energy (key
+ * |n|^2 + 2 n.theta/2pi in FP64, ties kept in the periodic order) and the
+ * lowest N are holes; N must then be even, but need not close a shell. */
 typedef struct {
     int32_t n_particles;  /* N: closed shell of the basis (2, 14, 38, 54, 66, 114, ...) */
     int32_t nmax2;        /* keep states with n_x^2+n_y^2+n_z^2 <= nmax2 */
@@ -61,6 +68,7 @@ typedef struct {
     double hbar2_over_m;  /* MeV fm^2, e.g. 41.47 */
     double V_R, kappa_R;  /* repulsive Gaussian, e.g. 200 MeV, 1.487 fm^-2 */
     double V_S, kappa_S;  /* singlet Gaussian, e.g. -91.85 MeV, 0.465 fm^-2 */
+    double twist[3];      /* theta_x, theta_y, theta_z in radians (finite) */
 } ccd_problem;
 
 /* Term bits of eq. ccd3 (all set = full CCD) */
@@ -204,6 +212,27 @@ ccd_status ccd_set_tuning(ccd_ctx* ctx, const int32_t* src, int32_t n);
  * (eq. ccdcorr).  Synchronises the stream.  Any pointer may be NULL. */
 ccd_status ccd_energy(const ccd_ctx* ctx, int32_t problem, double* e_ref, double* e_mbpt2,
                       double* e_corr);
+
+/* Kinetic energy T = sum_i t_i of the Fermi sea of problem `problem` and the
+ * first-order (Hartree-Fock) potential energy E_ref - T, box totals in MeV:
+ * the two quantities the twist-averaging passage compares with infinite
+ * matter.  Host data only (no GPU work).  Either pointer may be NULL. */
+ccd_status ccd_reference_parts(const ccd_ctx* ctx, int32_t problem, double* kinetic, double* hf_potential);
+
+/* Gauss-Legendre twist mesh of the twist-averaging algorithm: n points on
+ * [0, pi] in each direction, n^3 twists theta[3k .. 3k+2] (x slowest, nodes
+ * ascending) with weights weight[k] = w_x w_y w_z / pi^3, which sum to 1, so
+ * that sum_k weight[k] E(theta_k) is the twist average.  Nodes by Newton's
+ * method on the Legendre polynomial P_n.  n in [1, 64]; host buffers of 3 n^3
+ * and n^3 doubles.  No GPU work.  Errors: CCD_EINVAL. */
+ccd_status ccd_twist_mesh(int32_t n, double* theta, double* weight);
+
+/* Weighted sums over all problems p of a context (e.g. one problem per twist,
+ * weights from ccd_twist_mesh): out[0..4] = sum_p weight[p] (T, E_ref - T,
+ * E_ref, MBPT2 correlation energy, current correlation energy).  weight: host,
+ * n_problems finite doubles; out: host, 5 doubles.  Synchronises the stream.
+ * Errors: CCD_EINVAL, CCD_ESTATE (no workspace), CCD_EHIP. */
+ccd_status ccd_twist_average(const ccd_ctx* ctx, const double* weight, double* out);
 
 /* Sizes and operation counts of problem `problem`. */
 ccd_status ccd_problem_info(const ccd_ctx* ctx, int32_t problem, ccd_info* info);

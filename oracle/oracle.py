@@ -118,8 +118,8 @@ class PNM:
         self.L = lib().orc_pnm_L(self.h)
 
     def __del__(self):
-        if getattr(self, "h", None):
-            lib().orc_pnm_free(self.h)
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.orc_pnm_free(self.h)
             self.h = None
 
     def states(self):
@@ -164,8 +164,8 @@ class O1:
         self.o = lib().orc_o1_new(self.n, nh, _dp(self._h), _dp(self._v))
 
     def __del__(self):
-        if getattr(self, "o", None):
-            lib().orc_o1_free(self.o)
+        if getattr(self, "o", None) and _lib is not None:
+            _lib.orc_o1_free(self.o)
             self.o = None
 
     eref = property(lambda s: lib().orc_o1_eref(s.o))
@@ -192,8 +192,8 @@ class O3:
         self.o = lib().orc_o3_new(pnm.h)
 
     def __del__(self):
-        if getattr(self, "o", None):
-            lib().orc_o3_free(self.o)
+        if getattr(self, "o", None) and _lib is not None:
+            _lib.orc_o3_free(self.o)
             self.o = None
 
     eref = property(lambda s: lib().orc_o3_eref(s.o))

@@ -22,7 +22,7 @@ def build(verbose: bool = False) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     tmp = LIB + ".tmp"
     cmd = [hipcc, f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
-           "-Wall", "-Wno-unused-function", *DEVICE_FLAGS,
+           "-Wall", "-Wno-unused-function", "-pthread", *DEVICE_FLAGS,
            "-I", os.path.join(HERE, "..", "include"),
            os.path.join(CSRC, "ccd_plan.cpp"), os.path.join(CSRC, "ccd_device.hip"),
            os.path.join(CSRC, "ccd_mlp.hip"),

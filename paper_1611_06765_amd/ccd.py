@@ -42,7 +42,7 @@ CCD_TUNE_LEN = 10
 class ccd_problem(C.Structure):
     _fields_ = [("n_particles", C.c_int32), ("nmax2", C.c_int32), ("density", C.c_double),
                 ("hbar2_over_m", C.c_double), ("V_R", C.c_double), ("kappa_R", C.c_double),
-                ("V_S", C.c_double), ("kappa_S", C.c_double)]
+                ("V_S", C.c_double), ("kappa_S", C.c_double), ("twist", C.c_double * 3)]
 
 
 class ccd_solver_opts(C.Structure):
@@ -77,6 +77,9 @@ _SIGS = {
     "ccd_iterate": (_i32, [_vp, C.POINTER(ccd_solver_opts), _ip, _dp]),
     "ccd_energy": (_i32, [_vp, _i32, _dp, _dp, _dp]),
     "ccd_problem_info": (_i32, [_vp, _i32, C.POINTER(ccd_info)]),
+    "ccd_reference_parts": (_i32, [_vp, _i32, _dp, _dp]),
+    "ccd_twist_mesh": (_i32, [_i32, _dp, _dp]),
+    "ccd_twist_average": (_i32, [_vp, _dp, _dp]),
     "ccd_get_amplitudes": (_i32, [_vp, _i32, _dp, _sz]),
     "ccd_set_amplitudes": (_i32, [_vp, _i32, _dp, _sz]),
     "ccd_reset_amplitudes": (_i32, [_vp]),
@@ -125,11 +128,21 @@ MINNESOTA = dict(V_R=200.0, kappa_R=1.487, V_S=-91.85, kappa_S=0.465)
 HBAR2_OVER_M = 41.47
 
 
-def problem(n_particles, nmax2, density, hbar2_over_m=HBAR2_OVER_M, **pot):
+def problem(n_particles, nmax2, density, hbar2_over_m=HBAR2_OVER_M, twist=(0.0, 0.0, 0.0), **pot):
+    """ccd_problem; twist = (theta_x, theta_y, theta_z) in radians (0 = periodic)."""
     p = dict(MINNESOTA)
     p.update(pot)
     return ccd_problem(n_particles, nmax2, density, hbar2_over_m,
-                       p["V_R"], p["kappa_R"], p["V_S"], p["kappa_S"])
+                       p["V_R"], p["kappa_R"], p["V_S"], p["kappa_S"],
+                       (C.c_double * 3)(*(float(x) for x in twist)))
+
+
+def twist_mesh(n):
+    """Gauss-Legendre twist mesh: (n^3 x 3 angles on [0, pi], n^3 weights summing to 1)."""
+    th = np.zeros(3 * n ** 3)
+    w = np.zeros(n ** 3)
+    _check(_lib.ccd_twist_mesh(n, _dptr(th), _dptr(w)), "ccd_twist_mesh")
+    return th.reshape(-1, 3), w
 
 
 def _dptr(a):
@@ -212,6 +225,21 @@ class Context:
         a, b, c = C.c_double(), C.c_double(), C.c_double()
         _check(_lib.ccd_energy(self._h, p, C.byref(a), C.byref(b), C.byref(c)), "ccd_energy")
         return a.value, b.value, c.value
+
+    def reference_parts(self, p=0):
+        """(kinetic energy, Hartree-Fock potential energy) of the Fermi sea (host plan)."""
+        a, b = C.c_double(), C.c_double()
+        _check(_lib.ccd_reference_parts(self._h, p, C.byref(a), C.byref(b)), "ccd_reference_parts")
+        return a.value, b.value
+
+    def twist_average(self, weights):
+        """Weighted sums of (T, E_ref - T, E_ref, MBPT2, correlation energy) over the problems."""
+        w = np.ascontiguousarray(weights, dtype=np.float64)
+        if w.shape != (self.n,):
+            raise ValueError("one weight per problem")
+        out = np.zeros(5)
+        _check(_lib.ccd_twist_average(self._h, _dptr(w), _dptr(out)), "ccd_twist_average")
+        return out
 
     def eref(self, p=0):
         """Reference energy (host plan; no GPU needed)."""

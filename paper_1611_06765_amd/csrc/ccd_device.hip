@@ -31,6 +31,8 @@
 #include <functional>
 #include <map>
 #include <string>
+#include <thread>
+#include <tuple>
 #include <type_traits>
 #include <vector>
 
@@ -534,6 +536,7 @@ __global__ void __launch_bounds__(256) k_dchi(DevPtrs d, uint32_t mask, int n_it
 // ring per pair {Q, P = -Q} of cross channels and problem.  With
 //   A[u][x] = T~_Q  = t_ik^ac,  (a,i) = member u of Q, (c,k) = member x of P
 //   B[x][m] = <kl||cd>,         (c,k) = member x of P, (d,l) = member m of Q
+// (A is n_Q x n_P and B n_P x n_Q; the two sizes differ under a twist)
 // the partner's blocks are the transposes (T~_P = A^T, its Vbar = B^T), so
 //   chi_P = <kb||cj>_P + 1/2 B A      (chi_kbcj for the ring of Q)
 //   M_Q   = <kb||cj>_Q + 1/2 A B      (the transpose of chi_kbcj for the ring of P)
@@ -544,14 +547,15 @@ __global__ void __launch_bounds__(256) k_dchi(DevPtrs d, uint32_t mask, int n_it
 // takes three products instead of four.  Each entry of Out is stored once,
 // to the ring slot (2e + k) of the amplitude e it feeds (k = which of its two
 // ring terms), so the amplitude update reads its two slots with one 16-byte
-// load.  The products run on MFMA from LDS (matrices padded to n16, row stride
-// n16 + 1), their K loops cut at the block order rounded up to the MFMA K step.
+// load.  The products run on MFMA from LDS (matrices padded to n16 >= both
+// sizes, row stride n16 + 1), their K loops cut at the contracted size rounded
+// up to the MFMA K step.
 struct PairCtx {
-    const int32_t* map;    // position map of Q
+    const int32_t* map;    // position map of Q, [nq][np]
     const double* t;       // amplitudes of the problem
     double* zc;            // ring slots of the problem
-    const int32_t* zs;     // position -> slot table of the pair block
-    int n;
+    const int32_t* zs;     // position -> slot table of the pair block, [nq][np]
+    int nq, np;            // members of Q and of P = -Q
     bool self;             // Q is its own partner
 };
 
@@ -564,7 +568,8 @@ __device__ __forceinline__ bool pair_ctx(const DevPtrs& d, const Item it, int cu
     r.t = d.t[cur] + G.t_base + g * G.n_amp;
     r.zc = d.zc + 2 * (G.t_base + g * G.n_amp);
     r.zs = d.zs + G.zidx_off + q.zp_off;
-    r.n = q.n;
+    r.nq = q.n;
+    r.np = q.m;
     r.self = q.partner == it.chan;
     memQ = q.mem_off;
     memP = d.ph[q.partner].mem_off;
@@ -574,12 +579,16 @@ __device__ __forceinline__ bool pair_ctx(const DevPtrs& d, const Item it, int cu
 
 // stage (p, h) states of both member lists and the problem's W/2 table
 __device__ __forceinline__ void pair_stage(const DevPtrs& d, const Item it, int memQ, int memP, int lut_off,
-                                           int n, int32_t* qs, int32_t* ps, double* lutS, int t0, int stride) {
+                                           int nq, int np, int32_t* qs, int32_t* ps, double* lutS, int t0,
+                                           int stride) {
     const DevGroup G = d.groups[d.ph[it.chan].group];
     const int32_t* st = d.st + G.st_off;
-    for (int e = t0; e < n; e += stride) {
-        int32_t m = d.phmem[memQ + e], o = d.phmem[memP + e];
+    for (int e = t0; e < nq; e += stride) {
+        const int32_t m = d.phmem[memQ + e];
         qs[2 * e] = st[pa(m)]; qs[2 * e + 1] = st[pb(m)];
+    }
+    for (int e = t0; e < np; e += stride) {
+        const int32_t o = d.phmem[memP + e];
         ps[2 * e] = st[pa(o)]; ps[2 * e + 1] = st[pb(o)];
     }
     for (int e = t0; e < G.nlut; e += stride) lutS[e] = d.lut[lut_off + e];
@@ -590,7 +599,7 @@ __device__ __forceinline__ void pair_stage(const DevPtrs& d, const Item it, int 
 template <typename E, int n16, int lda, int stride, bool TR>
 __device__ __forceinline__ void pair_fill(const PairCtx& r, const int32_t* qs, const int32_t* ps,
                                           const double* lutS, E* A, E* B, E* At, E* Bt, int t0, bool qring) {
-    const int n = r.n;
+    const int nq = r.nq, np = r.np;
     constexpr int tot = n16 * n16;
     for (int base = t0; base < tot; base += 8 * stride) {
         int m[8];
@@ -599,7 +608,7 @@ __device__ __forceinline__ void pair_fill(const PairCtx& r, const int32_t* qs, c
         for (int j = 0; j < 8; j++) {
             int e = base + j * stride;
             int u = e / n16, x = e - u * n16;
-            m[j] = (e < tot && u < n && x < n) ? r.map[u * n + x] : -1;
+            m[j] = (e < tot && u < nq && x < np) ? r.map[u * np + x] : -1;
         }
 #pragma unroll
         for (int j = 0; j < 8; j++) tv[j] = m[j] >= 0 ? r.t[m[j] >> 3] : 0.0;
@@ -609,7 +618,7 @@ __device__ __forceinline__ void pair_fill(const PairCtx& r, const int32_t* qs, c
             if (e < tot) {
                 int u = e / n16, x = e - u * n16;
                 double b = 0.0;
-                if (qring && u < n && x < n)  // <kl||cd>: (c,k) = P member u, (d,l) = Q member x
+                if (qring && u < np && x < nq)  // <kl||cd>: (c,k) = P member u, (d,l) = Q member x
                     b = vas(lutS, ps[2 * u + 1], qs[2 * x + 1], ps[2 * u], qs[2 * x]);
                 const E av = (E)((m[j] & 1) ? -tv[j] : tv[j]), bv = (E)b;
                 A[u * lda + x] = av;
@@ -634,10 +643,10 @@ __device__ __forceinline__ void pair_store(const PairCtx& r, AT acc, int tu, int
 #pragma unroll
     for (int q = 0; q < 4; q++) {
         int u = tu * 16 + orow<P>(lane, q), y = ty * 16 + (lane & 15);
-        if (u < r.n && y < r.n) {
+        if (u < r.nq && y < r.np) {
             // the position's ring slot (a self pair holds both orders of one
             // amplitude; only the p < p' one has a slot)
-            const int32_t z = r.zs[u * r.n + y];
+            const int32_t z = r.zs[u * r.np + y];
             const double v = (double)acc[q];
             if (z >= 0) r.zc[z >> 1] = (z & 1) ? -v : v;
         }
@@ -704,7 +713,7 @@ __device__ __forceinline__ void pair_body(const DevPtrs& d, const Item it, int c
     constexpr int lda = P == P_BF16 ? kpad + 8 : N16 + 1;
     constexpr int rows = P == P_BF16 ? kpad : N16;  // rows allocated per matrix
     PairCtx r;
-    r.n = 0; r.self = false; r.map = nullptr; r.t = nullptr; r.zc = nullptr; r.zs = nullptr;
+    r.nq = 0; r.np = 0; r.self = false; r.map = nullptr; r.t = nullptr; r.zc = nullptr; r.zs = nullptr;
     int32_t memQ = 0, memP = 0, lo = 0;
     // every wave reaches every barrier below; only the work is guarded by live
     const bool live = it.chan >= 0 && pair_ctx(d, it, cur, r, memQ, memP, lo);
@@ -720,7 +729,7 @@ __device__ __forceinline__ void pair_body(const DevPtrs& d, const Item it, int c
     E* Bt = At + rows * lda;  // BF16 only
     const bool qring = (mask & CCD_T_QRING) != 0, ring = (mask & CCD_T_RING) != 0;
     if (live) {
-        pair_stage(d, it, memQ, memP, lo, r.n, qs, ps, lutS, tid, 64 * NW);
+        pair_stage(d, it, memQ, memP, lo, r.nq, r.np, qs, ps, lutS, tid, 64 * NW);
         if constexpr (P == P_BF16) {
             // zero the K padding (rows and columns n16 .. kpad) of all three matrices
             for (int e = tid; e < 3 * rows * lda; e += 64 * NW) A[e] = (E)0.0f;
@@ -729,8 +738,10 @@ __device__ __forceinline__ void pair_body(const DevPtrs& d, const Item it, int c
     __syncthreads();
     if (live) pair_fill<E, n16, lda, 64 * NW, P == P_BF16>(r, qs, ps, lutS, A, B, At, Bt, tid, qring);
     __syncthreads();
-    // K extent of the products: the block order rounded up to the MFMA K step
-    const int kq = P == P_BF16 ? ((r.n + 31) & ~31) : ((r.n + 3) & ~3);
+    // K extents: the contracted size rounded up to the MFMA K step (n_P for
+    // A B and A V_P, n_Q for X A)
+    const int kp = P == P_BF16 ? ((r.np + 31) & ~31) : ((r.np + 3) & ~3);
+    const int kq = P == P_BF16 ? ((r.nq + 31) & ~31) : ((r.nq + 3) & ~3);
     // X = A B for this wave's tiles (quadratic ring)
     AT xq[TPW];
 #pragma unroll
@@ -739,8 +750,8 @@ __device__ __forceinline__ void pair_body(const DevPtrs& d, const Item it, int c
         const int tile = w + NW * k;
         if (live && qring && tile < ntt) {
             const int tx = tile / nt, ty = tile - tx * nt;
-            if constexpr (P == P_BF16) xq[k] = mmbf(A, Bt, lda, tx, ty, kq, lane, xq[k]);
-            else xq[k] = mm4<P>(A, B, lda, tx, ty, kq, lane, xq[k]);
+            if constexpr (P == P_BF16) xq[k] = mmbf(A, Bt, lda, tx, ty, kp, lane, xq[k]);
+            else xq[k] = mm4<P>(A, B, lda, tx, ty, kp, lane, xq[k]);
         }
     }
     __syncthreads();  // every wave has finished reading B (Bt)
@@ -755,7 +766,7 @@ __device__ __forceinline__ void pair_body(const DevPtrs& d, const Item it, int c
             for (int q = 0; q < 4; q++) {
                 const int x = tx * 16 + orow<P>(lane, q), y = ty * 16 + (lane & 15);
                 double xv = (double)xq[k][q];
-                if (ring && x < r.n && y < r.n) xv += pair_vph(qs, lutS, x, y);
+                if (ring && x < r.nq && y < r.nq) xv += pair_vph(qs, lutS, x, y);
                 XB[x * lda + y] = (E)xv;
             }
         }
@@ -783,7 +794,7 @@ __device__ __forceinline__ void pair_body(const DevPtrs& d, const Item it, int c
 #pragma unroll
             for (int q = 0; q < 4; q++) {
                 const int x = tx * 16 + orow<P>(lane, q), y = ty * 16 + (lane & 15);
-                const double vp = (ring && x < r.n && y < r.n) ? pair_vph(ps, lutS, x, y) : 0.0;
+                const double vp = (ring && x < r.np && y < r.np) ? pair_vph(ps, lutS, x, y) : 0.0;
                 if constexpr (P == P_BF16) XB[y * lda + x] = (E)(float)vp;
                 else XB[x * lda + y] = (E)vp;
             }
@@ -796,8 +807,8 @@ __device__ __forceinline__ void pair_body(const DevPtrs& d, const Item it, int c
         const int tile = w + NW * k;
         if (live && tile < ntt) {
             const int tu = tile / nt, ty = tile - tu * nt;
-            if constexpr (P == P_BF16) acc[k] = mmbf(A, XB, lda, tu, ty, kq, lane, acc[k]);
-            else acc[k] = mm4<P>(A, XB, lda, tu, ty, kq, lane, acc[k]);
+            if constexpr (P == P_BF16) acc[k] = mmbf(A, XB, lda, tu, ty, kp, lane, acc[k]);
+            else acc[k] = mm4<P>(A, XB, lda, tu, ty, kp, lane, acc[k]);
             pair_store<P>(r, acc[k], tu, ty, lane);
         }
     }
@@ -1345,11 +1356,17 @@ static std::vector<Item> xcd_order_cost(const std::vector<std::pair<int, Item>>&
     return out;
 }
 
-// group the problems by structure and lay out the device tables
+// group the problems by structure (N, nmax2 and the twist, which decides the
+// hole set) and lay out the device tables
 static ccd_status assemble(ccd_ctx* c) {
-    std::map<std::pair<int, int>, std::vector<int>> by_structure;
-    for (size_t p = 0; p < c->probs.size(); p++)
-        by_structure[{c->probs[p].par.n_particles, c->probs[p].par.nmax2}].push_back((int)p);
+    using SKey = std::tuple<int, int, double, double, double>;
+    std::map<SKey, std::vector<int>> by_structure;
+    for (size_t p = 0; p < c->probs.size(); p++) {
+        const ccd_problem& q = c->probs[p].par;
+        // +0.0 folds -0.0 into 0.0, so a zero twist of either sign is one structure
+        by_structure[SKey{q.n_particles, q.nmax2, q.twist[0] + 0.0, q.twist[1] + 0.0, q.twist[2] + 0.0}]
+            .push_back((int)p);
+    }
     const size_t P = c->probs.size();
     c->pgrp.assign(P, 0);
     c->pgi.assign(P, 0);
@@ -1498,14 +1515,16 @@ static ccd_status assemble(ccd_ctx* c) {
             dp.map_off = map0 + h.z_off;
             dp.group = gi;
             dp.n = h.n;
+            dp.m = H.ph[h.partner].n;
             dp.partner = ph0 + h.partner;
             dp.mem_off = mem0 + h.mem_off;
             dp.zp_off = h.zp_off;
             const int pid = (int)c->dph.size();
             if (h.zp_off >= 0) {
+                const int nb = std::max(h.n, dp.m);  // the pair's padded order
                 for (int g = 0; g < D.G; g++) {
-                    if (h.n <= 16) rs.push_back({slot0 + g, Item{pid, g}});
-                    else rb[((h.n + 15) >> 4) - 2].push_back({slot0 + g, Item{pid, g}});
+                    if (nb <= 16) rs.push_back({slot0 + g, Item{pid, g}});
+                    else rb[((nb + 15) >> 4) - 2].push_back({slot0 + g, Item{pid, g}});
                 }
             }
             c->dph.push_back(dp);
@@ -1911,15 +1930,26 @@ ccd_status ccd_build_channels(const ccd_problem* probs, int32_t n, void* stream,
     if (!c) { set_error("out of host memory"); return CCD_ENOMEM; }
     c->stream = (hipStream_t)stream;
     c->probs.resize(n);
-    for (int i = 0; i < n; i++) {
-        std::string err;
-        ccd_status s = build_problem(probs[i], c->probs[i], err);
-        if (s != CCD_OK) {
-            set_error("problem " + std::to_string(i) + ": " + err);
+    // the plans are independent: host threads take problems i = w, w + T, ...
+    std::vector<ccd_status> st(n, CCD_OK);
+    std::vector<std::string> errs(n);
+    {
+        const int T = std::max(1, std::min({n, 16, (int)std::thread::hardware_concurrency()}));
+        auto work = [&](int w) {
+            for (int i = w; i < n; i += T) st[i] = build_problem(probs[i], c->probs[i], errs[i]);
+        };
+        std::vector<std::thread> pool;
+        for (int w = 1; w < T; w++) pool.emplace_back(work, w);
+        work(0);
+        for (auto& th : pool) th.join();
+    }
+    for (int i = 0; i < n; i++)
+        if (st[i] != CCD_OK) {
+            set_error("problem " + std::to_string(i) + ": " + errs[i]);
+            const ccd_status s = st[i];
             delete c;
             return s;
         }
-    }
     ccd_status s = assemble(c);
     if (s != CCD_OK) { delete c; return s; }
     c->emp2.assign(n, 0.0);
@@ -2100,6 +2130,36 @@ ccd_status ccd_energy(const ccd_ctx* cc, int32_t p, double* eref, double* emp2, 
         if (emp2) *emp2 = c->emp2[p];
         if (ecorr) *ecorr = e;
     }
+    return CCD_OK;
+}
+
+ccd_status ccd_reference_parts(const ccd_ctx* c, int32_t p, double* kinetic, double* hf_potential) {
+    if (!c || p < 0 || p >= (int)c->probs.size()) { set_error("ccd_reference_parts: bad problem"); return CCD_EINVAL; }
+    if (kinetic) *kinetic = c->probs[p].ekin;
+    if (hf_potential) *hf_potential = c->probs[p].eref - c->probs[p].ekin;
+    return CCD_OK;
+}
+
+ccd_status ccd_twist_average(const ccd_ctx* cc, const double* weight, double* out) {
+    ccd_ctx* c = (ccd_ctx*)cc;
+    if (!c || !weight || !out) { set_error("ccd_twist_average: NULL argument"); return CCD_EINVAL; }
+    if (!c->bound) { set_error("ccd_twist_average: no workspace bound"); return CCD_ESTATE; }
+    const size_t P = c->probs.size();
+    std::vector<double> ec(P);
+    HIP_TRY(hipMemcpyAsync(ec.data(), c->ws + c->r_ecorr.off, 8 * P, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    double acc[5] = {0, 0, 0, 0, 0};
+    for (size_t p = 0; p < P; p++) {
+        const HostProblem& H = c->probs[p];
+        const double w = weight[p];
+        if (!std::isfinite(w)) { set_error("ccd_twist_average: weight not finite"); return CCD_EINVAL; }
+        acc[0] += w * H.ekin;
+        acc[1] += w * (H.eref - H.ekin);
+        acc[2] += w * H.eref;
+        acc[3] += w * c->emp2[p];
+        acc[4] += w * ec[c->slot_of[p]];
+    }
+    for (int k = 0; k < 5; k++) out[k] = acc[k];
     return CCD_OK;
 }
 

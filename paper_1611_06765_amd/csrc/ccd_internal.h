@@ -74,10 +74,11 @@ struct DevChan {
 };
 
 struct DevPh {
-    int64_t map_off;      // global offset of the [n][n] position map (shared)
-    int64_t zp_off;       // offset of the pair block if this channel is the primary of
-                          // its pair {Q, -Q} (the lower index), else -1
+    int64_t map_off;      // global offset of the [n][m] position map (shared)
+    int64_t zp_off;       // offset of the [n][m] pair block if this channel is the
+                          // primary of its pair {Q, -Q} (the lower index), else -1
     int32_t group, n, partner, mem_off;  // partner / mem_off global
+    int32_t m;            // the partner's size (differs from n under a twist)
 };
 
 struct Item {             // work item: a channel and a start (row or element)
@@ -96,7 +97,7 @@ struct PhChan {
     int Qx, Qy, Qz, sig;  // sig = 2 (s_p - s_h): -2, 0, +2
     int n, partner;       // local partner index
     int mem_off;          // local offset in phmem (pairs)
-    int64_t z_off;        // local offset of the position map
+    int64_t z_off;        // local offset of the position map [n][partner's n]
     int64_t zp_off;       // pair-block offset if primary of {Q, -Q} (lower index), else -1
 };
 
@@ -107,7 +108,7 @@ struct HostProblem {
     std::vector<int> nx, ny, nz, sz;     // sz = 2 s_z = -1 or +1
     std::vector<double> tkin, eps;       // kinetic and Fock energies
     std::vector<double> W;               // W(m), m = 0 .. 4 nmax2
-    double eref = 0;
+    double ekin = 0, eref = 0;           // kinetic and reference energy of the Fermi sea
     std::vector<Chan> chans;
     std::vector<int32_t> hh, pp;         // pairs, 2 ints each, channel after channel
     int64_t n_amp = 0;

@@ -7,6 +7,15 @@
 // states are holes (sec. "Single-particle basis for infinite matter" and the
 // model-space loop of sec. "Developing a CCD code for infinite matter").
 //
+// Twisted boundary conditions (the twist-averaging passage and its algorithm):
+// phi(x + L) = e^{i theta} phi(x) gives k = (2 pi n + theta) / L.  The same
+// states are then ordered by energy, i.e. by |n|^2 + 2 n.phi with
+// phi = theta / 2 pi (FP64, left to right, stable in the order above), and the
+// first N are holes.  Momentum transfers and momentum conservation do not see
+// the twist, so the interaction table and the channel rules are unchanged; the
+// hole set is no longer symmetric under n -> -n, so a cross channel Q and its
+// partner -Q can differ in size.
+//
 // Interaction: between two neutrons the isospin exchange is +1, so the
 // Minnesota operator 1/2 (V_R + 1/2(1+P_s)V_T + 1/2(1-P_s)V_S)(1 - P_s P_t)
 // (sec. "Two-body interaction") reduces to 1/2 (V_R(r) + V_S(r)) (1 - P_s):
@@ -32,6 +41,9 @@
 
 #include "ccd_internal.h"
 
+// the state order is an integer decision taken on FP64 keys: no contraction
+#pragma STDC FP_CONTRACT OFF
+
 namespace ccd {
 
 static double minnesota_W(const ccd_problem& p, double L, int m) {
@@ -52,6 +64,10 @@ ccd_status build_problem(const ccd_problem& par, HostProblem& P, std::string& er
     if (!(par.density > 0.0) || !std::isfinite(par.density)) { err = "density must be > 0"; return CCD_EINVAL; }
     if (!(par.hbar2_over_m > 0.0)) { err = "hbar2_over_m must be > 0"; return CCD_EINVAL; }
     if (!(par.kappa_R > 0.0) || !(par.kappa_S > 0.0)) { err = "Gaussian ranges must be > 0"; return CCD_EINVAL; }
+    for (int d = 0; d < 3; d++)
+        if (!std::isfinite(par.twist[d])) { err = "twist angles must be finite"; return CCD_EINVAL; }
+    const bool twisted = par.twist[0] != 0.0 || par.twist[1] != 0.0 || par.twist[2] != 0.0;
+    if (par.n_particles & 1) { err = "n_particles must be even"; return CCD_ENOTMAGIC; }
 
     // ---- model space ------------------------------------------------------
     int R = 0;
@@ -65,15 +81,30 @@ ccd_status build_problem(const ccd_problem& par, HostProblem& P, std::string& er
                 if (n2 <= par.nmax2) mom.push_back({n2, x, y, z});
             }
     std::sort(mom.begin(), mom.end());
-    for (auto& m : mom)
-        for (int s : {-1, 1}) {
-            P.nx.push_back(m[1]); P.ny.push_back(m[2]); P.nz.push_back(m[3]); P.sz.push_back(s);
-        }
+    {
+        // energy order under the twist; both spins of a momentum stay together
+        const double phx = par.twist[0] / (2.0 * M_PI), phy = par.twist[1] / (2.0 * M_PI),
+                     phz = par.twist[2] / (2.0 * M_PI);
+        std::vector<std::pair<double, size_t>> key(mom.size());
+        for (size_t k = 0; k < mom.size(); k++)
+            key[k] = {(double)mom[k][0] + 2.0 * ((double)mom[k][1] * phx + (double)mom[k][2] * phy +
+                                                 (double)mom[k][3] * phz),
+                      k};
+        std::stable_sort(key.begin(), key.end(),
+                         [](const std::pair<double, size_t>& a, const std::pair<double, size_t>& b) {
+                             return a.first < b.first;
+                         });
+        for (auto& kv : key)
+            for (int s : {-1, 1}) {
+                const auto& m = mom[kv.second];
+                P.nx.push_back(m[1]); P.ny.push_back(m[2]); P.nz.push_back(m[3]); P.sz.push_back(s);
+            }
+    }
     P.ns = (int)P.nx.size();
     P.nh = par.n_particles;
     if (P.nh >= P.ns) { err = "no particle states: raise nmax2"; return CCD_ENOTMAGIC; }
     auto shell = [&](int p) { return P.nx[p] * P.nx[p] + P.ny[p] * P.ny[p] + P.nz[p] * P.nz[p]; };
-    if (shell(P.nh - 1) == shell(P.nh)) {
+    if (!twisted && shell(P.nh - 1) == shell(P.nh)) {
         err = "n_particles does not close a shell of the plane-wave basis";
         return CCD_ENOTMAGIC;
     }
@@ -83,9 +114,12 @@ ccd_status build_problem(const ccd_problem& par, HostProblem& P, std::string& er
 
     // ---- energies and interaction table -------------------------------------
     const double pi = 3.14159265358979323846;
-    double dk = 2.0 * pi / P.L;
     P.tkin.resize(P.ns);
-    for (int p = 0; p < P.ns; p++) P.tkin[p] = 0.5 * par.hbar2_over_m * dk * dk * (double)shell(p);
+    for (int p = 0; p < P.ns; p++) {
+        const double kx = (2.0 * pi * P.nx[p] + par.twist[0]) / P.L, ky = (2.0 * pi * P.ny[p] + par.twist[1]) / P.L,
+                     kz = (2.0 * pi * P.nz[p] + par.twist[2]) / P.L;
+        P.tkin[p] = 0.5 * par.hbar2_over_m * (kx * kx + ky * ky + kz * kz);
+    }
     int nlut = 4 * par.nmax2 + 1;
     P.W.resize(nlut);
     for (int m = 0; m < nlut; m++) P.W[m] = minnesota_W(par, P.L, m);
@@ -107,6 +141,7 @@ ccd_status build_problem(const ccd_problem& par, HostProblem& P, std::string& er
         for (int i = 0; i < P.nh; i++)
             for (int j = 0; j < P.nh; j++)
                 if (P.sz[i] != P.sz[j]) v += 0.5 * (P.W[0] + P.W[d2(i, j)]);
+        P.ekin = t;
         P.eref = t + 0.5 * v;
     }
 
@@ -166,31 +201,32 @@ ccd_status build_problem(const ccd_problem& par, HostProblem& P, std::string& er
             auto& e = phmap[k];
             e.push_back(p); e.push_back(h);
         }
+    // a channel whose partner -Q holds no pair carries no ring term (the two
+    // positions of every ring term lie in Q and -Q): it is left out
     std::map<Key, int> phid;
     for (auto& kv : phmap) {
+        const Key partner{-std::get<0>(kv.first), -std::get<1>(kv.first), -std::get<2>(kv.first),
+                          -std::get<3>(kv.first)};
+        if (phmap.find(partner) == phmap.end()) continue;
         PhChan c;
         c.sig = std::get<0>(kv.first); c.Qx = std::get<1>(kv.first);
         c.Qy = std::get<2>(kv.first); c.Qz = std::get<3>(kv.first);
         c.n = (int)kv.second.size() / 2;
         c.mem_off = (int)P.phmem.size() / 2;
         c.partner = -1;
-        c.z_off = P.nz_ph;
-        P.nz_ph += (int64_t)c.n * c.n;
         phid[kv.first] = (int)P.ph.size();
         P.phmem.insert(P.phmem.end(), kv.second.begin(), kv.second.end());
         P.ph.push_back(c);
         P.max_ph = std::max(P.max_ph, c.n);
-        P.flops_ring += 4.0 * (double)c.n * c.n * c.n;
     }
-    P.flops_ordered += P.flops_ring;
     P.phq.assign((size_t)P.np * P.nh, -1);
     P.phpos.assign((size_t)P.np * P.nh, -1);
     for (size_t q = 0; q < P.ph.size(); q++) {
         PhChan& c = P.ph[q];
         Key partner{-c.sig, -c.Qx, -c.Qy, -c.Qz};
         auto it = phid.find(partner);
-        if (it == phid.end() || P.ph[it->second].n != c.n) {
-            err = "internal: particle-hole channel without a partner of equal size";
+        if (it == phid.end()) {
+            err = "internal: particle-hole channel without a partner";
             return CCD_EINVAL;
         }
         c.partner = it->second;
@@ -200,6 +236,15 @@ ccd_status build_problem(const ccd_problem& par, HostProblem& P, std::string& er
             P.phpos[(size_t)(p - P.nh) * P.nh + h] = u;
         }
     }
+    // position maps [n_Q][n_-Q]; ring flops 2 n_-Q^2 n_Q for chi_kbcj and as
+    // many for Z_Q (both square when the hole set is symmetric)
+    for (PhChan& c : P.ph) {
+        const int m = P.ph[c.partner].n;
+        c.z_off = P.nz_ph;
+        P.nz_ph += (int64_t)c.n * m;
+        P.flops_ring += 4.0 * (double)c.n * m * m;
+    }
+    P.flops_ordered += P.flops_ring;
     if (P.max_ph > kMaxPH) {
         err = "a particle-hole channel has more than 80 pairs (N too large for this library)";
         return CCD_EINVAL;
@@ -228,7 +273,7 @@ ccd_status build_problem(const ccd_problem& par, HostProblem& P, std::string& er
         const PhChan& pc = P.ph[c.partner];
         for (int u = 0; u < c.n; u++) {
             int p = P.phmem[2 * (c.mem_off + u)], h = P.phmem[2 * (c.mem_off + u) + 1];
-            for (int y = 0; y < c.n; y++) {
+            for (int y = 0; y < pc.n; y++) {
                 int p2 = P.phmem[2 * (pc.mem_off + y)], h2 = P.phmem[2 * (pc.mem_off + y) + 1];
                 if (p == p2 || h == h2) continue;
                 int i = std::min(h, h2), j = std::max(h, h2);
@@ -240,25 +285,28 @@ ccd_status build_problem(const ccd_problem& par, HostProblem& P, std::string& er
                 int64_t e = dc.t_off + (int64_t)r * dc.nhh + hpos[(size_t)i * P.nh + j];
                 int slot = 2 * (p > p2) + (h > h2);
                 int neg = (p > p2) ^ (h > h2);
-                P.phmap[(size_t)c.z_off + (size_t)u * c.n + y] = (int32_t)((e << 3) | (slot << 1) | neg);
+                P.phmap[(size_t)c.z_off + (size_t)u * pc.n + y] = (int32_t)((e << 3) | (slot << 1) | neg);
             }
         }
     }
     // ---- pair blocks {Q, -Q} and the ring indices of each amplitude ----------
+    // the primary (lower index) Q of a pair owns the block [n_Q][n_-Q]
     for (size_t q = 0; q < P.ph.size(); q++) {
         PhChan& c = P.ph[q];
         c.zp_off = -1;
         if (c.partner >= (int)q) {
             c.zp_off = P.n_zp;
-            P.n_zp += (int64_t)c.n * c.n;
+            P.n_zp += (int64_t)c.n * P.ph[c.partner].n;
         }
     }
     if (P.n_zp >= ((int64_t)1 << 31) || P.n_amp >= ((int64_t)1 << 29)) { err = "too many ring entries"; return CCD_EINVAL; }
     auto zpos = [&](int p, int h, int p2, int h2) -> int64_t {
         size_t x1 = (size_t)(p - P.nh) * P.nh + h, x2 = (size_t)(p2 - P.nh) * P.nh + h2;
+        if (P.phq[x1] < 0 || P.phq[x2] < 0) return (int64_t)-1;
         const PhChan& c = P.ph[P.phq[x1]];
-        if (c.zp_off >= 0) return c.zp_off + (int64_t)P.phpos[x1] * c.n + P.phpos[x2];
-        return P.ph[c.partner].zp_off + (int64_t)P.phpos[x2] * c.n + P.phpos[x1];
+        const PhChan& pc = P.ph[c.partner];
+        if (c.zp_off >= 0) return c.zp_off + (int64_t)P.phpos[x1] * pc.n + P.phpos[x2];
+        return pc.zp_off + (int64_t)P.phpos[x2] * c.n + P.phpos[x1];
     };
     P.zidx.resize(2 * (size_t)P.n_amp);
     for (const Chan& c : P.chans)
@@ -267,8 +315,10 @@ ccd_status build_problem(const ccd_problem& par, HostProblem& P, std::string& er
             for (int q = 0; q < c.nhh; q++) {
                 int i = P.hh[2 * (c.hh_off + q)], j = P.hh[2 * (c.hh_off + q) + 1];
                 int64_t e = c.t_off + (int64_t)r * c.nhh + q;
-                P.zidx[2 * e] = (int32_t)zpos(a, i, b, j);
-                P.zidx[2 * e + 1] = (int32_t)zpos(a, j, b, i);
+                const int64_t z0 = zpos(a, i, b, j), z1 = zpos(a, j, b, i);
+                if (z0 < 0 || z1 < 0) { err = "internal: ring position in a channel without a partner"; return CCD_EINVAL; }
+                P.zidx[2 * e] = (int32_t)z0;
+                P.zidx[2 * e + 1] = (int32_t)z1;
             }
         }
     // inverse: each written pair-block position feeds one ring slot 2e + k of one
@@ -278,11 +328,12 @@ ccd_status build_problem(const ccd_problem& par, HostProblem& P, std::string& er
     for (const PhChan& c : P.ph) {
         if (c.zp_off < 0) continue;
         const bool self = c.partner == (int)(&c - P.ph.data());
+        const int ncol = P.ph[c.partner].n;
         for (int u = 0; u < c.n; u++)
-            for (int y = 0; y < c.n; y++) {
-                const int32_t m = P.phmap[(size_t)c.z_off + (size_t)u * c.n + y];
+            for (int y = 0; y < ncol; y++) {
+                const int32_t m = P.phmap[(size_t)c.z_off + (size_t)u * ncol + y];
                 if (m < 0 || (self && ((m >> 2) & 1))) continue;
-                const int64_t e = m >> 3, pos = c.zp_off + (int64_t)u * c.n + y;
+                const int64_t e = m >> 3, pos = c.zp_off + (int64_t)u * ncol + y;
                 int k = -1;
                 if (P.zidx[2 * e] == pos) k = 0;
                 else if (P.zidx[2 * e + 1] == pos) k = 1;
@@ -296,3 +347,59 @@ ccd_status build_problem(const ccd_problem& par, HostProblem& P, std::string& er
 }
 
 }  // namespace ccd
+
+// Gauss-Legendre rule by Newton's method on P_n, evaluated with the
+// three-term recurrence (k+1) P_{k+1} = (2k+1) x P_k - k P_{k-1}; nodes
+// ascending on [-1, 1], weights 2 / ((1 - x^2) P_n'(x)^2).
+static void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    const double pi = 3.14159265358979323846;
+    for (int i = 0; i < (n + 1) / 2; i++) {
+        double z = std::cos(pi * (i + 0.75) / (n + 0.5)), dp = 1.0;
+        for (int it = 0; it < 100; it++) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 1; k < n; k++) {
+                const double p2 = ((2.0 * k + 1.0) * z * p1 - k * p0) / (k + 1.0);
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+            const double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) break;
+        }
+        // recompute the derivative at the converged node for the weight
+        double p0 = 1.0, p1 = z;
+        for (int k = 1; k < n; k++) {
+            const double p2 = ((2.0 * k + 1.0) * z * p1 - k * p0) / (k + 1.0);
+            p0 = p1;
+            p1 = p2;
+        }
+        dp = n * (z * p1 - p0) / (z * z - 1.0);
+        const double wt = 2.0 / ((1.0 - z * z) * dp * dp);
+        x[n - 1 - i] = z;  w[n - 1 - i] = wt;
+        x[i] = -z;         w[i] = wt;
+    }
+    if (n & 1) x[n / 2] = 0.0;
+}
+
+extern "C" ccd_status ccd_twist_mesh(int32_t n, double* theta, double* weight) {
+    if (n < 1 || n > 64 || !theta || !weight) {
+        ccd::set_error("ccd_twist_mesh: n must be in [1, 64] and the buffers non-NULL");
+        return CCD_EINVAL;
+    }
+    std::vector<double> x, w;
+    gauss_legendre(n, x, w);
+    const double pi = 3.14159265358979323846, h = 0.5 * pi;
+    size_t k = 0;
+    for (int a = 0; a < n; a++)
+        for (int b = 0; b < n; b++)
+            for (int c = 0; c < n; c++, k++) {
+                theta[3 * k] = h * (x[a] + 1.0);
+                theta[3 * k + 1] = h * (x[b] + 1.0);
+                theta[3 * k + 2] = h * (x[c] + 1.0);
+                weight[k] = (h * w[a]) * (h * w[b]) * (h * w[c]) / (pi * pi * pi);
+            }
+    return CCD_OK;
+}
