@@ -63,6 +63,16 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ d4 mfma64(double a, double b, d4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
+// Four independent 4x4x4 FP64 products (blocks q = 0..3).  Lane l supplies
+// A_q[i][k] and B_q[k][j] at l = 16k + 4q + i (resp. + j) and receives
+// D_q[i][j] at l = 16i + 4q + j.  With the rows of a 16-row tile as 4q + i, the
+// A operand is laid out as for mfma64 (row l%16, k = l/16); every block takes
+// the same 4-column group of B (column l%4), and lane l receives row
+// 4 ((l%16)/4) + l/16, column l%4.  Narrow column groups waste 4x less than
+// 16-column tiles, and the instruction itself runs faster per flop.
+__device__ __forceinline__ double mfma4(double a, double b, double c) {
+    return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
+}
 
 
 // Mixed precision: FP32 operands on the 16x16x4 FP32 MFMA, or BF16 operands on
@@ -874,29 +884,47 @@ __global__ void __launch_bounds__(256) k_onebody(DevPtrs d) {
     }
 }
 
-// ladder sums per (64-row tile, 16-column tile of an S_z = 0 channel, problem):
+// ladder sums per (128-row tile, 16-column tile of an S_z = 0 channel, problem):
 // 1/2 sum_cd <ab||cd> t_ij^cd + 1/2 sum_kl t_kl^ab chi_klij into rmm.  Wave w
-// owns rows 16w .. 16w+15 of the tile.  The pp ladder runs on MFMA with
-// <ab||cd> generated per lane in the A-operand layout from W(m) in LDS, over
-// chunks of kKP particle-pair rows of t staged through registers one chunk
-// ahead; then the hh ladder on MFMA.  It needs t and chi_klij only, so it runs
-// beside the ring.  P selects the precision of the two contractions.
+// owns rows 32w .. 32w+31 of the tile as two 16-row MFMA tiles that share each
+// staged t operand and column descriptor (the LDS reads per MFMA are what
+// bound this kernel).  The pp ladder runs on MFMA with <ab||cd> generated per
+// lane in the A-operand layout from W(m) in LDS, over chunks of kKP
+// particle-pair rows of t staged through registers one chunk ahead; then the
+// hh ladder on MFMA.  It needs t and chi_klij only, so it runs beside the
+// ring.  P selects the precision of the two contractions.
+//
+// Generator.  In an S_z = 0 channel <ab||cd> = s_a s_c (W(|n_a - n_c|^2) +
+// W(|n_a - n_d|^2)) / 2 with s = +1 for spin up, -1 for spin down (c, d and a, b
+// have opposite spins).  With d = K - c and b = K - a,
+//   |n_a - n_c|^2 = A2 + C2 - 2 a.c,   |n_a - n_d|^2 = A2 - 2 a.K + D2 + 2 a.c,
+// so with S the byte size of a table entry both byte offsets follow from one
+// dot product: o1 = S A2 + S C2 - 2S a.c (sdot4 of -(S/2) n_a and 4 n_c, both
+// int8, accumulated onto the row and column constants) and
+// o2 = S (2 A2 - 2 a.K) + S (C2 + D2) - o1.  The column sign s_c picks a
+// negated copy of the table (its offset is folded into the column constants)
+// and the row sign s_a multiplies the finished sums.  Padding columns carry
+// c = K and D2 = 0, so both offsets stay inside the table (|n_b|^2 and A2); their
+// t rows are zero.
 constexpr int kKP = 128;  // particle-pair columns staged per barrier
 template <int P>
 __global__ void __launch_bounds__(256, 3) k_ladder(DevPtrs d, int cur, uint32_t mask, int n_items) {
     using ET = typename AccT<P>::E;   // element type of the generated operand
     using AT = typename AccT<P>::T;   // accumulator
-    __shared__ ET lutS[kMaxLut];
+    constexpr int S = (int)sizeof(ET);
+    constexpr int kNeg = S * kMaxLut;  // byte offset of the negated table
+    __shared__ ET lutS[2 * kMaxLut];
     // t chunk: [k][16] for FP64 / FP32, transposed [16][k] for BF16
     __shared__ __attribute__((aligned(16))) char tks[P == P_F64 ? kKP * 16 * 8 : (P == P_F32 ? kKP * 16 * 4 : 16 * (kKP + 8) * 2)];
-    // per staged column cd: (n_c packed as int8 x, y, z, 0; |n_c|^2 | |n_d|^2 << 10 | spin(c) << 20)
-    __shared__ int2 cvi[kKP];
+    // per staged column cd: (4 n_c as int8 x, y, z; S C2 + neg; S (C2 + D2) + 2 neg; 0)
+    __shared__ int4 cvi[kKP];
+    const char* lutB = (const char*)lutS;
     for (int bi = blockIdx.x; bi < n_items; bi += gridDim.x) {
     const Item lg = d.it_lg[bi];
     if (lg.chan < 0) continue;
     const int litem = lg.chan, g = lg.start;
     const Item it = d.it_ladder[litem];
-    const int r0 = it.start & 0xfffff, ct0 = it.start >> 20;  // row tile and column tile of the item
+    const int r0 = it.start & 0xfffff, ct = it.start >> 20;  // row tile and column tile of the item
     const DevChan c = d.chans[it.chan];
     const DevGroup G = d.groups[c.group];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -908,51 +936,59 @@ __global__ void __launch_bounds__(256, 3) k_ladder(DevPtrs d, int cur, uint32_t 
     const double* tcur = d.t[cur] + T0;
 
     __syncthreads();  // the previous item's reads of lutS are done
-    for (int e = threadIdx.x; e < G.nlut; e += 256) lutS[e] = (ET)d.lut[G.lut_base + g * G.nlut + e];
+    for (int e = threadIdx.x; e < G.nlut; e += 256) {
+        const ET v = (ET)d.lut[G.lut_base + g * G.nlut + e];
+        lutS[e] = v;
+        lutS[kMaxLut + e] = -v;
+    }
 
-    // generator row a of this lane (A-operand row = lane % 16); rows past the
-    // channel get a = 0, whose generated values are never stored
-    const int ra = r0 + 16 * w + (lane & 15);
-    const bool rav = ra < npp;
+    // generator rows of this lane (A-operand row = lane % 16) in the wave's two
+    // tiles; rows past the channel get a = 0, whose sums are never stored
+    const int rbase = r0 + 32 * w;
     const int32_t kpack = (int32_t)((uint32_t)(uint8_t)(int8_t)c.kx | ((uint32_t)(uint8_t)(int8_t)c.ky << 8) |
                                     ((uint32_t)(uint8_t)(int8_t)c.kz << 16));
     const int K2 = c.kx * c.kx + c.ky * c.ky + c.kz * c.kz;
-    int32_t apack = 0;
-    int A2 = 0, AK = 0, sa = 0;
-    if (rav) {
-        const int2 ri = d.ppinfo[c.pp_off + ra];
-        apack = ri.x;
-        sa = (ri.y >> 20) & 1;
-        A2 = ri.y & 1023;
-        AK = A2 - 2 * __builtin_amdgcn_sdot4(apack, kpack, 0, false);
+    // 4 n as packed int8 (|4 n_i| <= 64): shift each byte left by two, dropping
+    // the bits carried into the next byte
+    auto times4 = [](int32_t x) { return (int32_t)(((uint32_t)x << 2) & 0xfcfcfcfcu); };
+    int32_t apack[2] = {0, 0};  // -(S/2) n_a as packed int8
+    int rowA[2] = {0, 0}, rowS[2] = {0, 0};
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        const int ra = rbase + 16 * h + (lane & 15);
+        if (ra < npp) {
+            const int2 ri = d.ppinfo[c.pp_off + ra];
+            const int ax = (int8_t)(ri.x & 0xff), ay = (int8_t)((ri.x >> 8) & 0xff), az = (int8_t)((ri.x >> 16) & 0xff);
+            const int q = -(S / 2);
+            apack[h] = (int32_t)((uint32_t)(uint8_t)(int8_t)(q * ax) | ((uint32_t)(uint8_t)(int8_t)(q * ay) << 8) |
+                                 ((uint32_t)(uint8_t)(int8_t)(q * az) << 16));
+            const int A2 = ri.y & 1023;
+            const int aK = ax * c.kx + ay * c.ky + az * c.kz;
+            rowA[h] = S * A2;
+            rowS[h] = S * (2 * A2 - 2 * aK);
+        }
     }
-    // <ab||cd> for staged column k: with d = K - c and b = K - a,
-    //   |n_a - n_c|^2 = A2 + |n_c|^2 - 2 a.c,  |n_a - n_d|^2 = A2 - 2 a.K + |n_d|^2 + 2 a.c.
-    // Padding columns carry c = K, |n_d|^2 = 0: both indices stay inside the
-    // table (|n_b|^2 and A2) and their t rows are zero.
-    auto gen = [&](int k) -> ET {
-        const int2 ci = cvi[k];
-        const int ac = __builtin_amdgcn_sdot4(apack, ci.x, 0, false);
-        const int m1 = A2 + (ci.y & 1023) - 2 * ac;
-        const int m2 = AK + ((ci.y >> 10) & 1023) + 2 * ac;
-        const ET v = lutS[m1] + lutS[m2];
-        return (((ci.y >> 20) & 1) == sa) ? v : -v;
-    };
     // one staged chunk: t rows kp .. kp + kKP - 1 of column tile ct (zero past
     // the channel) and the column descriptors; loaded into registers one chunk
     // ahead of the MFMA work on the previous one
     constexpr int kPer = kKP * 16 / 256;
     double tv[kPer];
-    int2 cv = make_int2(kpack, K2);
-    auto load_chunk = [&](int ct, int kp) {
+    const int4 cpad = make_int4(times4(kpack), S * K2, S * K2, 0);
+    int4 cv = cpad;
+    auto load_chunk = [&](int kp) {
         const int kn = min(kKP, npp - kp);
 #pragma unroll
         for (int i = 0; i < kPer; i++) {
             const int e = threadIdx.x + 256 * i, kk = e >> 4, cc = ct * 16 + (e & 15);
             tv[i] = (kk < kn && cc < nhh) ? tcur[(int64_t)(kp + kk) * nhh + cc] : 0.0;
         }
-        cv = make_int2(kpack, K2);
-        if (threadIdx.x < kn) cv = d.ppinfo[c.pp_off + kp + threadIdx.x];
+        cv = cpad;
+        if (threadIdx.x < kn) {
+            const int2 q = d.ppinfo[c.pp_off + kp + threadIdx.x];
+            const int C2 = q.y & 1023, D2 = (q.y >> 10) & 1023;
+            const int neg = ((q.y >> 20) & 1) ? 0 : kNeg;  // s_c = -1 for spin down
+            cv = make_int4(times4(q.x), S * C2 + neg, S * (C2 + D2) + 2 * neg, 0);
+        }
     };
     auto store_chunk = [&]() {
 #pragma unroll
@@ -964,80 +1000,324 @@ __global__ void __launch_bounds__(256, 3) k_ladder(DevPtrs d, int cur, uint32_t 
         }
         if (threadIdx.x < kKP) cvi[threadIdx.x] = cv;
     };
-    for (int ct = ct0; ct < ct0 + 1; ct++) {
-        const int col = ct * 16 + (lane & 15);
-        AT acc = {0, 0, 0, 0}, acc2 = {0, 0, 0, 0};
-        if (pp_on) {
-            load_chunk(ct, 0);
-            for (int kp = 0; kp < npp; kp += kKP) {
-                const int kn = min(kKP, npp - kp);
-                __syncthreads();
-                store_chunk();
-                __syncthreads();
-                if (kp + kKP < npp) load_chunk(ct, kp + kKP);
-                if constexpr (P == P_BF16) {
-                    const int ksteps = (kn + 31) & ~31;
-                    for (int kk = 0; kk < ksteps; kk += 32) {
-                        const int k0 = kk + 8 * (lane >> 4);
-                        bf8 av;
+    // <ab||cd> (before the row sign) of tile h's row for column descriptor ci
+    auto gen = [&](const int4 ci, int h) -> ET {
+        const int o1 = __builtin_amdgcn_sdot4(apack[h], ci.x, rowA[h] + ci.y, false);
+        const int o2 = rowS[h] + ci.z - o1;
+        return *(const ET*)(lutB + o1) + *(const ET*)(lutB + o2);
+    };
+    const int col = ct * 16 + (lane & 15);
+    AT acc[2], acc2[2];
 #pragma unroll
-                        for (int j = 0; j < 8; j++) av[j] = (__bf16)gen(k0 + j);
-                        const bf8 bv = *(const bf8*)&((const __bf16*)tks)[(lane & 15) * (kKP + 8) + k0];
-                        acc = mfmabf(av, bv, acc);
+    for (int h = 0; h < 2; h++) { acc[h] = AT{0, 0, 0, 0}; acc2[h] = AT{0, 0, 0, 0}; }
+    if (pp_on) {
+        load_chunk(0);
+        for (int kp = 0; kp < npp; kp += kKP) {
+            const int kn = min(kKP, npp - kp);
+            __syncthreads();
+            store_chunk();
+            __syncthreads();
+            if (kp + kKP < npp) load_chunk(kp + kKP);
+            if constexpr (P == P_BF16) {
+                const int ksteps = (kn + 31) & ~31;
+                for (int kk = 0; kk < ksteps; kk += 32) {
+                    const int k0 = kk + 8 * (lane >> 4);
+                    bf8 av[2];
+#pragma unroll
+                    for (int j = 0; j < 8; j++) {
+                        const int4 ci = cvi[k0 + j];
+                        av[0][j] = (__bf16)gen(ci, 0);
+                        av[1][j] = (__bf16)gen(ci, 1);
                     }
-                } else {
-                    // eight MFMA steps per batch: all operands are produced first
-                    const int ksteps = (kn + 31) & ~31;
-                    for (int kk = 0; kk < ksteps; kk += 32) {
-                        ET va[8], vb[8];
+                    const bf8 bv = *(const bf8*)&((const __bf16*)tks)[(lane & 15) * (kKP + 8) + k0];
+                    acc[0] = mfmabf(av[0], bv, acc[0]);
+                    acc[1] = mfmabf(av[1], bv, acc[1]);
+                }
+            } else {
+                // four MFMA steps per batch for both tiles: all operands are
+                // produced first, each phase's LDS reads issued together
+                const int ksteps = (kn + 15) & ~15;
+                for (int kk = 0; kk < ksteps; kk += 16) {
+                    ET vb[4], x1[2][4], x2[2][4];
+                    int o1[2][4], o2[2][4];
 #pragma unroll
-                        for (int s = 0; s < 8; s++) {
-                            const int k = kk + 4 * s + (lane >> 4);
-                            va[s] = gen(k);
-                            vb[s] = ((const ET*)tks)[k * 16 + (lane & 15)];
+                    for (int s2 = 0; s2 < 4; s2++) {
+                        const int4 ci = cvi[kk + 4 * s2 + (lane >> 4)];
+#pragma unroll
+                        for (int h = 0; h < 2; h++) {
+                            o1[h][s2] = __builtin_amdgcn_sdot4(apack[h], ci.x, rowA[h] + ci.y, false);
+                            o2[h][s2] = rowS[h] + ci.z - o1[h][s2];
                         }
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                        for (int s = 0; s < 8; s += 2) {
+                    for (int s2 = 0; s2 < 4; s2++) {
+#pragma unroll
+                        for (int h = 0; h < 2; h++) {
+                            x1[h][s2] = *(const ET*)(lutB + o1[h][s2]);
+                            x2[h][s2] = *(const ET*)(lutB + o2[h][s2]);
+                        }
+                        vb[s2] = ((const ET*)tks)[(kk + 4 * s2 + (lane >> 4)) * 16 + (lane & 15)];
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                    for (int s2 = 0; s2 < 4; s2 += 2) {
+#pragma unroll
+                        for (int h = 0; h < 2; h++) {
+                            const ET va0 = x1[h][s2] + x2[h][s2], va1 = x1[h][s2 + 1] + x2[h][s2 + 1];
                             if constexpr (P == P_F64) {
-                                acc = mfma64(va[s], vb[s], acc);
-                                acc2 = mfma64(va[s + 1], vb[s + 1], acc2);
+                                acc[h] = mfma64(va0, vb[s2], acc[h]);
+                                acc2[h] = mfma64(va1, vb[s2 + 1], acc2[h]);
                             } else {
-                                acc = mfma32(va[s], vb[s], acc);
-                                acc2 = mfma32(va[s + 1], vb[s + 1], acc2);
+                                acc[h] = mfma32(va0, vb[s2], acc[h]);
+                                acc2[h] = mfma32(va1, vb[s2 + 1], acc2[h]);
                             }
                         }
                     }
                 }
             }
         }
-        if (hh_on) {
-            const double* xg = d.chh + G.chh_base + g * G.n_chh + c.chh_off;
-            for (int k0 = 0; k0 < nhh; k0 += 16) {
-                double a[4], b[4];
+        // row signs s_a of this lane's output rows
 #pragma unroll
-                for (int s = 0; s < 4; s++) {
-                    const int kq = k0 + 4 * s + (lane >> 4);
-                    a[s] = (rav && kq < nhh) ? tcur[(int64_t)ra * nhh + kq] : 0.0;
-                    b[s] = (kq < nhh && col < nhh) ? xg[kq * nhh + col] : 0.0;
-                }
-#pragma unroll
-                for (int s = 0; s < 4; s++) {
-                    if constexpr (P == P_F64) acc = mfma64(a[s], b[s], acc);
-                    else acc = mfma32((float)a[s], (float)b[s], acc);
-                }
-            }
-        }
-#pragma unroll
-        for (int r = 0; r < 4; r++) acc[r] += acc2[r];
-        // this lane owns rows orow(lane, r) of the wave's 16 rows, column col
-        if (act) {
+        for (int h = 0; h < 2; h++)
 #pragma unroll
             for (int r = 0; r < 4; r++) {
-                const int row = r0 + 16 * w + orow<P>(lane, r);
-                if (row < npp && col < nhh) d.rmm[T0 + (int64_t)row * nhh + col] = (double)acc[r];
+                const int row = rbase + 16 * h + orow<P>(lane, r);
+                const bool up = row < npp && ((d.ppinfo[c.pp_off + row].y >> 20) & 1);
+                acc[h][r] = up ? acc[h][r] + acc2[h][r] : -(acc[h][r] + acc2[h][r]);
+            }
+    }
+    if (hh_on) {
+        const double* xg = d.chh + G.chh_base + g * G.n_chh + c.chh_off;
+        for (int k0 = 0; k0 < nhh; k0 += 16) {
+            double b[4];
+#pragma unroll
+            for (int s2 = 0; s2 < 4; s2++) {
+                const int kq = k0 + 4 * s2 + (lane >> 4);
+                b[s2] = (kq < nhh && col < nhh) ? xg[kq * nhh + col] : 0.0;
+            }
+#pragma unroll
+            for (int h = 0; h < 2; h++) {
+                const int ra = rbase + 16 * h + (lane & 15);
+                double a[4];
+#pragma unroll
+                for (int s2 = 0; s2 < 4; s2++) {
+                    const int kq = k0 + 4 * s2 + (lane >> 4);
+                    a[s2] = (ra < npp && kq < nhh) ? tcur[(int64_t)ra * nhh + kq] : 0.0;
+                }
+#pragma unroll
+                for (int s2 = 0; s2 < 4; s2++) {
+                    if constexpr (P == P_F64) acc[h] = mfma64(a[s2], b[s2], acc[h]);
+                    else acc[h] = mfma32((float)a[s2], (float)b[s2], acc[h]);
+                }
             }
         }
     }
+    // this lane owns rows orow(lane, r) of each tile, column col
+    if (act) {
+#pragma unroll
+        for (int h = 0; h < 2; h++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int row = rbase + 16 * h + orow<P>(lane, r);
+                if (row < npp && col < nhh) d.rmm[T0 + (int64_t)row * nhh + col] = (double)acc[h][r];
+            }
+    }
+    }
+}
+
+// FP64 ladder sums on the 4x4x4 MFMA, with the items, generator and staging
+// of k_ladder: the 16-row tiles map onto the four blocks of the instruction and
+// the 16-column tile is cut into NG groups of four columns (NG = 1 .. 4, the
+// groups that hold columns of the channel), so a channel with n_hh = 2 costs
+// one instruction per K step instead of a 16-column product.  Each generated
+// <ab||cd> feeds all NG groups.  Accumulators alternate between two sets on
+// even and odd K steps.  The hh ladder uses the same layout.
+template <int NG>
+__device__ __forceinline__ void ladder64_item(const DevPtrs& d, const DevChan& c, const DevGroup& G, int g, int cur,
+                                              int r0, int ct, uint32_t mask, bool act, double* lutS,
+                                              double* tks, int4* cvi) {
+    constexpr int S = 8;
+    constexpr int kNeg = S * kMaxLut;
+    const char* lutB = (const char*)lutS;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int nhh = c.nhh, npp = c.npp;
+    const bool pp_on = act && (mask & CCD_T_PP) != 0;
+    const bool hh_on = act && (mask & (CCD_T_HH | CCD_T_QHH)) != 0;
+    const int64_t T0 = G.t_base + g * G.n_amp + c.t_off;
+    const double* tcur = d.t[cur] + T0;
+    const int rbase = r0 + 32 * w;
+    const int32_t kpack = (int32_t)((uint32_t)(uint8_t)(int8_t)c.kx | ((uint32_t)(uint8_t)(int8_t)c.ky << 8) |
+                                    ((uint32_t)(uint8_t)(int8_t)c.kz << 16));
+    const int K2 = c.kx * c.kx + c.ky * c.ky + c.kz * c.kz;
+    auto times4 = [](int32_t x) { return (int32_t)(((uint32_t)x << 2) & 0xfcfcfcfcu); };
+    int32_t apack[2] = {0, 0};
+    int rowA[2] = {0, 0}, rowS[2] = {0, 0};
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        const int ra = rbase + 16 * h + (lane & 15);
+        if (ra < npp) {
+            const int2 ri = d.ppinfo[c.pp_off + ra];
+            const int ax = (int8_t)(ri.x & 0xff), ay = (int8_t)((ri.x >> 8) & 0xff), az = (int8_t)((ri.x >> 16) & 0xff);
+            apack[h] = (int32_t)((uint32_t)(uint8_t)(int8_t)(-4 * ax) | ((uint32_t)(uint8_t)(int8_t)(-4 * ay) << 8) |
+                                 ((uint32_t)(uint8_t)(int8_t)(-4 * az) << 16));
+            const int A2 = ri.y & 1023;
+            const int aK = ax * c.kx + ay * c.ky + az * c.kz;
+            rowA[h] = S * A2;
+            rowS[h] = S * (2 * A2 - 2 * aK);
+        }
+    }
+    constexpr int kPer = kKP * 16 / 256;
+    double tv[kPer];
+    const int4 cpad = make_int4(times4(kpack), S * K2, S * K2, 0);
+    int4 cv = cpad;
+    auto load_chunk = [&](int kp) {
+        const int kn = min(kKP, npp - kp);
+#pragma unroll
+        for (int i = 0; i < kPer; i++) {
+            const int e = threadIdx.x + 256 * i, kk = e >> 4, cc = ct * 16 + (e & 15);
+            tv[i] = (kk < kn && cc < nhh) ? tcur[(int64_t)(kp + kk) * nhh + cc] : 0.0;
+        }
+        cv = cpad;
+        if (threadIdx.x < kn) {
+            const int2 q = d.ppinfo[c.pp_off + kp + threadIdx.x];
+            const int C2 = q.y & 1023, D2 = (q.y >> 10) & 1023;
+            const int neg = ((q.y >> 20) & 1) ? 0 : kNeg;
+            cv = make_int4(times4(q.x), S * C2 + neg, S * (C2 + D2) + 2 * neg, 0);
+        }
+    };
+    auto store_chunk = [&]() {
+#pragma unroll
+        for (int i = 0; i < kPer; i++) {
+            const int e = threadIdx.x + 256 * i;
+            tks[(e >> 4) * 16 + (e & 15)] = tv[i];
+        }
+        if (threadIdx.x < kKP) cvi[threadIdx.x] = cv;
+    };
+    // this lane's B column inside a group and its output row inside a tile
+    const int bj = lane & 3;
+    const int orow4 = 4 * ((lane & 15) >> 2) + (lane >> 4);
+    double acc[2][NG][2];
+#pragma unroll
+    for (int h = 0; h < 2; h++)
+#pragma unroll
+        for (int q = 0; q < NG; q++) { acc[h][q][0] = 0.0; acc[h][q][1] = 0.0; }
+    if (pp_on) {
+        load_chunk(0);
+        for (int kp = 0; kp < npp; kp += kKP) {
+            const int kn = min(kKP, npp - kp);
+            __syncthreads();
+            store_chunk();
+            __syncthreads();
+            if (kp + kKP < npp) load_chunk(kp + kKP);
+            const int ksteps = (kn + 15) & ~15;
+            for (int kk = 0; kk < ksteps; kk += 16) {
+                int o1[2][4], o2[2][4];
+#pragma unroll
+                for (int s2 = 0; s2 < 4; s2++) {
+                    const int4 ci = cvi[kk + 4 * s2 + (lane >> 4)];
+#pragma unroll
+                    for (int h = 0; h < 2; h++) {
+                        o1[h][s2] = __builtin_amdgcn_sdot4(apack[h], ci.x, rowA[h] + ci.y, false);
+                        o2[h][s2] = rowS[h] + ci.z - o1[h][s2];
+                    }
+                }
+                __builtin_amdgcn_sched_barrier(0);
+                double x1[2][4], x2[2][4], vb[4][NG];
+#pragma unroll
+                for (int s2 = 0; s2 < 4; s2++) {
+#pragma unroll
+                    for (int h = 0; h < 2; h++) {
+                        x1[h][s2] = *(const double*)(lutB + o1[h][s2]);
+                        x2[h][s2] = *(const double*)(lutB + o2[h][s2]);
+                    }
+#pragma unroll
+                    for (int q = 0; q < NG; q++) vb[s2][q] = tks[(kk + 4 * s2 + (lane >> 4)) * 16 + 4 * q + bj];
+                }
+#pragma unroll
+                for (int s2 = 0; s2 < 4; s2++) {
+#pragma unroll
+                    for (int h = 0; h < 2; h++) {
+                        const double va = x1[h][s2] + x2[h][s2];
+#pragma unroll
+                        for (int q = 0; q < NG; q++) acc[h][q][s2 & 1] = mfma4(va, vb[s2][q], acc[h][q][s2 & 1]);
+                    }
+                }
+            }
+        }
+        // row signs s_a of this lane's output rows
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const int row = rbase + 16 * h + orow4;
+            const bool up = row < npp && ((d.ppinfo[c.pp_off + row].y >> 20) & 1);
+#pragma unroll
+            for (int q = 0; q < NG; q++) {
+                const double v = acc[h][q][0] + acc[h][q][1];
+                acc[h][q][0] = up ? v : -v;
+                acc[h][q][1] = 0.0;
+            }
+        }
+    }
+    if (hh_on) {
+        // 1/2 sum_kl t_kl^ab chi_klij: A = t rows of the tile, B = chi_klij columns
+        const double* xg = d.chh + G.chh_base + g * G.n_chh + c.chh_off;
+        for (int k0 = 0; k0 < nhh; k0 += 4) {
+            const int kq = k0 + (lane >> 4);
+            double b[NG];
+#pragma unroll
+            for (int q = 0; q < NG; q++) {
+                const int cc = ct * 16 + 4 * q + bj;
+                b[q] = (kq < nhh && cc < nhh) ? xg[kq * nhh + cc] : 0.0;
+            }
+#pragma unroll
+            for (int h = 0; h < 2; h++) {
+                const int ra = rbase + 16 * h + (lane & 15);
+                const double a = (ra < npp && kq < nhh) ? tcur[(int64_t)ra * nhh + kq] : 0.0;
+#pragma unroll
+                for (int q = 0; q < NG; q++) acc[h][q][0] = mfma4(a, b[q], acc[h][q][0]);
+            }
+        }
+    }
+    if (act) {
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const int row = rbase + 16 * h + orow4;
+#pragma unroll
+            for (int q = 0; q < NG; q++) {
+                const int cc = ct * 16 + 4 * q + bj;
+                if (row < npp && cc < nhh) d.rmm[T0 + (int64_t)row * nhh + cc] = acc[h][q][0];
+            }
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256, 3) k_ladder64(DevPtrs d, int cur, uint32_t mask, int n_items) {
+    __shared__ double lutS[2 * kMaxLut];
+    __shared__ __attribute__((aligned(16))) double tks[kKP * 16];
+    __shared__ int4 cvi[kKP];
+    for (int bi = blockIdx.x; bi < n_items; bi += gridDim.x) {
+        const Item lg = d.it_lg[bi];
+        if (lg.chan < 0) continue;
+        const int g = lg.start;
+        const Item it = d.it_ladder[lg.chan];
+        const int r0 = it.start & 0xfffff, ct = it.start >> 20;
+        const DevChan c = d.chans[it.chan];
+        const DevGroup G = d.groups[c.group];
+        const bool act = d.active[G.p0 + g] != 0;
+        __syncthreads();  // the previous item's reads of LDS are done
+        for (int e = threadIdx.x; e < G.nlut; e += 256) {
+            const double v = d.lut[G.lut_base + g * G.nlut + e];
+            lutS[e] = v;
+            lutS[kMaxLut + e] = -v;
+        }
+        // groups of four columns of this column tile that hold columns
+        const int ng = min(4, (min(16, c.nhh - 16 * ct) + 3) >> 2);
+        switch (ng) {
+            case 1: ladder64_item<1>(d, c, G, g, cur, r0, ct, mask, act, lutS, tks, cvi); break;
+            case 2: ladder64_item<2>(d, c, G, g, cur, r0, ct, mask, act, lutS, tks, cvi); break;
+            case 3: ladder64_item<3>(d, c, G, g, cur, r0, ct, mask, act, lutS, tks, cvi); break;
+            default: ladder64_item<4>(d, c, G, g, cur, r0, ct, mask, act, lutS, tks, cvi); break;
+        }
     }
 }
 
@@ -1691,7 +1971,11 @@ template <int P>
 static ccd_status L_ladder(ccd_ctx* c, const DevPtrs& d, int cur, uint32_t mask) {
     const int n = (int)c->it_lg.size();
     if (mask & (CCD_T_PP | CCD_T_HH | CCD_T_QHH))
-        LAUNCH(F_LADDER, k_ladder<P>, grid_for(c, CCD_TUNE_LADDER, n), 256, 0, d, cur, mask, n);
+        if constexpr (P == P_F64) {
+            LAUNCH(F_LADDER, k_ladder64, grid_for(c, CCD_TUNE_LADDER, n), 256, 0, d, cur, mask, n);
+        } else {
+            LAUNCH(F_LADDER, k_ladder<P>, grid_for(c, CCD_TUNE_LADDER, n), 256, 0, d, cur, mask, n);
+        }
     return CCD_OK;
 }
 
