@@ -365,18 +365,24 @@ __global__ void __launch_bounds__(256, 3) k_warm(DevPtrs d, int cur, const float
 
 // per (item of kDirSplit particle-pair rows of an S_z = 0 channel, problem):
 // row sums of t v, the item's part of 1/2 sum_cd <kl||cd> t_ij^cd on MFMA over
-// LDS-staged 32-row chunks (FP64 in LDS, converted at the MFMA in the mixed
+// LDS-staged chunks of rows (FP64 in LDS, converted at the MFMA in the mixed
 // modes), and its part of the column sums (the diagonal of that product in
-// FP64; summed from the staged chunk in the mixed modes).
-// k_dsum adds the parts in a fixed order.  Wave w owns output tiles w, w+4, ...
-constexpr int kDirRows = 32;
+// FP64; summed from the staged chunk in the mixed modes).  Both operands are
+// amplitude-shaped blocks ([n_pp][n_hh] rows of <ab||ij> and t).  The staging
+// row stride follows the channel's tiles, so narrow channels stage more rows
+// per barrier.  With at most four 16x16 output tiles (n_hh <= 32) every wave
+// computes all tiles over every fourth 4-row K step of a chunk and the four
+// partial tiles are added in LDS in wave order; with more tiles wave w owns
+// tiles w, w+4, ...  k_dsum adds the items' parts in item order.
+constexpr int kDirBuf = 2048;  // doubles per staged operand
 template <int P>
 __global__ void __launch_bounds__(256) k_direct(DevPtrs d, int cur, uint32_t mask, int n_items) {
     using E = double;
     using AT = typename std::conditional<P == P_F64, d4, f4>::type;
     constexpr int PM = P == P_F64 ? P_F64 : P_F32;   // contraction precision used here
-    __shared__ __attribute__((aligned(16))) E vs[kDirRows][kMaxHH + 1];
-    __shared__ E ts[kDirRows][kMaxHH + 1];
+    __shared__ __attribute__((aligned(16))) E vs[kDirBuf];
+    __shared__ __attribute__((aligned(16))) E ts[kDirBuf];
+    __shared__ AT red[3][64];  // partial tiles of waves 1..3
     for (int bi = blockIdx.x; bi < n_items; bi += gridDim.x) {
     const Item it = d.it_direct[bi];
     if (it.chan < 0) continue;
@@ -386,57 +392,101 @@ __global__ void __launch_bounds__(256) k_direct(DevPtrs d, int cur, uint32_t mas
     const int g = it.start;
     if (!d.active[G.p0 + g]) continue;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int nhh = c.nhh, npp = c.npp, nt = (nhh + 15) >> 4;
+    const int nhh = c.nhh, npp = c.npp, nt = (nhh + 15) >> 4, ntt = nt * nt;
+    const int ld = nt * 16 + 1;                    // staging row stride
+    const int crows = (kDirBuf / ld) & ~3;         // rows per staged chunk
     const int k0 = sub.start, k1 = min(npp, k0 + kDirSplit), si = it.chan - c.dsub_lo;
     const int64_t E0 = G.t_base + g * G.n_amp + c.t_off;
     const double* t = d.t[cur] + E0;
     const double* vt = d.vt + E0;
     const bool quad = (mask & (CCD_T_QHH | CCD_T_QHOLE)) != 0;
+    const bool split = ntt <= 4;  // waves split K, each holding all tiles
     double* rows = d.rowsum + G.rows_base + g * G.n_rows + c.row_off;
     AT acc[4];
 #pragma unroll
     for (int k = 0; k < 4; k++) acc[k] = AT{0, 0, 0, 0};
     double cpart = 0.0;  // mixed modes: this thread's share of a column sum
-    for (int r0 = k0; r0 < k1; r0 += kDirRows) {
-        const int rc = min(kDirRows, k1 - r0);
-        __syncthreads();
-        for (int e = threadIdx.x; e < kDirRows * nhh; e += 256) {
-            int r = e / nhh, j = e - r * nhh;
-            bool ok = r < rc;
-            vs[r][j] = ok ? (E)vt[(int64_t)r0 * nhh + e] : (E)0;
-            ts[r][j] = ok ? (E)t[(int64_t)r0 * nhh + e] : (E)0;
+    // a chunk in the padded layout [crows][16 nt]: element e of it is loaded by
+    // thread e % 256 into register e / 256 (zero past the chunk and the block),
+    // one chunk ahead of the work on the previous one
+    constexpr int kPerD = kDirBuf / 256;
+    const int cw = 16 * nt;
+    double vr[kPerD], tr[kPerD];
+    auto load_chunk = [&](int r0) {
+        const int rc = min(crows, k1 - r0);
+#pragma unroll
+        for (int i = 0; i < kPerD; i++) {
+            const int e = threadIdx.x + 256 * i, r = e / cw, j = e - r * cw;
+            const bool ok = r < rc && j < nhh;
+            vr[i] = ok ? vt[(int64_t)(r0 + r) * nhh + j] : 0.0;
+            tr[i] = ok ? t[(int64_t)(r0 + r) * nhh + j] : 0.0;
         }
-        // zero the padding columns of the last tile
-        for (int e = threadIdx.x; e < kDirRows * (nt * 16 - nhh); e += 256) {
-            int r = e / (nt * 16 - nhh), j = nhh + e % (nt * 16 - nhh);
-            vs[r][j] = (E)0;
-            ts[r][j] = (E)0;
+    };
+    load_chunk(k0);
+    for (int r0 = k0; r0 < k1; r0 += crows) {
+        const int rc = min(crows, k1 - r0);
+        const int rpad = (rc + 3) & ~3;
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < kPerD; i++) {
+            const int e = threadIdx.x + 256 * i, r = e / cw, j = e - r * cw;
+            if (r < crows) { vs[r * ld + j] = vr[i]; ts[r * ld + j] = tr[i]; }
         }
         __syncthreads();
+        if (r0 + crows < k1) load_chunk(r0 + crows);
         // row sums of t v (one-body particle terms), FP64 in every mode
-        if ((mask & CCD_T_QPART) && threadIdx.x < rc) {
-            double sum = 0.0;
-            for (int j = 0; j < nhh; j++) sum += ts[threadIdx.x][j] * vs[threadIdx.x][j];
-            rows[r0 + threadIdx.x] = sum;
+        if (mask & CCD_T_QPART) {
+            for (int r = threadIdx.x; r < rc; r += 256) {
+                double sum = 0.0;
+                for (int j = 0; j < nhh; j++) sum += ts[r * ld + j] * vs[r * ld + j];
+                rows[r0 + r] = sum;
+            }
         }
         // mixed modes: this thread's share of a column sum, rows phase, phase + 4, ...
         if constexpr (P != P_F64) {
             const int j = threadIdx.x & 63;
             if ((mask & CCD_T_QHOLE) && j < nhh)
-                for (int r = threadIdx.x >> 6; r < rc; r += 4) cpart += ts[r][j] * vs[r][j];
+                for (int r = threadIdx.x >> 6; r < rc; r += 4) cpart += ts[r * ld + j] * vs[r * ld + j];
         }
         if (quad) {
+            const int col = lane & 15;
+            if (split) {
+                for (int kk = 4 * w; kk < rpad; kk += 16) {
+                    const int r = kk + (lane >> 4);
+                    // second column tile (nt = 2); with nt = 1 the same in-range
+                    // column is read and not used
+                    const int c1 = nt > 1 ? 16 + col : col;
+                    const E a0 = vs[r * ld + col], b0 = ts[r * ld + col];
+                    const E a1 = vs[r * ld + c1], b1 = ts[r * ld + c1];
+                    if constexpr (P == P_F64) {
+                        acc[0] = mfma64(a0, b0, acc[0]);
+                        if (nt > 1) {
+                            acc[1] = mfma64(a0, b1, acc[1]);
+                            acc[2] = mfma64(a1, b0, acc[2]);
+                            acc[3] = mfma64(a1, b1, acc[3]);
+                        }
+                    } else {
+                        acc[0] = mfma32((float)a0, (float)b0, acc[0]);
+                        if (nt > 1) {
+                            acc[1] = mfma32((float)a0, (float)b1, acc[1]);
+                            acc[2] = mfma32((float)a1, (float)b0, acc[2]);
+                            acc[3] = mfma32((float)a1, (float)b1, acc[3]);
+                        }
+                    }
+                }
+            } else {
 #pragma unroll
-            for (int k = 0; k < 4; k++) {
-                const int tile = w + 4 * k;
-                if (tile < nt * nt) {
-                    const int ti = tile / nt, tj = tile - ti * nt;
-#pragma unroll
-                    for (int kk = 0; kk < kDirRows; kk += 4) {
-                        E av = vs[kk + (lane >> 4)][ti * 16 + (lane & 15)];
-                        E bv = ts[kk + (lane >> 4)][tj * 16 + (lane & 15)];
-                        if constexpr (P == P_F64) acc[k] = mfma64(av, bv, acc[k]);
-                        else acc[k] = mfma32((float)av, (float)bv, acc[k]);
+                for (int k = 0; k < 4; k++) {
+                    const int tile = w + 4 * k;
+                    if (tile < ntt) {
+                        const int ti = tile / nt, tj = tile - ti * nt;
+                        for (int kk = 0; kk < rpad; kk += 4) {
+                            const int r = kk + (lane >> 4);
+                            const E av = vs[r * ld + ti * 16 + col];
+                            const E bv = ts[r * ld + tj * 16 + col];
+                            if constexpr (P == P_F64) acc[k] = mfma64(av, bv, acc[k]);
+                            else acc[k] = mfma32((float)av, (float)bv, acc[k]);
+                        }
                     }
                 }
             }
@@ -445,31 +495,46 @@ __global__ void __launch_bounds__(256) k_direct(DevPtrs d, int cur, uint32_t mas
     double* part = d.dpart + G.dpart_base + (int64_t)g * G.n_dpart + c.dpart_off + (int64_t)si * nhh * nhh;
     double* colp = d.dcolp + G.dcolp_base + (int64_t)g * G.n_dcolp + c.dcolp_off + (int64_t)si * nhh;
     if (quad) {
+        if (split) {
+            // add the partial tiles of waves 1..3 to wave 0's, tile by tile, in wave order
+            for (int k = 0; k < ntt; k++) {
+                __syncthreads();
+                if (w > 0) red[w - 1][lane] = acc[k];
+                __syncthreads();
+                if (w == 0) acc[k] = ((acc[k] + red[0][lane]) + red[1][lane]) + red[2][lane];
+            }
+        }
 #pragma unroll
         for (int k = 0; k < 4; k++) {
-            const int tile = w + 4 * k;
-            if (tile < nt * nt) {
-                const int ti = tile / nt, tj = tile - ti * nt;
+            int ti, tj;
+            if (split) {
+                // acc[k] holds tile (k / 2, k % 2) of the 2 x 2 layout
+                ti = k >> 1; tj = k & 1;
+                if (w != 0 || ti >= nt || tj >= nt) continue;
+            } else {
+                const int tile = w + 4 * k;
+                if (tile >= ntt) continue;
+                ti = tile / nt; tj = tile - ti * nt;
+            }
 #pragma unroll
-                for (int q = 0; q < 4; q++) {
-                    int kl = ti * 16 + orow<PM>(lane, q), ij = tj * 16 + (lane & 15);
-                    if (kl < nhh && ij < nhh) {
-                        const double qv = (double)acc[k][q];
-                        part[kl * nhh + ij] = qv;
-                        if (P == P_F64 && kl == ij) colp[kl] = qv;
-                    }
+            for (int q = 0; q < 4; q++) {
+                int kl = ti * 16 + orow<PM>(lane, q), ij = tj * 16 + (lane & 15);
+                if (kl < nhh && ij < nhh) {
+                    const double qv = (double)acc[k][q];
+                    part[kl * nhh + ij] = qv;
+                    if (P == P_F64 && kl == ij) colp[kl] = qv;
                 }
             }
         }
     }
     if constexpr (P != P_F64) {
         if (mask & CCD_T_QHOLE) {
-            double* red = (double*)&vs[0][0];  // 4 x 64 doubles
+            double* cred = vs;  // 4 x 64 doubles
             __syncthreads();
-            red[threadIdx.x] = cpart;
+            cred[threadIdx.x] = cpart;
             __syncthreads();
             if (threadIdx.x < nhh)
-                colp[threadIdx.x] = (red[threadIdx.x] + red[64 + threadIdx.x]) + (red[128 + threadIdx.x] + red[192 + threadIdx.x]);
+                colp[threadIdx.x] = (cred[threadIdx.x] + cred[64 + threadIdx.x]) + (cred[128 + threadIdx.x] + cred[192 + threadIdx.x]);
         }
     }
     }

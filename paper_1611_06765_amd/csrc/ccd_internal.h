@@ -16,7 +16,7 @@ constexpr int kMaxHH = 64;        // hole pairs of one direct channel (ladder ti
 constexpr int kMaxPH = 80;        // pairs of one particle-hole channel (2 N^2 doubles in LDS)
 constexpr int kLadderRows = 128;  // particle-pair rows per ladder work item
 constexpr int kElemChunk = 1024;  // amplitudes per elementwise work item
-constexpr int kDirSplit = 128;    // particle-pair rows per work item of the chi_klij product
+constexpr int kDirSplit = 256;    // particle-pair rows per work item of the chi_klij product
 constexpr int kMaxNmax2 = 64;     // cutoff limit: W(m) tables of 4 nmax2 + 1 entries live in LDS
 constexpr int kMaxLut = 4 * kMaxNmax2 + 1;
 
