@@ -418,7 +418,7 @@ def main():
                   for k in ("ladder", "direct") if fam_ms[k] > 0}
     dom = max(per_launch, key=lambda k: per_launch[k])
     achieved = fam_flops[dom] / (per_launch[dom] * 1e-3) / 1e12
-    roof = {"kernel": "k_ladder" if dom == "ladder" else "k_direct", "bound": "mfma",
+    roof = {"kernel": "k_ladder64" if dom == "ladder" else "k_direct", "bound": "mfma",
             "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP64_TFLOPS, "traffic": measured_traffic(dom),
             "ms_per_launch": per_launch[dom], "flops_per_launch": fam_flops[dom]}
