@@ -178,6 +178,18 @@ __device__ __forceinline__ double vas(const double* __restrict__ lut, int32_t p,
     return f > 0 ? w : -w;
 }
 
+// The same element when |n_p - n_r|^2 is known to be a constant of the block
+// (every ring element: p, r are the hole and particle of one member of a cross
+// channel Q, so |n_p - n_r|^2 = |Q|^2), with wr = W(|Q|^2)/2 read once.
+__device__ __forceinline__ double vas_q(const double* __restrict__ lut, double wr, int32_t p, int32_t q,
+                                        int32_t r, int32_t s) {
+    int sp = s_s(p), sq = s_s(q), sr = s_s(r), ss = s_s(s);
+    int f = (int)(sp == sr && sq == ss) - (int)(sp == ss && sq == sr);
+    if (f == 0) return 0.0;
+    double w = wr + lut[dist2(p, s)];
+    return f > 0 ? w : -w;
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     return v;
@@ -673,7 +685,8 @@ __device__ __forceinline__ void pair_stage(const DevPtrs& d, const Item it, int 
 // With TR set (BF16), A, At = A^T and Bt = B^T are written instead of A and B.
 template <typename E, int n16, int lda, int stride, bool TR>
 __device__ __forceinline__ void pair_fill(const PairCtx& r, const int32_t* qs, const int32_t* ps,
-                                          const double* lutS, E* A, E* B, E* At, E* Bt, int t0, bool qring) {
+                                          const double* lutS, double wq, E* A, E* B, E* At, E* Bt, int t0,
+                                          bool qring) {
     const int nq = r.nq, np = r.np;
     constexpr int tot = n16 * n16;
     for (int base = t0; base < tot; base += 8 * stride) {
@@ -694,7 +707,7 @@ __device__ __forceinline__ void pair_fill(const PairCtx& r, const int32_t* qs, c
                 int u = e / n16, x = e - u * n16;
                 double b = 0.0;
                 if (qring && u < np && x < nq)  // <kl||cd>: (c,k) = P member u, (d,l) = Q member x
-                    b = vas(lutS, ps[2 * u + 1], qs[2 * x + 1], ps[2 * u], qs[2 * x]);
+                    b = vas_q(lutS, wq, ps[2 * u + 1], qs[2 * x + 1], ps[2 * u], qs[2 * x]);
                 const E av = (E)((m[j] & 1) ? -tv[j] : tv[j]), bv = (E)b;
                 A[u * lda + x] = av;
                 if constexpr (TR) {
@@ -709,8 +722,8 @@ __device__ __forceinline__ void pair_fill(const PairCtx& r, const int32_t* qs, c
 }
 
 // <kb||cj> between members x, y of one list (states interleaved (p, h))
-__device__ __forceinline__ double pair_vph(const int32_t* s2, const double* lutS, int x, int y) {
-    return vas(lutS, s2[2 * x + 1], s2[2 * y], s2[2 * x], s2[2 * y + 1]);
+__device__ __forceinline__ double pair_vph(const int32_t* s2, const double* lutS, double wq, int x, int y) {
+    return vas_q(lutS, wq, s2[2 * x + 1], s2[2 * y], s2[2 * x], s2[2 * y + 1]);
 }
 
 template <int P, typename AT>
@@ -811,7 +824,10 @@ __device__ __forceinline__ void pair_body(const DevPtrs& d, const Item it, int c
         }
     }
     __syncthreads();
-    if (live) pair_fill<E, n16, lda, 64 * NW, P == P_BF16>(r, qs, ps, lutS, A, B, At, Bt, tid, qring);
+    // W(|Q|^2)/2, the first table entry of every element of the pair (member 0
+    // of Q: hole qs[1], particle qs[0])
+    const double wq = live ? lutS[dist2(qs[1], qs[0])] : 0.0;
+    if (live) pair_fill<E, n16, lda, 64 * NW, P == P_BF16>(r, qs, ps, lutS, wq, A, B, At, Bt, tid, qring);
     __syncthreads();
     // K extents: the contracted size rounded up to the MFMA K step (n_P for
     // A B and A V_P, n_Q for X A)
@@ -841,7 +857,7 @@ __device__ __forceinline__ void pair_body(const DevPtrs& d, const Item it, int c
             for (int q = 0; q < 4; q++) {
                 const int x = tx * 16 + orow<P>(lane, q), y = ty * 16 + (lane & 15);
                 double xv = (double)xq[k][q];
-                if (ring && x < r.nq && y < r.nq) xv += pair_vph(qs, lutS, x, y);
+                if (ring && x < r.nq && y < r.nq) xv += pair_vph(qs, lutS, wq, x, y);
                 XB[x * lda + y] = (E)xv;
             }
         }
@@ -869,7 +885,7 @@ __device__ __forceinline__ void pair_body(const DevPtrs& d, const Item it, int c
 #pragma unroll
             for (int q = 0; q < 4; q++) {
                 const int x = tx * 16 + orow<P>(lane, q), y = ty * 16 + (lane & 15);
-                const double vp = (ring && x < r.np && y < r.np) ? pair_vph(ps, lutS, x, y) : 0.0;
+                const double vp = (ring && x < r.np && y < r.np) ? pair_vph(ps, lutS, wq, x, y) : 0.0;
                 if constexpr (P == P_BF16) XB[y * lda + x] = (E)(float)vp;
                 else XB[x * lda + y] = (E)vp;
             }
