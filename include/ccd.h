@@ -234,6 +234,18 @@ ccd_status ccd_twist_mesh(int32_t n, double* theta, double* weight);
  * Errors: CCD_EINVAL, CCD_ESTATE (no workspace), CCD_EHIP. */
 ccd_status ccd_twist_average(const ccd_ctx* ctx, const double* weight, double* out);
 
+/* Third-order MBPT energies (sec. "Developing a CCD code for infinite
+ * matter", eqs. diag3-diag5): one Jacobi sweep of eq. ccd3 from the MBPT2
+ * amplitudes with only linear terms and no mixing changes the correlation
+ * energy by exactly the corresponding third-order diagrams, so for each of
+ * the pp ladder (4), the hh ladder (5), the ring (3) and all three,
+ * E3 = E(t1) - E_MBPT2.  out: host, 4 doubles per problem,
+ * [n_problems][4] = (pp, hh, ring, total), box totals in MeV.  FP64.  Leaves
+ * every problem at its MBPT2 amplitudes (as ccd_reset_amplitudes).
+ * Synchronises the stream.  Errors: CCD_EINVAL, CCD_ESTATE, CCD_EHIP,
+ * CCD_DIVERGED. */
+ccd_status ccd_mbpt3(ccd_ctx* ctx, double* out);
+
 /* Sizes and operation counts of problem `problem`. */
 ccd_status ccd_problem_info(const ccd_ctx* ctx, int32_t problem, ccd_info* info);
 

@@ -77,6 +77,7 @@ _SIGS = {
     "ccd_iterate": (_i32, [_vp, C.POINTER(ccd_solver_opts), _ip, _dp]),
     "ccd_energy": (_i32, [_vp, _i32, _dp, _dp, _dp]),
     "ccd_problem_info": (_i32, [_vp, _i32, C.POINTER(ccd_info)]),
+    "ccd_mbpt3": (_i32, [_vp, _dp]),
     "ccd_reference_parts": (_i32, [_vp, _i32, _dp, _dp]),
     "ccd_twist_mesh": (_i32, [_i32, _dp, _dp]),
     "ccd_twist_average": (_i32, [_vp, _dp, _dp]),
@@ -225,6 +226,13 @@ class Context:
         a, b, c = C.c_double(), C.c_double(), C.c_double()
         _check(_lib.ccd_energy(self._h, p, C.byref(a), C.byref(b), C.byref(c)), "ccd_energy")
         return a.value, b.value, c.value
+
+    def mbpt3(self):
+        """Third-order energies [n_problems][4] = (pp, hh, ring, total) in MeV;
+        leaves the context at its MBPT2 amplitudes."""
+        out = np.zeros((self.n, 4))
+        _check(_lib.ccd_mbpt3(self._h, _dptr(out)), "ccd_mbpt3")
+        return out
 
     def reference_parts(self, p=0):
         """(kinetic energy, Hartree-Fock potential energy) of the Fermi sea (host plan)."""

@@ -2483,6 +2483,34 @@ ccd_status ccd_iterate(ccd_ctx* c, const ccd_solver_opts* o, int32_t* sweeps_don
     return CCD_OK;
 }
 
+ccd_status ccd_mbpt3(ccd_ctx* c, double* out) {
+    if (!c || !out) { set_error("ccd_mbpt3: NULL argument"); return CCD_EINVAL; }
+    if (!c->bound) { set_error("ccd_mbpt3: no workspace bound"); return CCD_ESTATE; }
+    const int P = (int)c->probs.size();
+    const uint32_t masks[4] = {CCD_T_PP, CCD_T_HH, CCD_T_RING, CCD_T_PP | CCD_T_HH | CCD_T_RING};
+    ccd_solver_opts o;
+    std::memset(&o, 0, sizeof(o));
+    o.mixing = 1.0;
+    o.max_iter = 1;
+    o.precision = CCD_PREC_FP64;
+    o.check_every = 1;
+    std::vector<double> e(P);
+    for (int k = 0; k < 4; k++) {
+        ccd_status s = ccd_reset_amplitudes(c);
+        if (s != CCD_OK) return s;
+        o.terms = masks[k];
+        s = ccd_iterate(c, &o, nullptr, nullptr);
+        if (s != CCD_OK && s != CCD_NOT_CONVERGED) {
+            (void)ccd_reset_amplitudes(c);
+            return s;
+        }
+        HIP_TRY(hipMemcpyAsync(e.data(), c->ws + c->r_ecorr.off, 8 * P, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        for (int p = 0; p < P; p++) out[4 * p + k] = e[c->slot_of[p]] - c->emp2[p];
+    }
+    return ccd_reset_amplitudes(c);
+}
+
 ccd_status ccd_energy(const ccd_ctx* cc, int32_t p, double* eref, double* emp2, double* ecorr) {
     ccd_ctx* c = (ccd_ctx*)cc;
     if (!c || p < 0 || p >= (int)c->probs.size()) { set_error("ccd_energy: bad problem"); return CCD_EINVAL; }

@@ -355,13 +355,15 @@ def test_first_iteration_energy_is_mbpt2(orc):
     assert orc.O1(p.kinetic(), v, N).emp2 == pytest.approx(e2, rel=1e-12)
 
 
-@pytest.mark.parametrize("mask_name", ["PP", "HH", "RING", "LINEAR"])
-def test_linear_terms_reproduce_third_order_diagrams(orc, mask_name):
-    """One sweep from t^(0) with only linear terms adds the third-order
-    diagrams: pp ladder (4), hh ladder (5) and ring (3), eqs. diag3-diag5.
-    Diagram (3) is read with <bk|v|jc> in place of the printed <bk|v|ic>."""
-    p, v, eps = _dense_setup(orc, 14, 2, 0.12)
-    N, n = 14, p.ns
+def third_order_diagrams(orc, N, nmax2, rho, **kw):
+    """Third-order MBPT diagrams (4) pp ladder, (5) hh ladder and (3) ring of
+    eqs. diag3-diag5 by brute force over dense elements with Fock
+    denominators; diagram (3) read with <bk|v|jc> in place of the printed
+    <bk|v|ic>.  Returns (pnm, v, d4, d5, d3)."""
+    p = orc.PNM(N, nmax2, rho, **kw)
+    v = p.dense_v()
+    eps = p.fock()
+    n = p.ns
     H, P = range(N), range(N, n)
     D2 = lambda i, j, a, b: eps[i] + eps[j] - eps[a] - eps[b]
     vh = v  # dense <pq||rs>
@@ -387,6 +389,16 @@ def test_linear_terms_reproduce_third_order_diagrams(orc, mask_name):
                         d3 += x * y * vh[a, c, i, k] / (dij * D2(i, k, a, c))
     d4 /= 8.0
     d5 /= 8.0
+    return p, v, d4, d5, d3
+
+
+@pytest.mark.parametrize("mask_name", ["PP", "HH", "RING", "LINEAR"])
+def test_linear_terms_reproduce_third_order_diagrams(orc, mask_name):
+    """One sweep from t^(0) with only linear terms adds the third-order
+    diagrams: pp ladder (4), hh ladder (5) and ring (3), eqs. diag3-diag5.
+    Diagram (3) is read with <bk|v|jc> in place of the printed <bk|v|ic>."""
+    N = 14
+    p, v, d4, d5, d3 = third_order_diagrams(orc, N, 2, 0.12)
     T = {"PP": (orc.T_PP, d4), "HH": (orc.T_HH, d5), "RING": (orc.T_RING, d3),
          "LINEAR": (orc.T_LINEAR, d3 + d4 + d5)}
     mask, want = T[mask_name]
