@@ -246,6 +246,19 @@ ccd_status ccd_twist_average(const ccd_ctx* ctx, const double* weight, double* o
  * CCD_DIVERGED. */
 ccd_status ccd_mbpt3(ccd_ctx* ctx, double* out);
 
+/* Measured ceilings of the current GPU, for stating kernel rates against what
+ * the part reaches rather than only its published peaks:
+ *   out[0] HBM copy bandwidth, GB/s (read + write bytes; one half of dev_buf
+ *          copied onto the other, five passes);
+ *   out[1] FP64 MFMA 16x16x4, out[2] FP64 MFMA 4x4x4 (four blocks),
+ *   out[3] FP32 MFMA 16x16x4, out[4] BF16 MFMA 16x16x32 (FP32 accumulation),
+ *          TFLOP/s of resident loops (three workgroups of four waves per
+ *          compute unit, four independent accumulators per wave).
+ * dev_buf: caller-owned device memory, 256-byte aligned, at least 64 MiB (its
+ * contents are overwritten); work on hip_stream (NULL = default), which is
+ * synchronised.  No context needed.  Errors: CCD_EINVAL, CCD_EHIP. */
+ccd_status ccd_measure_ceilings(void* dev_buf, size_t bytes, void* hip_stream, double* out);
+
 /* Sizes and operation counts of problem `problem`. */
 ccd_status ccd_problem_info(const ccd_ctx* ctx, int32_t problem, ccd_info* info);
 

@@ -78,6 +78,7 @@ _SIGS = {
     "ccd_energy": (_i32, [_vp, _i32, _dp, _dp, _dp]),
     "ccd_problem_info": (_i32, [_vp, _i32, C.POINTER(ccd_info)]),
     "ccd_mbpt3": (_i32, [_vp, _dp]),
+    "ccd_measure_ceilings": (_i32, [_vp, _sz, _vp, _dp]),
     "ccd_reference_parts": (_i32, [_vp, _i32, _dp, _dp]),
     "ccd_twist_mesh": (_i32, [_i32, _dp, _dp]),
     "ccd_twist_average": (_i32, [_vp, _dp, _dp]),
@@ -136,6 +137,20 @@ def problem(n_particles, nmax2, density, hbar2_over_m=HBAR2_OVER_M, twist=(0.0, 
     return ccd_problem(n_particles, nmax2, density, hbar2_over_m,
                        p["V_R"], p["kappa_R"], p["V_S"], p["kappa_S"],
                        (C.c_double * 3)(*(float(x) for x in twist)))
+
+
+def measure_ceilings(nbytes=1 << 30, stream=None, device="cuda"):
+    """Measured ceilings of the GPU: dict of HBM copy GB/s and the FP64 / FP32 /
+    BF16 MFMA TFLOP/s of resident loops (ccd_measure_ceilings)."""
+    import torch
+    buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    ptr = (buf.data_ptr() + 255) & ~255
+    out = np.zeros(5)
+    sp = None if stream is None else _vp(stream)
+    _check(_lib.ccd_measure_ceilings(_vp(ptr), nbytes, sp, _dptr(out)), "ccd_measure_ceilings")
+    del buf
+    return {"hbm_copy_gbs": out[0], "fp64_mfma_16x16x4_tflops": out[1], "fp64_mfma_4x4x4_tflops": out[2],
+            "fp32_mfma_16x16x4_tflops": out[3], "bf16_mfma_16x16x32_tflops": out[4]}
 
 
 def twist_mesh(n):

@@ -212,3 +212,12 @@ def test_size_limits():
     with pytest.raises(ccd.CCDError) as e:
         _ctx(66, 65, 0.16)
     assert e.value.status == ccd.CCD_EINVAL
+
+
+def test_measure_ceilings_checks_its_arguments():
+    import numpy as np
+    out = np.zeros(5)
+    st = ccd._lib.ccd_measure_ceilings(None, 1 << 30, None, out.ctypes.data_as(ccd._dp))
+    assert st == ccd.CCD_EINVAL
+    st = ccd._lib.ccd_measure_ceilings(ccd._vp(4096 + 8), 1 << 30, None, out.ctypes.data_as(ccd._dp))
+    assert st == ccd.CCD_EINVAL  # misaligned
