@@ -259,6 +259,27 @@ ccd_status ccd_mbpt3(ccd_ctx* ctx, double* out);
  * synchronised.  No context needed.  Errors: CCD_EINVAL, CCD_EHIP. */
 ccd_status ccd_measure_ceilings(void* dev_buf, size_t bytes, void* hip_stream, double* out);
 
+/* Dense CCD for small model spaces given by their matrix elements, e.g. the
+ * pairing model of eqs. sppairing / intpairing (sec. "Developing a CCD code
+ * for infinite matter"): h[n] the one-body diagonal (canonical Hartree-Fock
+ * basis), v[n^4] the antisymmetrised <pq||rs> at ((p n + q) n + r) n + s (host,
+ * caller-owned), the lowest n_holes states are holes.  Fock energies
+ * eps_p = h_p + sum_i <pi||pi> (eq. pairingsp), E_ref = sum_i h_i +
+ * 1/2 sum_ij <ij||ij>, the MBPT2 start (eq. ccdGuess), then Jacobi sweeps of
+ * eq. ccd3 with the terms opts->terms (all eight = CCD_T_ALL), linear mixing
+ * opts->mixing, stop when |dE_n - dE_(n-1)| < tol + tol_rel |dE_n| (FP64; the
+ * other options are ignored).  One GPU thread per ordered amplitude: cost
+ * O(n_h^4 n_p^4) per sweep, a validation path, not the fast one.  2 <= n <= 48.
+ * dev_work: ccd_dense_workspace_size bytes of caller-owned device memory,
+ * 256-byte aligned.  Outputs are host pointers (nullable; e_hist: max_iter
+ * doubles, NAN past the last sweep).  Synchronises hip_stream once per sweep.
+ * Returns CCD_OK, CCD_NOT_CONVERGED, CCD_DIVERGED, CCD_EINVAL (also when a hole
+ * is not below every particle in Fock energy), CCD_EHIP. */
+ccd_status ccd_dense_workspace_size(int32_t n, int32_t n_holes, size_t* bytes);
+ccd_status ccd_dense_solve(const double* h, const double* v, int32_t n, int32_t n_holes,
+                           const ccd_solver_opts* opts, void* dev_work, size_t work_bytes, void* hip_stream,
+                           double* e_ref, double* e_mbpt2, double* e_ccd, int32_t* sweeps, double* e_hist);
+
 /* Sizes and operation counts of problem `problem`. */
 ccd_status ccd_problem_info(const ccd_ctx* ctx, int32_t problem, ccd_info* info);
 

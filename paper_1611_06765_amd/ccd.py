@@ -79,6 +79,9 @@ _SIGS = {
     "ccd_problem_info": (_i32, [_vp, _i32, C.POINTER(ccd_info)]),
     "ccd_mbpt3": (_i32, [_vp, _dp]),
     "ccd_measure_ceilings": (_i32, [_vp, _sz, _vp, _dp]),
+    "ccd_dense_workspace_size": (_i32, [_i32, _i32, C.POINTER(_sz)]),
+    "ccd_dense_solve": (_i32, [_dp, _dp, _i32, _i32, C.POINTER(ccd_solver_opts), _vp, _sz, _vp, _dp, _dp, _dp,
+                               _ip, _dp]),
     "ccd_reference_parts": (_i32, [_vp, _i32, _dp, _dp]),
     "ccd_twist_mesh": (_i32, [_i32, _dp, _dp]),
     "ccd_twist_average": (_i32, [_vp, _dp, _dp]),
@@ -151,6 +154,34 @@ def measure_ceilings(nbytes=1 << 30, stream=None, device="cuda"):
     del buf
     return {"hbm_copy_gbs": out[0], "fp64_mfma_16x16x4_tflops": out[1], "fp64_mfma_4x4x4_tflops": out[2],
             "fp32_mfma_16x16x4_tflops": out[3], "bf16_mfma_16x16x32_tflops": out[4]}
+
+
+def dense_solve(h, v, n_holes, mixing=1.0, tol=1e-10, max_iter=500, terms=CCD_T_ALL, tol_rel=0.0,
+                stream=None, device="cuda"):
+    """CCD of a small dense Hamiltonian (ccd_dense_solve): h[n] one-body
+    diagonal, v[n,n,n,n] antisymmetrised elements, the lowest n_holes states
+    holes.  Returns dict(status, e_ref, e_mbpt2, e_ccd, sweeps, history)."""
+    import torch
+    h = np.ascontiguousarray(h, dtype=np.float64)
+    n = h.size
+    v = np.ascontiguousarray(v, dtype=np.float64).reshape(-1)
+    if v.size != n ** 4:
+        raise ValueError("v must hold n^4 elements")
+    need = _sz()
+    _check(_lib.ccd_dense_workspace_size(n, n_holes, C.byref(need)), "ccd_dense_workspace_size")
+    buf = torch.empty(need.value + 256, dtype=torch.uint8, device=device)
+    ptr = (buf.data_ptr() + 255) & ~255
+    o = ccd_solver_opts(mixing, tol, max_iter, CCD_PREC_FP64, 0, terms, 0.0, 1, 0, tol_rel, 0)
+    er, e2, ec = C.c_double(), C.c_double(), C.c_double()
+    sw = C.c_int32()
+    hist = np.zeros(max_iter)
+    sp = None if stream is None else _vp(stream)
+    st = _lib.ccd_dense_solve(_dptr(h), _dptr(v), n, n_holes, C.byref(o), _vp(ptr), need.value, sp,
+                              C.byref(er), C.byref(e2), C.byref(ec), C.byref(sw), _dptr(hist))
+    _check(st, "ccd_dense_solve", ok=(CCD_OK, CCD_NOT_CONVERGED, CCD_DIVERGED))
+    del buf
+    return {"status": st, "e_ref": er.value, "e_mbpt2": e2.value, "e_ccd": ec.value, "sweeps": sw.value,
+            "history": hist[:sw.value]}
 
 
 def twist_mesh(n):

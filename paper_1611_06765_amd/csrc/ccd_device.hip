@@ -2051,12 +2051,13 @@ static ccd_status L_ring(ccd_ctx* c, const DevPtrs& d, int cur, uint32_t mask, i
 template <int P>
 static ccd_status L_ladder(ccd_ctx* c, const DevPtrs& d, int cur, uint32_t mask) {
     const int n = (int)c->it_lg.size();
-    if (mask & (CCD_T_PP | CCD_T_HH | CCD_T_QHH))
+    if (mask & (CCD_T_PP | CCD_T_HH | CCD_T_QHH)) {
         if constexpr (P == P_F64) {
             LAUNCH(F_LADDER, k_ladder64, grid_for(c, CCD_TUNE_LADDER, n), 256, 0, d, cur, mask, n);
         } else {
             LAUNCH(F_LADDER, k_ladder<P>, grid_for(c, CCD_TUNE_LADDER, n), 256, 0, d, cur, mask, n);
         }
+    }
     return CCD_OK;
 }
 

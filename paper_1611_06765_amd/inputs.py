@@ -83,3 +83,32 @@ def mlp_flatten(P):
     p[OFF_W3:OFF_B3] = P["W3"]
     p[OFF_B3] = P["b3"]
     return p
+
+
+def pairing_hamiltonian(g, delta=1.0, n_levels=4):
+    """The pairing model of eqs. sppairing / intpairing as dense arrays:
+    h[s] = delta (p - 1) for state s = 2 (p - 1) + (0 for spin up, 1 for
+    spin down), and the antisymmetrised elements <ab||cd> = <ab|V|cd> -
+    <ab|V|dc> of V = -g/2 sum_pq a+_{p+} a+_{p-} a_{q-} a_{q+}, whose direct
+    elements <p+ p-|V|q+ q-> = <p- p+|V|q- q+> = -g/2 are the only nonzero
+    ones (the operator moves a pair of opposite spins from level q to p)."""
+    n = 2 * n_levels
+    h = np.array([delta * (s // 2) for s in range(n)], dtype=np.float64)
+
+    def direct(a, b, c, d):
+        # <ab|V|cd>: a, b one pair of level p (a spin up, b spin down or the
+        # reverse), c, d one pair of level q in the same spin order
+        if a // 2 != b // 2 or c // 2 != d // 2 or a == b or c == d:
+            return 0.0
+        if a % 2 != c % 2:
+            return 0.0
+        return -0.5 * g
+
+    v = np.zeros((n, n, n, n))
+    for a in range(n):
+        for b in range(n):
+            for c in range(n):
+                for d in range(n):
+                    v[a, b, c, d] = direct(a, b, c, d) - direct(a, b, d, c)
+    return h, v
+

@@ -221,3 +221,23 @@ def test_measure_ceilings_checks_its_arguments():
     assert st == ccd.CCD_EINVAL
     st = ccd._lib.ccd_measure_ceilings(ccd._vp(4096 + 8), 1 << 30, None, out.ctypes.data_as(ccd._dp))
     assert st == ccd.CCD_EINVAL  # misaligned
+
+
+@pytest.mark.parametrize("n,nh", [(1, 1), (49, 4), (8, 0), (8, 8)])
+def test_dense_solver_limits(n, nh):
+    import ctypes
+    b = ctypes.c_size_t()
+    assert ccd._lib.ccd_dense_workspace_size(n, nh, ctypes.byref(b)) == ccd.CCD_EINVAL
+
+
+def test_pairing_hamiltonian_two_constructions_agree(orc):
+    """The input module's pairing elements (direct, then antisymmetrised) equal
+    the oracle's (signed pair factors), and the model's E_ref = 2 delta - g."""
+    import numpy as np
+    from paper_1611_06765_amd import inputs
+    for g in (-1.0, -0.3, 0.7):
+        h1, v1 = inputs.pairing_hamiltonian(g)
+        h2, v2 = orc.pairing_model(g)
+        assert np.array_equal(h1, h2) and np.array_equal(v1, v2)
+        eref = h1[:4].sum() + 0.5 * sum(v1[i, j, i, j] for i in range(4) for j in range(4))
+        assert eref == pytest.approx(2.0 - g, abs=1e-14)
