@@ -2,25 +2,24 @@
 //
 // One Jacobi sweep of eq. ccd3 in the intermediates form (sec. "Developing a
 // CCD code for infinite matter"), every term from the current amplitudes t:
-//   k_direct  per S_z = 0 block: chi_klij = <kl||ij> + 1/2 sum_cd <kl||cd> t_ij^cd
-//             (FP64 MFMA), and the row / column sums of t <ab||ij> that make the
-//             one-body intermediates
+//   k_direct  per S_z = 0 block: the parts of 1/2 sum_cd <kl||cd> t_ij^cd
+//   k_dsum    (MFMA), and the row / column sums of t <ab||ij>; k_dsum adds the
+//             parts and <kl||ij> into chi_klij
 //   k_dchi    one-body intermediates, diagonal by momentum conservation:
 //             chi_bb - f_bb = -1/2 sum_kld t_kl^bd <kl||bd>,
 //             chi_jj - f_jj = +1/2 sum_cdl <jl||cd> t_jl^cd
-//   k_ring    per cross channel Q: gather T~_Q[(a,i),(c,k)] = t_ik^ac, then
-//             chi~ = <kb||cj> + 1/2 Vbar T~_Q (chi_kbcj) and Z_Q = T~_Q chi~
-//             (sum_kc t_ik^ac chi_kbcj), both on FP64 MFMA in LDS; Z is written
-//             with its P(ij)P(ab) sign into four slots per canonical amplitude
-//   k_ladder  per S_z = 0 block and 64-row tile: pp ladder sum_{c<d} <ab||cd> t_ij^cd
-//             on FP64 MFMA with <ab||cd> generated in registers from W(m), hh
-//             ladder sum_{k<l} t_kl^ab chi_klij, ring slots, one-body terms,
-//             t_new = R / eps_ij^ab, linear mixing, energy partial sums
-//   k_update  the same update for the S_z = +-1 blocks (no ladders there)
+//   k_ringp   per pair {Q, -Q} of cross channels: gather T~_Q, generate the
+//             interaction blocks, the two ring terms of every amplitude in three
+//             MFMA products in LDS, stored to the amplitude's ring slots
+//   k_ladder  per S_z = 0 block, 128-row and 16-column tile: pp ladder
+//             1/2 sum_cd <ab||cd> t_ij^cd on MFMA with <ab||cd> generated in
+//             registers from W(m), plus the hh ladder 1/2 sum_kl t_kl^ab chi_klij
+//   k_update  every amplitude: <ab||ij> + ladder sums + ring slots + one-body
+//             terms, t_new = R / eps_ij^ab, linear mixing, energy partial sums
 //   k_energy  deterministic per-problem energy and convergence flag
-// Problems with the same (N, nmax2) share the integer tables; every work item
-// serves all problems of its group, so index arithmetic is done once for all
-// densities.  Reductions are fixed-order trees (no floating-point atomics):
+// Problems with the same (N, nmax2, twist) share the integer tables; every work
+// item serves all problems of its group, so index arithmetic is done once for
+// all densities.  Reductions are fixed-order trees (no floating-point atomics):
 // energies are bit-identical from run to run.
 #include <hip/hip_runtime.h>
 
