@@ -22,7 +22,7 @@ from . import ccd, inputs
 def converged_context(specs, stream, mixing=0.5, tol=1e-9, max_iter=3000):
     """Context of problems (N, nmax2, rho) iterated in FP64 until |dE| < tol."""
     ctx = ccd.Context([ccd.problem(*s) for s in specs], stream=stream).bind()
-    r = ctx.iterate(mixing=mixing, tol=tol, max_iter=max_iter, check_every=16, graph=True)
+    r = ctx.iterate(mixing=mixing, tol=tol, max_iter=max_iter, check_every=16)
     return ctx, r
 
 
