@@ -24,6 +24,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -127,6 +128,10 @@ struct DevPtrs {
     const Item* it_ring_s;   // (primary cross channel with n <= 16, problem in group)
     const Item* it_ring_b;   // (primary cross channel with n > 16, problem in group)
     const Item* it_lg;       // (ladder item, problem in group)
+    const int4* lpinfo;      // per momentum pair {p, q} of an S_z = 0 block: (p as int8 x, y, z, 0;
+                             // |p|^2 | |q|^2 << 10; row of (p up, q down); row of (p down, q up)), -1 = none
+    const Item* it_ladder64; // FP64 ladder items over momentum pairs (S_z = 0)
+    const Item* it_lg64;     // (FP64 ladder item, problem in group)
     const Item* it_ue;       // (elementwise item, problem in group): the update
     double* t[2];
     double* vt;              // <ab||ij>
@@ -1206,96 +1211,142 @@ __global__ void __launch_bounds__(256, 3) k_ladder(DevPtrs d, int cur, uint32_t 
     }
 }
 
-// FP64 ladder sums on the 4x4x4 MFMA, with the items, generator and staging
-// of k_ladder: the 16-row tiles map onto the four blocks of the instruction and
-// the 16-column tile is cut into NG groups of four columns (NG = 1 .. 4, the
-// groups that hold columns of the channel), so a channel with n_hh = 2 costs
-// one instruction per K step instead of a 16-column product.  Each generated
-// <ab||cd> feeds all NG groups.  Accumulators alternate between two sets on
-// even and odd K steps.  The hh ladder uses the same layout.
+// FP64 ladder sums over momentum pairs, on the 4x4x4 MFMA.
+//
+// In an S_z = 0 block the generated <ab||cd> = s_a s_c (W(|n_a - n_c|^2) +
+// W(|n_a - n_d|^2)) / 2 depends on the row only through s_a and n_a and on the
+// column only through s_c and the momenta (n_c, n_d).  The rows of a block come
+// in momentum pairs P = {p, q = K - p}: (p up, q down) and (p down, q up), or
+// the one row (p down, p up) when p = q; both rows of a pair have n_a = p.  So
+//   sum_cd <ab||cd> t_ij^cd = s_a u_ij(P_a),   u(P') = sum_P M[P'][P] delta(P),
+//   M[P'][P] = (W(|p' - p|^2) + W(|p' - q|^2)) / 2,
+//   delta(P) = t(p up, q down) - t(p down, q up)   (-t(p down, p up) if p = q),
+// a square product over the momentum pairs: a quarter of the multiply-adds and
+// of the table reads of the product over spin pairs.  M is generated per lane
+// in the A-operand layout with the generator of k_ladder (row p', column
+// (p, q), no column sign: it is in delta), delta is formed while a chunk of
+// kKP pairs is staged in LDS, and the finished u goes to the two rows of P' with
+// signs + and -.  The hh ladder 1/2 sum_kl t_kl^ab chi_klij then runs per row on
+// the same accumulators (one set per spin row).
+//
+// The 16-row tiles of pairs map onto the four blocks of the instruction and the
+// 16-column tile is cut into NG groups of four columns (NG = 1 .. 4, the groups
+// that hold columns of the channel).  Staging is pipelined one chunk ahead: the
+// column descriptors (with the two rows of each pair) of chunk c + 1 are in LDS
+// while chunk c is multiplied, so the t loads of chunk c + 1 are in flight then.
 template <int NG>
 __device__ __forceinline__ void ladder64_item(const DevPtrs& d, const DevChan& c, const DevGroup& G, int g, int cur,
                                               int r0, int ct, uint32_t mask, bool act, double* lutS,
-                                              double* tks, int4* cvi) {
+                                              double* tks, int4 (*cvi)[kKP]) {
     constexpr int S = 8;
-    constexpr int kNeg = S * kMaxLut;
     const char* lutB = (const char*)lutS;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int nhh = c.nhh, npp = c.npp;
+    const int nhh = c.nhh, nlp = c.n_lp;
     const bool pp_on = act && (mask & CCD_T_PP) != 0;
     const bool hh_on = act && (mask & (CCD_T_HH | CCD_T_QHH)) != 0;
     const int64_t T0 = G.t_base + g * G.n_amp + c.t_off;
     const double* tcur = d.t[cur] + T0;
+    const int4* lp = d.lpinfo + c.lp_off;
     const int rbase = r0 + 32 * w;
+    // this lane's B column inside a group and its output row inside a tile
+    const int bj = lane & 3;
+    const int orow4 = 4 * ((lane & 15) >> 2) + (lane >> 4);
     const int32_t kpack = (int32_t)((uint32_t)(uint8_t)(int8_t)c.kx | ((uint32_t)(uint8_t)(int8_t)c.ky << 8) |
                                     ((uint32_t)(uint8_t)(int8_t)c.kz << 16));
     const int K2 = c.kx * c.kx + c.ky * c.ky + c.kz * c.kz;
     auto times4 = [](int32_t x) { return (int32_t)(((uint32_t)x << 2) & 0xfcfcfcfcu); };
+
+    // generator rows (A layout)
     int32_t apack[2] = {0, 0};
     int rowA[2] = {0, 0}, rowS[2] = {0, 0};
 #pragma unroll
     for (int h = 0; h < 2; h++) {
-        const int ra = rbase + 16 * h + (lane & 15);
-        if (ra < npp) {
-            const int2 ri = d.ppinfo[c.pp_off + ra];
-            const int ax = (int8_t)(ri.x & 0xff), ay = (int8_t)((ri.x >> 8) & 0xff), az = (int8_t)((ri.x >> 16) & 0xff);
-            apack[h] = (int32_t)((uint32_t)(uint8_t)(int8_t)(-4 * ax) | ((uint32_t)(uint8_t)(int8_t)(-4 * ay) << 8) |
-                                 ((uint32_t)(uint8_t)(int8_t)(-4 * az) << 16));
-            const int A2 = ri.y & 1023;
-            const int aK = ax * c.kx + ay * c.ky + az * c.kz;
-            rowA[h] = S * A2;
-            rowS[h] = S * (2 * A2 - 2 * aK);
-        }
+        const int pr = rbase + 16 * h + (lane & 15);
+        const int4 li = pr < nlp ? lp[pr] : make_int4(0, 0, -1, -1);
+        const int ax = (int8_t)(li.x & 0xff), ay = (int8_t)((li.x >> 8) & 0xff), az = (int8_t)((li.x >> 16) & 0xff);
+        apack[h] = (int32_t)((uint32_t)(uint8_t)(int8_t)(-4 * ax) | ((uint32_t)(uint8_t)(int8_t)(-4 * ay) << 8) |
+                             ((uint32_t)(uint8_t)(int8_t)(-4 * az) << 16));
+        const int A2 = li.y & 1023;
+        const int aK = ax * c.kx + ay * c.ky + az * c.kz;
+        rowA[h] = S * A2;
+        rowS[h] = S * (2 * A2 - 2 * aK);
     }
+    // column descriptor: (4 p as int8, S |p|^2, S (|p|^2 + |q|^2), rows + 1 as
+    // two 16-bit fields); padding columns carry p = K, q = 0 and no rows, so
+    // both table offsets stay in range and delta is zero
+    const int4 cpad = make_int4(times4(kpack), S * K2, S * K2, 0);
+    auto cdesc = [&](const int4& li) {
+        const int C2 = li.y & 1023, D2 = (li.y >> 10) & 1023;
+        return make_int4(times4(li.x), S * C2, S * (C2 + D2),
+                         (int)((uint32_t)(li.z + 1) | ((uint32_t)(li.w + 1) << 16)));
+    };
     constexpr int kPer = kKP * 16 / 256;
     double tv[kPer];
-    const int4 cpad = make_int4(times4(kpack), S * K2, S * K2, 0);
-    int4 cv = cpad;
-    auto load_chunk = [&](int kp) {
-        const int kn = min(kKP, npp - kp);
+    // delta of chunk kp from the rows in cvi[b]
+    auto load_delta = [&](int kp, int b) {
+        const int kn = min(kKP, nlp - kp);
 #pragma unroll
         for (int i = 0; i < kPer; i++) {
             const int e = threadIdx.x + 256 * i, kk = e >> 4, cc = ct * 16 + (e & 15);
-            tv[i] = (kk < kn && cc < nhh) ? tcur[(int64_t)(kp + kk) * nhh + cc] : 0.0;
-        }
-        cv = cpad;
-        if (threadIdx.x < kn) {
-            const int2 q = d.ppinfo[c.pp_off + kp + threadIdx.x];
-            const int C2 = q.y & 1023, D2 = (q.y >> 10) & 1023;
-            const int neg = ((q.y >> 20) & 1) ? 0 : kNeg;
-            cv = make_int4(times4(q.x), S * C2 + neg, S * (C2 + D2) + 2 * neg, 0);
+            double v = 0.0;
+            if (kk < kn && cc < nhh) {
+                const uint32_t rr = (uint32_t)cvi[b][kk].w;
+                const int rp = (int)(rr & 0xffff) - 1, rm = (int)(rr >> 16) - 1;
+                const double tp = rp >= 0 ? tcur[(int64_t)rp * nhh + cc] : 0.0;
+                const double tm = rm >= 0 ? tcur[(int64_t)rm * nhh + cc] : 0.0;
+                v = tp - tm;
+            }
+            tv[i] = v;
         }
     };
-    auto store_chunk = [&]() {
+    auto store_delta = [&]() {
 #pragma unroll
         for (int i = 0; i < kPer; i++) {
             const int e = threadIdx.x + 256 * i;
             tks[(e >> 4) * 16 + (e & 15)] = tv[i];
         }
-        if (threadIdx.x < kKP) cvi[threadIdx.x] = cv;
     };
-    // this lane's B column inside a group and its output row inside a tile
-    const int bj = lane & 3;
-    const int orow4 = 4 * ((lane & 15) >> 2) + (lane >> 4);
+
     double acc[2][NG][2];
 #pragma unroll
     for (int h = 0; h < 2; h++)
 #pragma unroll
         for (int q = 0; q < NG; q++) { acc[h][q][0] = 0.0; acc[h][q][1] = 0.0; }
+
+    const double* lutg = d.lut + G.lut_base + g * G.nlut;
+    const double lv0 = threadIdx.x < G.nlut ? lutg[threadIdx.x] : 0.0;
+    const double lv1 = threadIdx.x + 256 < G.nlut ? lutg[threadIdx.x + 256] : 0.0;
+    int4 lpc = cpad;
+    if (pp_on && threadIdx.x < kKP && threadIdx.x < nlp) lpc = lp[threadIdx.x];
+    __syncthreads();  // the previous item's reads of LDS are done
+    lutS[threadIdx.x] = lv0;
+    if (threadIdx.x + 256 < kMaxLut) lutS[threadIdx.x + 256] = lv1;
     if (pp_on) {
-        load_chunk(0);
-        for (int kp = 0; kp < npp; kp += kKP) {
-            const int kn = min(kKP, npp - kp);
-            __syncthreads();
-            store_chunk();
-            __syncthreads();
-            if (kp + kKP < npp) load_chunk(kp + kKP);
+        if (threadIdx.x < kKP) cvi[0][threadIdx.x] = threadIdx.x < nlp ? cdesc(lpc) : cpad;
+        lpc = cpad;
+        if (threadIdx.x < kKP && kKP + threadIdx.x < nlp) lpc = lp[kKP + threadIdx.x];
+    }
+    __syncthreads();
+    if (pp_on) {
+        load_delta(0, 0);
+        store_delta();
+        for (int kp = 0; kp < nlp; kp += kKP) {
+            const int b = (kp / kKP) & 1;
+            const bool more = kp + kKP < nlp;
+            if (more && threadIdx.x < kKP) {
+                cvi[b ^ 1][threadIdx.x] = kp + kKP + threadIdx.x < nlp ? cdesc(lpc) : cpad;
+                lpc = cpad;
+                if (kp + 2 * kKP + threadIdx.x < nlp) lpc = lp[kp + 2 * kKP + threadIdx.x];
+            }
+            __syncthreads();  // this chunk's delta and the next chunk's descriptors are in LDS
+            if (more) load_delta(kp + kKP, b ^ 1);
+            const int kn = min(kKP, nlp - kp);
             const int ksteps = (kn + 15) & ~15;
             for (int kk = 0; kk < ksteps; kk += 16) {
                 int o1[2][4], o2[2][4];
 #pragma unroll
                 for (int s2 = 0; s2 < 4; s2++) {
-                    const int4 ci = cvi[kk + 4 * s2 + (lane >> 4)];
+                    const int4 ci = cvi[b][kk + 4 * s2 + (lane >> 4)];
 #pragma unroll
                     for (int h = 0; h < 2; h++) {
                         o1[h][s2] = __builtin_amdgcn_sdot4(apack[h], ci.x, rowA[h] + ci.y, false);
@@ -1324,72 +1375,80 @@ __device__ __forceinline__ void ladder64_item(const DevPtrs& d, const DevChan& c
                     }
                 }
             }
+            __syncthreads();  // every wave is done with this chunk
+            if (more) store_delta();
         }
-        // row signs s_a of this lane's output rows
+        // u of the lane's output pair: + to the (p up, q down) row, - to the other
 #pragma unroll
-        for (int h = 0; h < 2; h++) {
-            const int row = rbase + 16 * h + orow4;
-            const bool up = row < npp && ((d.ppinfo[c.pp_off + row].y >> 20) & 1);
+        for (int h = 0; h < 2; h++)
 #pragma unroll
             for (int q = 0; q < NG; q++) {
-                const double v = acc[h][q][0] + acc[h][q][1];
-                acc[h][q][0] = up ? v : -v;
-                acc[h][q][1] = 0.0;
+                const double u = acc[h][q][0] + acc[h][q][1];
+                acc[h][q][0] = u;
+                acc[h][q][1] = -u;
             }
-        }
+    }
+    // the two spin rows of the lane's A-operand pairs and of its output pairs
+    const int2* lpr = (const int2*)lp;
+    int arow[2][2], orow[2][2];
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        const int pr = rbase + 16 * h + (lane & 15), po = rbase + 16 * h + orow4;
+        const int2 ra = (hh_on && pr < nlp) ? lpr[2 * pr + 1] : make_int2(-1, -1);
+        const int2 ro = po < nlp ? lpr[2 * po + 1] : make_int2(-1, -1);
+        arow[h][0] = ra.x; arow[h][1] = ra.y;
+        orow[h][0] = ro.x; orow[h][1] = ro.y;
     }
     if (hh_on) {
-        // 1/2 sum_kl t_kl^ab chi_klij: A = t rows of the tile, B = chi_klij columns
+        // 1/2 sum_kl t_kl^ab chi_klij per spin row: A = t rows, B = chi_klij columns
         const double* xg = d.chh + G.chh_base + g * G.n_chh + c.chh_off;
         for (int k0 = 0; k0 < nhh; k0 += 4) {
             const int kq = k0 + (lane >> 4);
-            double b[NG];
+            double bb[NG];
 #pragma unroll
             for (int q = 0; q < NG; q++) {
                 const int cc = ct * 16 + 4 * q + bj;
-                b[q] = (kq < nhh && cc < nhh) ? xg[kq * nhh + cc] : 0.0;
+                bb[q] = (kq < nhh && cc < nhh) ? xg[kq * nhh + cc] : 0.0;
             }
 #pragma unroll
-            for (int h = 0; h < 2; h++) {
-                const int ra = rbase + 16 * h + (lane & 15);
-                const double a = (ra < npp && kq < nhh) ? tcur[(int64_t)ra * nhh + kq] : 0.0;
+            for (int h = 0; h < 2; h++)
 #pragma unroll
-                for (int q = 0; q < NG; q++) acc[h][q][0] = mfma4(a, b[q], acc[h][q][0]);
-            }
+                for (int s = 0; s < 2; s++) {
+                    const int r = arow[h][s];
+                    const double a = (r >= 0 && kq < nhh) ? tcur[(int64_t)r * nhh + kq] : 0.0;
+#pragma unroll
+                    for (int q = 0; q < NG; q++) acc[h][q][s] = mfma4(a, bb[q], acc[h][q][s]);
+                }
         }
     }
     if (act) {
 #pragma unroll
-        for (int h = 0; h < 2; h++) {
-            const int row = rbase + 16 * h + orow4;
+        for (int h = 0; h < 2; h++)
 #pragma unroll
-            for (int q = 0; q < NG; q++) {
-                const int cc = ct * 16 + 4 * q + bj;
-                if (row < npp && cc < nhh) d.rmm[T0 + (int64_t)row * nhh + cc] = acc[h][q][0];
+            for (int s = 0; s < 2; s++) {
+                const int r = orow[h][s];
+#pragma unroll
+                for (int q = 0; q < NG; q++) {
+                    const int cc = ct * 16 + 4 * q + bj;
+                    if (r >= 0 && cc < nhh) d.rmm[T0 + (int64_t)r * nhh + cc] = acc[h][q][s];
+                }
             }
-        }
     }
 }
 
 __global__ void __launch_bounds__(256, 3) k_ladder64(DevPtrs d, int cur, uint32_t mask, int n_items) {
-    __shared__ double lutS[2 * kMaxLut];
+    __shared__ double lutS[kMaxLut];
     __shared__ __attribute__((aligned(16))) double tks[kKP * 16];
-    __shared__ int4 cvi[kKP];
+    __shared__ int4 cvi[2][kKP];
     for (int bi = blockIdx.x; bi < n_items; bi += gridDim.x) {
-        const Item lg = d.it_lg[bi];
+        const Item lg = d.it_lg64[bi];
         if (lg.chan < 0) continue;
         const int g = lg.start;
-        const Item it = d.it_ladder[lg.chan];
+        const Item it = d.it_ladder64[lg.chan];
         const int r0 = it.start & 0xfffff, ct = it.start >> 20;
         const DevChan c = d.chans[it.chan];
         const DevGroup G = d.groups[c.group];
         const bool act = d.active[G.p0 + g] != 0;
-        __syncthreads();  // the previous item's reads of LDS are done
-        for (int e = threadIdx.x; e < G.nlut; e += 256) {
-            const double v = d.lut[G.lut_base + g * G.nlut + e];
-            lutS[e] = v;
-            lutS[kMaxLut + e] = -v;
-        }
         // groups of four columns of this column tile that hold columns
         const int ng = min(4, (min(16, c.nhh - 16 * ct) + 3) >> 2);
         switch (ng) {
@@ -1516,11 +1575,11 @@ struct ccd_ctx {
     std::vector<DevGroup> dgroups;
     std::vector<DevChan> dchans;
     std::vector<DevPh> dph;
-    std::vector<int32_t> ppinfo;
+    std::vector<int32_t> ppinfo, lpinfo;
     std::vector<int32_t> st, hh, pp, phmem, phmap, zs, csr_ptr, csr_idx, pgrp, pgi, it_sz0;
     std::vector<double> eps, lut, rowE, colE, pscale;
     std::vector<Item> it_elem, it_ladder, it_dchi, it_direct, it_ring_s, it_ring_b, it_lg, it_ue, it_dsub,
-        it_dsum;
+        it_dsum, it_ladder64, it_lg64;
     int64_t n_dpart = 0, n_dcolp = 0;
     int ring_lo[4] = {0}, ring_n[4] = {0};  // big pair items by padded size n16 = 32, 48, 64, 80
     std::vector<int64_t> prob_t0;  // amplitude index of each problem (caller order)
@@ -1564,7 +1623,8 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
     X(csr_idx, int32_t) X(pgrp, int32_t) X(pgi, int32_t) X(pscale, double) \
     X(it_elem, Item) X(it_ladder, Item) X(it_sz0, int32_t) X(it_dchi, Item) \
     X(it_direct, Item) X(it_ring_s, Item) X(it_ring_b, Item) X(it_lg, Item) X(it_ue, Item) \
-    X(it_dsub, Item) X(it_dsum, Item) X(ppinfo, int32_t)
+    X(it_dsub, Item) X(it_dsum, Item) X(ppinfo, int32_t) X(lpinfo, int32_t) X(it_ladder64, Item) \
+    X(it_lg64, Item)
 
 static DevPtrs make_ptrs(ccd_ctx* c) {
     DevPtrs d;
@@ -1577,6 +1637,7 @@ static DevPtrs make_ptrs(ccd_ctx* c) {
     const void* p_it_dchi; const void* p_it_direct; const void* p_it_ring_s; const void* p_it_ring_b;
     const void* p_it_lg; const void* p_it_ue; const void* p_zs; const void* p_rowE; const void* p_colE;
     const void* p_pscale; const void* p_it_dsub; const void* p_it_dsum; const void* p_ppinfo;
+    const void* p_lpinfo; const void* p_it_ladder64; const void* p_it_lg64;
 #define TAKE(name, T)             \
     p_##name = base + o;          \
     o += align256(c->name.size() * sizeof(T));
@@ -1597,6 +1658,8 @@ static DevPtrs make_ptrs(ccd_ctx* c) {
     d.pscale = (const double*)p_pscale;
     d.it_dsub = (const Item*)p_it_dsub; d.it_dsum = (const Item*)p_it_dsum;
     d.ppinfo = (const int2*)p_ppinfo;
+    d.lpinfo = (const int4*)p_lpinfo;
+    d.it_ladder64 = (const Item*)p_it_ladder64; d.it_lg64 = (const Item*)p_it_lg64;
     d.dpart = (double*)(base + c->r_dpart.off);
     d.dcolp = (double*)(base + c->r_dcolp.off);
     d.t[0] = (double*)(base + c->r_t0.off);
@@ -1732,8 +1795,8 @@ static ccd_status assemble(ccd_ctx* c) {
     c->pgi.assign(P, 0);
     c->prob_t0.assign(P, 0);
     c->slot_of.assign(P, 0);
-    std::vector<std::pair<int, Item>> lg, ue, dir, dsum, rs, rb[4];
-    std::vector<double> lg_cost;
+    std::vector<std::pair<int, Item>> lg, lg64, ue, dir, dsum, rs, rb[4];
+    std::vector<double> lg_cost, lg64_cost;
     int64_t t_base = 0;
     int gi = 0, slot0 = 0;
     for (auto& kv : by_structure) {
@@ -1823,6 +1886,45 @@ static ccd_status assemble(ccd_ctx* c) {
                             lg_cost.push_back((double)h.npp);  // MFMA steps of the item
                         }
                     }
+                // momentum pairs {n_a, n_b} of the rows, in order of first row;
+                // a row's pair is keyed by n_a (b follows from K and the spins)
+                if (h.npp >= 0xffff) {  // rows travel as 16-bit fields in the kernel
+                    set_error("an S_z = 0 block has more than 65534 particle pairs");
+                    return CCD_EINVAL;
+                }
+                dc.lp_off = (int)(c->lpinfo.size() / 4);
+                std::map<std::tuple<int, int, int>, int> lp_of;
+                std::vector<std::array<int32_t, 4>> lps;
+                for (int r = 0; r < h.npp; r++) {
+                    const int a = H.pp[2 * (h.pp_off + r)], b = H.pp[2 * (h.pp_off + r) + 1];
+                    auto ins = lp_of.insert({{H.nx[a], H.ny[a], H.nz[a]}, (int)lps.size()});
+                    if (ins.second) {
+                        const int A2 = H.nx[a] * H.nx[a] + H.ny[a] * H.ny[a] + H.nz[a] * H.nz[a];
+                        const int B2 = H.nx[b] * H.nx[b] + H.ny[b] * H.ny[b] + H.nz[b] * H.nz[b];
+                        lps.push_back({pack_state(H.nx[a], H.ny[a], H.nz[a], 0), A2 | (B2 << 10), -1, -1});
+                    }
+                    int32_t& slot = lps[ins.first->second][H.sz[a] > 0 ? 2 : 3];
+                    if (slot >= 0) {
+                        set_error("internal: two rows of one S_z = 0 block share a and its spin");
+                        return CCD_EINVAL;
+                    }
+                    slot = r;
+                }
+                if ((int)lps.size() != h.nlp) {
+                    set_error("internal: momentum-pair count of an S_z = 0 block");
+                    return CCD_EINVAL;
+                }
+                for (auto& e : lps) c->lpinfo.insert(c->lpinfo.end(), e.begin(), e.end());
+                dc.n_lp = h.nlp;
+                for (int r0 = 0; r0 < h.nlp; r0 += kLadderRows)
+                    for (int ct = 0; ct < (h.nhh + 15) / 16; ct++) {
+                        const int li = (int)c->it_ladder64.size();
+                        c->it_ladder64.push_back({id, r0 | (ct << 20)});
+                        for (int g = 0; g < D.G; g++) {
+                            lg64.push_back({slot0 + g, Item{li, g}});
+                            lg64_cost.push_back((double)h.nlp);
+                        }
+                    }
             }
             const int nel = h.nhh * h.npp;
             for (int e0 = 0; e0 < nel; e0 += kElemChunk) {
@@ -1904,6 +2006,7 @@ static ccd_status assemble(ccd_ctx* c) {
 
     if (c->csr_idx.empty()) c->csr_idx.push_back(0);
     c->it_lg = xcd_order_cost(lg, lg_cost);
+    c->it_lg64 = xcd_order_cost(lg64, lg64_cost);
     c->it_ue = xcd_order(ue);
     c->it_direct = xcd_order(dir);
     c->it_dsum = xcd_order(dsum);
@@ -2049,11 +2152,12 @@ static ccd_status L_ring(ccd_ctx* c, const DevPtrs& d, int cur, uint32_t mask, i
 
 template <int P>
 static ccd_status L_ladder(ccd_ctx* c, const DevPtrs& d, int cur, uint32_t mask) {
-    const int n = (int)c->it_lg.size();
     if (mask & (CCD_T_PP | CCD_T_HH | CCD_T_QHH)) {
         if constexpr (P == P_F64) {
+            const int n = (int)c->it_lg64.size();
             LAUNCH(F_LADDER, k_ladder64, grid_for(c, CCD_TUNE_LADDER, n), 256, 0, d, cur, mask, n);
         } else {
+            const int n = (int)c->it_lg.size();
             LAUNCH(F_LADDER, k_ladder<P>, grid_for(c, CCD_TUNE_LADDER, n), 256, 0, d, cur, mask, n);
         }
     }

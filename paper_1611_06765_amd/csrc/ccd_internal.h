@@ -71,6 +71,7 @@ struct DevChan {
     int32_t rowa_off, cola_off;     // first row / column of the block among all rows / columns
     int32_t dsub_lo, dsub_n;        // S_z = 0: items of kDirSplit rows of the chi_klij product
     int32_t dpart_off, dcolp_off;   // S_z = 0: local offsets of their partial sums
+    int32_t lp_off, n_lp;           // S_z = 0: momentum pairs of the rows (global offset, count)
 };
 
 struct DevPh {
@@ -89,6 +90,7 @@ struct Item {             // work item: a channel and a start (row or element)
 struct Chan {
     int Kx, Ky, Kz, Sz;   // Sz = 2 S_z
     int nhh, npp;
+    int nlp;              // S_z = 0: momentum pairs {n_a, n_b} of the rows
     int64_t t_off;        // local to the problem
     int hh_off, pp_off;   // local to the problem (in pairs)
 };

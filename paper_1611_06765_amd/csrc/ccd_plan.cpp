@@ -37,6 +37,7 @@
 #include <array>
 #include <cmath>
 #include <map>
+#include <set>
 #include <tuple>
 
 #include "ccd_internal.h"
@@ -169,7 +170,7 @@ ccd_status build_problem(const ccd_problem& par, HostProblem& P, std::string& er
         Chan c;
         c.Sz = std::get<0>(kv.first); c.Kx = std::get<1>(kv.first);
         c.Ky = std::get<2>(kv.first); c.Kz = std::get<3>(kv.first);
-        c.nhh = nhh; c.npp = npp;
+        c.nhh = nhh; c.npp = npp; c.nlp = 0;
         c.t_off = toff;
         c.hh_off = (int)P.hh.size() / 2;
         c.pp_off = (int)P.pp.size() / 2;
@@ -181,8 +182,17 @@ ccd_status build_problem(const ccd_problem& par, HostProblem& P, std::string& er
         P.max_pp = std::max(P.max_pp, npp);
         if (c.Sz == 0) {
             P.n_sz0++;
-            double M = npp, Nn = nhh;
-            P.flops_pp += 2.0 * M * M * Nn;
+            // rows with a spin-down a, plus spin-up rows whose spin-down
+            // partner (the same momenta) is missing: one per momentum pair
+            std::set<std::tuple<int, int, int>> moms;
+            for (size_t k = 0; k < kv.second.second.size(); k += 2) {
+                const int a = kv.second.second[k];
+                moms.insert({P.nx[a], P.ny[a], P.nz[a]});
+            }
+            P.chans.back().nlp = (int)moms.size();
+            double M = npp, Nn = nhh, Mr = (double)moms.size();
+            // executed by the FP64 path: the product over momentum pairs
+            P.flops_pp += 2.0 * Mr * Mr * Nn;
             P.flops_hh += 2.0 * M * Nn * Nn + 2.0 * Nn * Nn * M;  // hh ladder + chi_klij
             P.flops_ordered += 8.0 * (2.0 * M * M * Nn + 4.0 * M * Nn * Nn);
         }

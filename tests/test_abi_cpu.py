@@ -141,7 +141,15 @@ def test_operation_counts_match_definition():
     ch = c.export_map(ccd.CCD_MAP_CHANNELS).reshape(-1, 6)
     sz0 = ch[ch[:, 3] == 0]
     M, Nn = sz0[:, 5].astype(float), sz0[:, 4].astype(float)
-    assert i["flops_pp"] == pytest.approx(np.sum(2 * M * M * Nn))
+    # the FP64 pp product runs over the momentum pairs {n_a, n_b} of each block:
+    # the distinct momenta of the rows' first states
+    st = c.export_map(ccd.CCD_MAP_STATES).reshape(-1, 4)
+    pp = c.export_map(ccd.CCD_MAP_PP).reshape(-1, 2)
+    off = np.concatenate([[0], np.cumsum(ch[:, 5])])
+    Mr = np.array([len({tuple(st[a, :3]) for a in pp[off[k]:off[k + 1], 0]})
+                   for k in range(len(ch)) if ch[k, 3] == 0], dtype=float)
+    assert np.all((Mr >= M / 2) & (Mr <= (M + 1) / 2))
+    assert i["flops_pp"] == pytest.approx(np.sum(2 * Mr * Mr * Nn))
     ph = c.export_map(ccd.CCD_MAP_PH_CHANNELS).reshape(-1, 6)
     assert i["flops_ring"] == pytest.approx(np.sum(4.0 * ph[:, 4].astype(float) ** 3))
     # ordered-pair form of the paper: pp + hh + chi_klij at ordered pairs + ring
