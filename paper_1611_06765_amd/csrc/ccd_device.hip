@@ -107,7 +107,6 @@ struct DevPtrs {
     const DevPh* ph;
     const int32_t* hh;       // packed pairs (per structure)
     const int32_t* pp;
-    const int2* ppinfo;      // per particle pair (c, d): (n_c as int8 x, y, z, 0; |n_c|^2 | |n_d|^2 << 10 | spin(c) << 20)
     const int32_t* phmem;
     const int32_t* phmap;
     const int32_t* csr_ptr;
@@ -119,7 +118,7 @@ struct DevPtrs {
     const int32_t* pgi;      // per problem: index inside the group
     const double* pscale;    // per problem: rho, 2 pi / L, L^3 / 1000 (network features)
     const Item* it_elem;     // elementwise items, all channels
-    const Item* it_ladder;   // ladder items (S_z = 0)
+    const Item* it_ladder;   // ladder items over momentum pairs (S_z = 0)
     const int32_t* it_sz0;   // S_z = 0 channel ids
     const Item* it_dchi;     // (group, first state)
     const Item* it_dsub;     // (S_z = 0 channel, first row) of the chi_klij product items
@@ -130,8 +129,6 @@ struct DevPtrs {
     const Item* it_lg;       // (ladder item, problem in group)
     const int4* lpinfo;      // per momentum pair {p, q} of an S_z = 0 block: (p as int8 x, y, z, 0;
                              // |p|^2 | |q|^2 << 10; row of (p up, q down); row of (p down, q up)), -1 = none
-    const Item* it_ladder64; // FP64 ladder items over momentum pairs (S_z = 0)
-    const Item* it_lg64;     // (FP64 ladder item, problem in group)
     const Item* it_ue;       // (elementwise item, problem in group): the update
     double* t[2];
     double* vt;              // <ab||ij>
@@ -969,66 +966,54 @@ __global__ void __launch_bounds__(256) k_onebody(DevPtrs d) {
     }
 }
 
-// ladder sums per (128-row tile, 16-column tile of an S_z = 0 channel, problem):
-// 1/2 sum_cd <ab||cd> t_ij^cd + 1/2 sum_kl t_kl^ab chi_klij into rmm.  Wave w
-// owns rows 32w .. 32w+31 of the tile as two 16-row MFMA tiles that share each
-// staged t operand and column descriptor (the LDS reads per MFMA are what
-// bound this kernel).  The pp ladder runs on MFMA with <ab||cd> generated per
-// lane in the A-operand layout from W(m) in LDS, over chunks of kKP
-// particle-pair rows of t staged through registers one chunk ahead; then the
-// hh ladder on MFMA.  It needs t and chi_klij only, so it runs beside the
-// ring.  P selects the precision of the two contractions.
+// ladder sums per (128-pair tile, 16-column tile of an S_z = 0 channel,
+// problem): 1/2 sum_cd <ab||cd> t_ij^cd + 1/2 sum_kl t_kl^ab chi_klij into rmm.
+// They need t and chi_klij only, so they run beside the ring.  Both kernels
+// run the pp sum as a product over the momentum pairs P = {p, K - p} of the
+// block (see k_ladder64 below for the identity): wave w owns pairs 32w ..
+// 32w+31 of the tile as two 16-row MFMA tiles that share each staged operand
+// and column descriptor, and each finished sum goes to the two spin rows of
+// its pair with signs + and -.
 //
-// Generator.  In an S_z = 0 channel <ab||cd> = s_a s_c (W(|n_a - n_c|^2) +
-// W(|n_a - n_d|^2)) / 2 with s = +1 for spin up, -1 for spin down (c, d and a, b
-// have opposite spins).  With d = K - c and b = K - a,
-//   |n_a - n_c|^2 = A2 + C2 - 2 a.c,   |n_a - n_d|^2 = A2 - 2 a.K + D2 + 2 a.c,
-// so with S the byte size of a table entry both byte offsets follow from one
-// dot product: o1 = S A2 + S C2 - 2S a.c (sdot4 of -(S/2) n_a and 4 n_c, both
-// int8, accumulated onto the row and column constants) and
-// o2 = S (2 A2 - 2 a.K) + S (C2 + D2) - o1.  The column sign s_c picks a
-// negated copy of the table (its offset is folded into the column constants)
-// and the row sign s_a multiplies the finished sums.  Padding columns carry
-// c = K and D2 = 0, so both offsets stay inside the table (|n_b|^2 and A2); their
-// t rows are zero.
-constexpr int kKP = 128;  // particle-pair columns staged per barrier
+// Generator.  With p' the row pair's first momentum and (p, q = K - p) the
+// column pair's, M[P'][P] = (W(|p' - p|^2) + W(|p' - q|^2)) / 2.  With S the
+// byte size of a table entry both table byte offsets follow from one dot
+// product: |p' - p|^2 = A2 + C2 - 2 p'.p and |p' - q|^2 = A2 - 2 p'.K + D2 +
+// 2 p'.p (A2 = |p'|^2, C2 = |p|^2, D2 = |q|^2), so o1 = S A2 + S C2 - 2S p'.p
+// (sdot4 of -(S/2) p' and 4 p, both packed int8, accumulated onto the row and
+// column constants) and o2 = S (2 A2 - 2 p'.K) + S (C2 + D2) - o1.  Padding
+// columns carry p = K and D2 = 0, so both offsets stay inside the table
+// (|q'|^2 and A2); their delta is zero.  Padding rows carry p' = 0.
+constexpr int kKP = 128;  // momentum pairs staged per barrier
+
+// the mixed modes: FP32 operands on the 16x16x4 FP32 MFMA or BF16 operands on
+// the 16x16x32 BF16 MFMA, FP32 accumulation; staging as in k_ladder64
 template <int P>
 __global__ void __launch_bounds__(256, 3) k_ladder(DevPtrs d, int cur, uint32_t mask, int n_items) {
-    using ET = typename AccT<P>::E;   // element type of the generated operand
-    using AT = typename AccT<P>::T;   // accumulator
-    constexpr int S = (int)sizeof(ET);
-    constexpr int kNeg = S * kMaxLut;  // byte offset of the negated table
-    __shared__ ET lutS[2 * kMaxLut];
-    // t chunk: [k][16] for FP64 / FP32, transposed [16][k] for BF16
-    __shared__ __attribute__((aligned(16))) char tks[P == P_F64 ? kKP * 16 * 8 : (P == P_F32 ? kKP * 16 * 4 : 16 * (kKP + 8) * 2)];
-    // per staged column cd: (4 n_c as int8 x, y, z; S C2 + neg; S (C2 + D2) + 2 neg; 0)
-    __shared__ int4 cvi[kKP];
+    static_assert(P != P_F64, "the FP64 ladder is k_ladder64");
+    constexpr int S = 4;
+    __shared__ float lutS[kMaxLut];
+    // delta chunk: [k][16] FP32, transposed [16][k] BF16
+    __shared__ __attribute__((aligned(16))) char tks[P == P_F32 ? kKP * 16 * 4 : 16 * (kKP + 8) * 2];
+    // per staged pair: (4 p as int8, S |p|^2, S (|p|^2 + |q|^2), rows + 1 as two 16-bit fields)
+    __shared__ int4 cvi[2][kKP];
     const char* lutB = (const char*)lutS;
     for (int bi = blockIdx.x; bi < n_items; bi += gridDim.x) {
     const Item lg = d.it_lg[bi];
     if (lg.chan < 0) continue;
-    const int litem = lg.chan, g = lg.start;
-    const Item it = d.it_ladder[litem];
-    const int r0 = it.start & 0xfffff, ct = it.start >> 20;  // row tile and column tile of the item
+    const int g = lg.start;
+    const Item it = d.it_ladder[lg.chan];
+    const int r0 = it.start & 0xfffff, ct = it.start >> 20;  // pair tile and column tile of the item
     const DevChan c = d.chans[it.chan];
     const DevGroup G = d.groups[c.group];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int nhh = c.nhh, npp = c.npp;
+    const int nhh = c.nhh, nlp = c.n_lp;
     const bool act = d.active[G.p0 + g] != 0;
     const bool pp_on = act && (mask & CCD_T_PP) != 0;
     const bool hh_on = act && (mask & (CCD_T_HH | CCD_T_QHH)) != 0;
     const int64_t T0 = G.t_base + g * G.n_amp + c.t_off;
     const double* tcur = d.t[cur] + T0;
-
-    __syncthreads();  // the previous item's reads of lutS are done
-    for (int e = threadIdx.x; e < G.nlut; e += 256) {
-        const ET v = (ET)d.lut[G.lut_base + g * G.nlut + e];
-        lutS[e] = v;
-        lutS[kMaxLut + e] = -v;
-    }
-
-    // generator rows of this lane (A-operand row = lane % 16) in the wave's two
-    // tiles; rows past the channel get a = 0, whose sums are never stored
+    const int4* lp = d.lpinfo + c.lp_off;
     const int rbase = r0 + 32 * w;
     const int32_t kpack = (int32_t)((uint32_t)(uint8_t)(int8_t)c.kx | ((uint32_t)(uint8_t)(int8_t)c.ky << 8) |
                                     ((uint32_t)(uint8_t)(int8_t)c.kz << 16));
@@ -1036,73 +1021,91 @@ __global__ void __launch_bounds__(256, 3) k_ladder(DevPtrs d, int cur, uint32_t 
     // 4 n as packed int8 (|4 n_i| <= 64): shift each byte left by two, dropping
     // the bits carried into the next byte
     auto times4 = [](int32_t x) { return (int32_t)(((uint32_t)x << 2) & 0xfcfcfcfcu); };
-    int32_t apack[2] = {0, 0};  // -(S/2) n_a as packed int8
+    int32_t apack[2] = {0, 0};  // -(S/2) p' as packed int8
     int rowA[2] = {0, 0}, rowS[2] = {0, 0};
 #pragma unroll
     for (int h = 0; h < 2; h++) {
-        const int ra = rbase + 16 * h + (lane & 15);
-        if (ra < npp) {
-            const int2 ri = d.ppinfo[c.pp_off + ra];
-            const int ax = (int8_t)(ri.x & 0xff), ay = (int8_t)((ri.x >> 8) & 0xff), az = (int8_t)((ri.x >> 16) & 0xff);
-            const int q = -(S / 2);
-            apack[h] = (int32_t)((uint32_t)(uint8_t)(int8_t)(q * ax) | ((uint32_t)(uint8_t)(int8_t)(q * ay) << 8) |
-                                 ((uint32_t)(uint8_t)(int8_t)(q * az) << 16));
-            const int A2 = ri.y & 1023;
-            const int aK = ax * c.kx + ay * c.ky + az * c.kz;
-            rowA[h] = S * A2;
-            rowS[h] = S * (2 * A2 - 2 * aK);
-        }
+        const int pr = rbase + 16 * h + (lane & 15);
+        const int4 li = pr < nlp ? lp[pr] : make_int4(0, 0, -1, -1);
+        const int ax = (int8_t)(li.x & 0xff), ay = (int8_t)((li.x >> 8) & 0xff), az = (int8_t)((li.x >> 16) & 0xff);
+        apack[h] = (int32_t)((uint32_t)(uint8_t)(int8_t)(-2 * ax) | ((uint32_t)(uint8_t)(int8_t)(-2 * ay) << 8) |
+                             ((uint32_t)(uint8_t)(int8_t)(-2 * az) << 16));
+        const int A2 = li.y & 1023;
+        const int aK = ax * c.kx + ay * c.ky + az * c.kz;
+        rowA[h] = S * A2;
+        rowS[h] = S * (2 * A2 - 2 * aK);
     }
-    // one staged chunk: t rows kp .. kp + kKP - 1 of column tile ct (zero past
-    // the channel) and the column descriptors; loaded into registers one chunk
-    // ahead of the MFMA work on the previous one
+    const int4 cpad = make_int4(times4(kpack), S * K2, S * K2, 0);
+    auto cdesc = [&](const int4& li) {
+        const int C2 = li.y & 1023, D2 = (li.y >> 10) & 1023;
+        return make_int4(times4(li.x), S * C2, S * (C2 + D2),
+                         (int)((uint32_t)(li.z + 1) | ((uint32_t)(li.w + 1) << 16)));
+    };
     constexpr int kPer = kKP * 16 / 256;
     double tv[kPer];
-    const int4 cpad = make_int4(times4(kpack), S * K2, S * K2, 0);
-    int4 cv = cpad;
-    auto load_chunk = [&](int kp) {
-        const int kn = min(kKP, npp - kp);
+    auto load_delta = [&](int kp, int b) {
+        const int kn = min(kKP, nlp - kp);
 #pragma unroll
         for (int i = 0; i < kPer; i++) {
             const int e = threadIdx.x + 256 * i, kk = e >> 4, cc = ct * 16 + (e & 15);
-            tv[i] = (kk < kn && cc < nhh) ? tcur[(int64_t)(kp + kk) * nhh + cc] : 0.0;
-        }
-        cv = cpad;
-        if (threadIdx.x < kn) {
-            const int2 q = d.ppinfo[c.pp_off + kp + threadIdx.x];
-            const int C2 = q.y & 1023, D2 = (q.y >> 10) & 1023;
-            const int neg = ((q.y >> 20) & 1) ? 0 : kNeg;  // s_c = -1 for spin down
-            cv = make_int4(times4(q.x), S * C2 + neg, S * (C2 + D2) + 2 * neg, 0);
+            double v = 0.0;
+            if (kk < kn && cc < nhh) {
+                const uint32_t rr = (uint32_t)cvi[b][kk].w;
+                const int rp = (int)(rr & 0xffff) - 1, rm = (int)(rr >> 16) - 1;
+                const double tp = rp >= 0 ? tcur[(int64_t)rp * nhh + cc] : 0.0;
+                const double tm = rm >= 0 ? tcur[(int64_t)rm * nhh + cc] : 0.0;
+                v = tp - tm;
+            }
+            tv[i] = v;
         }
     };
-    auto store_chunk = [&]() {
+    auto store_delta = [&]() {
 #pragma unroll
         for (int i = 0; i < kPer; i++) {
             const int e = threadIdx.x + 256 * i, kk = e >> 4, jj = e & 15;
-            if constexpr (P == P_F64) ((double*)tks)[kk * 16 + jj] = tv[i];
-            else if constexpr (P == P_F32) ((float*)tks)[kk * 16 + jj] = (float)tv[i];
+            if constexpr (P == P_F32) ((float*)tks)[kk * 16 + jj] = (float)tv[i];
             else ((__bf16*)tks)[jj * (kKP + 8) + kk] = (__bf16)tv[i];
         }
-        if (threadIdx.x < kKP) cvi[threadIdx.x] = cv;
     };
-    // <ab||cd> (before the row sign) of tile h's row for column descriptor ci
-    auto gen = [&](const int4 ci, int h) -> ET {
+    // M[P'][P] of tile h's row for column descriptor ci
+    auto gen = [&](const int4 ci, int h) -> float {
         const int o1 = __builtin_amdgcn_sdot4(apack[h], ci.x, rowA[h] + ci.y, false);
         const int o2 = rowS[h] + ci.z - o1;
-        return *(const ET*)(lutB + o1) + *(const ET*)(lutB + o2);
+        return *(const float*)(lutB + o1) + *(const float*)(lutB + o2);
     };
     const int col = ct * 16 + (lane & 15);
-    AT acc[2], acc2[2];
+    f4 acc[2], acc2[2];
 #pragma unroll
-    for (int h = 0; h < 2; h++) { acc[h] = AT{0, 0, 0, 0}; acc2[h] = AT{0, 0, 0, 0}; }
+    for (int h = 0; h < 2; h++) { acc[h] = f4{0, 0, 0, 0}; acc2[h] = f4{0, 0, 0, 0}; }
+
+    const double* lutg = d.lut + G.lut_base + g * G.nlut;
+    const float lv0 = threadIdx.x < G.nlut ? (float)lutg[threadIdx.x] : 0.0f;
+    const float lv1 = threadIdx.x + 256 < G.nlut ? (float)lutg[threadIdx.x + 256] : 0.0f;
+    int4 lpc = cpad;
+    if (pp_on && threadIdx.x < kKP && threadIdx.x < nlp) lpc = lp[threadIdx.x];
+    __syncthreads();  // the previous item's reads of LDS are done
+    lutS[threadIdx.x] = lv0;
+    if (threadIdx.x + 256 < kMaxLut) lutS[threadIdx.x + 256] = lv1;
     if (pp_on) {
-        load_chunk(0);
-        for (int kp = 0; kp < npp; kp += kKP) {
-            const int kn = min(kKP, npp - kp);
-            __syncthreads();
-            store_chunk();
-            __syncthreads();
-            if (kp + kKP < npp) load_chunk(kp + kKP);
+        if (threadIdx.x < kKP) cvi[0][threadIdx.x] = threadIdx.x < nlp ? cdesc(lpc) : cpad;
+        lpc = cpad;
+        if (threadIdx.x < kKP && kKP + threadIdx.x < nlp) lpc = lp[kKP + threadIdx.x];
+    }
+    __syncthreads();
+    if (pp_on) {
+        load_delta(0, 0);
+        store_delta();
+        for (int kp = 0; kp < nlp; kp += kKP) {
+            const int b = (kp / kKP) & 1;
+            const bool more = kp + kKP < nlp;
+            if (more && threadIdx.x < kKP) {
+                cvi[b ^ 1][threadIdx.x] = kp + kKP + threadIdx.x < nlp ? cdesc(lpc) : cpad;
+                lpc = cpad;
+                if (kp + 2 * kKP + threadIdx.x < nlp) lpc = lp[kp + 2 * kKP + threadIdx.x];
+            }
+            __syncthreads();  // this chunk's delta and the next chunk's descriptors are in LDS
+            if (more) load_delta(kp + kKP, b ^ 1);
+            const int kn = min(kKP, nlp - kp);
             if constexpr (P == P_BF16) {
                 const int ksteps = (kn + 31) & ~31;
                 for (int kk = 0; kk < ksteps; kk += 32) {
@@ -1110,7 +1113,7 @@ __global__ void __launch_bounds__(256, 3) k_ladder(DevPtrs d, int cur, uint32_t 
                     bf8 av[2];
 #pragma unroll
                     for (int j = 0; j < 8; j++) {
-                        const int4 ci = cvi[k0 + j];
+                        const int4 ci = cvi[b][k0 + j];
                         av[0][j] = (__bf16)gen(ci, 0);
                         av[1][j] = (__bf16)gen(ci, 1);
                     }
@@ -1123,11 +1126,11 @@ __global__ void __launch_bounds__(256, 3) k_ladder(DevPtrs d, int cur, uint32_t 
                 // produced first, each phase's LDS reads issued together
                 const int ksteps = (kn + 15) & ~15;
                 for (int kk = 0; kk < ksteps; kk += 16) {
-                    ET vb[4], x1[2][4], x2[2][4];
+                    float vb[4], x1[2][4], x2[2][4];
                     int o1[2][4], o2[2][4];
 #pragma unroll
                     for (int s2 = 0; s2 < 4; s2++) {
-                        const int4 ci = cvi[kk + 4 * s2 + (lane >> 4)];
+                        const int4 ci = cvi[b][kk + 4 * s2 + (lane >> 4)];
 #pragma unroll
                         for (int h = 0; h < 2; h++) {
                             o1[h][s2] = __builtin_amdgcn_sdot4(apack[h], ci.x, rowA[h] + ci.y, false);
@@ -1139,73 +1142,81 @@ __global__ void __launch_bounds__(256, 3) k_ladder(DevPtrs d, int cur, uint32_t 
                     for (int s2 = 0; s2 < 4; s2++) {
 #pragma unroll
                         for (int h = 0; h < 2; h++) {
-                            x1[h][s2] = *(const ET*)(lutB + o1[h][s2]);
-                            x2[h][s2] = *(const ET*)(lutB + o2[h][s2]);
+                            x1[h][s2] = *(const float*)(lutB + o1[h][s2]);
+                            x2[h][s2] = *(const float*)(lutB + o2[h][s2]);
                         }
-                        vb[s2] = ((const ET*)tks)[(kk + 4 * s2 + (lane >> 4)) * 16 + (lane & 15)];
+                        vb[s2] = ((const float*)tks)[(kk + 4 * s2 + (lane >> 4)) * 16 + (lane & 15)];
                     }
                     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                     for (int s2 = 0; s2 < 4; s2 += 2) {
 #pragma unroll
                         for (int h = 0; h < 2; h++) {
-                            const ET va0 = x1[h][s2] + x2[h][s2], va1 = x1[h][s2 + 1] + x2[h][s2 + 1];
-                            if constexpr (P == P_F64) {
-                                acc[h] = mfma64(va0, vb[s2], acc[h]);
-                                acc2[h] = mfma64(va1, vb[s2 + 1], acc2[h]);
-                            } else {
-                                acc[h] = mfma32(va0, vb[s2], acc[h]);
-                                acc2[h] = mfma32(va1, vb[s2 + 1], acc2[h]);
-                            }
+                            const float va0 = x1[h][s2] + x2[h][s2], va1 = x1[h][s2 + 1] + x2[h][s2 + 1];
+                            acc[h] = mfma32(va0, vb[s2], acc[h]);
+                            acc2[h] = mfma32(va1, vb[s2 + 1], acc2[h]);
                         }
                     }
                 }
             }
+            __syncthreads();  // every wave is done with this chunk
+            if (more) store_delta();
         }
-        // row signs s_a of this lane's output rows
+        // u of the lane's output pairs: + to the (p up, q down) row, - to the other
 #pragma unroll
-        for (int h = 0; h < 2; h++)
-#pragma unroll
-            for (int r = 0; r < 4; r++) {
-                const int row = rbase + 16 * h + orow<P>(lane, r);
-                const bool up = row < npp && ((d.ppinfo[c.pp_off + row].y >> 20) & 1);
-                acc[h][r] = up ? acc[h][r] + acc2[h][r] : -(acc[h][r] + acc2[h][r]);
-            }
+        for (int h = 0; h < 2; h++) {
+            const f4 u = acc[h] + acc2[h];
+            acc[h] = u;
+            acc2[h] = -u;
+        }
     }
     if (hh_on) {
+        // 1/2 sum_kl t_kl^ab chi_klij per spin row: A = t rows, B = chi_klij columns
+        const int2* lpr = (const int2*)lp;
         const double* xg = d.chh + G.chh_base + g * G.n_chh + c.chh_off;
+        int2 arow[2];
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const int pr = rbase + 16 * h + (lane & 15);
+            arow[h] = pr < nlp ? lpr[2 * pr + 1] : make_int2(-1, -1);
+        }
         for (int k0 = 0; k0 < nhh; k0 += 16) {
-            double b[4];
+            double bq[4];
 #pragma unroll
             for (int s2 = 0; s2 < 4; s2++) {
                 const int kq = k0 + 4 * s2 + (lane >> 4);
-                b[s2] = (kq < nhh && col < nhh) ? xg[kq * nhh + col] : 0.0;
+                bq[s2] = (kq < nhh && col < nhh) ? xg[kq * nhh + col] : 0.0;
             }
 #pragma unroll
             for (int h = 0; h < 2; h++) {
-                const int ra = rbase + 16 * h + (lane & 15);
-                double a[4];
+                double ap[4], am[4];
 #pragma unroll
                 for (int s2 = 0; s2 < 4; s2++) {
                     const int kq = k0 + 4 * s2 + (lane >> 4);
-                    a[s2] = (ra < npp && kq < nhh) ? tcur[(int64_t)ra * nhh + kq] : 0.0;
+                    ap[s2] = (arow[h].x >= 0 && kq < nhh) ? tcur[(int64_t)arow[h].x * nhh + kq] : 0.0;
+                    am[s2] = (arow[h].y >= 0 && kq < nhh) ? tcur[(int64_t)arow[h].y * nhh + kq] : 0.0;
                 }
 #pragma unroll
                 for (int s2 = 0; s2 < 4; s2++) {
-                    if constexpr (P == P_F64) acc[h] = mfma64(a[s2], b[s2], acc[h]);
-                    else acc[h] = mfma32((float)a[s2], (float)b[s2], acc[h]);
+                    acc[h] = mfma32((float)ap[s2], (float)bq[s2], acc[h]);
+                    acc2[h] = mfma32((float)am[s2], (float)bq[s2], acc2[h]);
                 }
             }
         }
     }
-    // this lane owns rows orow(lane, r) of each tile, column col
+    // this lane owns pairs orow(lane, r) of each tile, column col
     if (act) {
+        const int2* lpr = (const int2*)lp;
 #pragma unroll
         for (int h = 0; h < 2; h++)
 #pragma unroll
             for (int r = 0; r < 4; r++) {
-                const int row = rbase + 16 * h + orow<P>(lane, r);
-                if (row < npp && col < nhh) d.rmm[T0 + (int64_t)row * nhh + col] = (double)acc[h][r];
+                const int po = rbase + 16 * h + orow<P>(lane, r);
+                if (po < nlp && col < nhh) {
+                    const int2 rr = lpr[2 * po + 1];
+                    if (rr.x >= 0) d.rmm[T0 + (int64_t)rr.x * nhh + col] = (double)acc[h][r];
+                    if (rr.y >= 0) d.rmm[T0 + (int64_t)rr.y * nhh + col] = (double)acc2[h][r];
+                }
             }
     }
     }
@@ -1441,10 +1452,10 @@ __global__ void __launch_bounds__(256, 3) k_ladder64(DevPtrs d, int cur, uint32_
     __shared__ __attribute__((aligned(16))) double tks[kKP * 16];
     __shared__ int4 cvi[2][kKP];
     for (int bi = blockIdx.x; bi < n_items; bi += gridDim.x) {
-        const Item lg = d.it_lg64[bi];
+        const Item lg = d.it_lg[bi];
         if (lg.chan < 0) continue;
         const int g = lg.start;
-        const Item it = d.it_ladder64[lg.chan];
+        const Item it = d.it_ladder[lg.chan];
         const int r0 = it.start & 0xfffff, ct = it.start >> 20;
         const DevChan c = d.chans[it.chan];
         const DevGroup G = d.groups[c.group];
@@ -1575,11 +1586,11 @@ struct ccd_ctx {
     std::vector<DevGroup> dgroups;
     std::vector<DevChan> dchans;
     std::vector<DevPh> dph;
-    std::vector<int32_t> ppinfo, lpinfo;
+    std::vector<int32_t> lpinfo;
     std::vector<int32_t> st, hh, pp, phmem, phmap, zs, csr_ptr, csr_idx, pgrp, pgi, it_sz0;
     std::vector<double> eps, lut, rowE, colE, pscale;
     std::vector<Item> it_elem, it_ladder, it_dchi, it_direct, it_ring_s, it_ring_b, it_lg, it_ue, it_dsub,
-        it_dsum, it_ladder64, it_lg64;
+        it_dsum;
     int64_t n_dpart = 0, n_dcolp = 0;
     int ring_lo[4] = {0}, ring_n[4] = {0};  // big pair items by padded size n16 = 32, 48, 64, 80
     std::vector<int64_t> prob_t0;  // amplitude index of each problem (caller order)
@@ -1623,8 +1634,7 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
     X(csr_idx, int32_t) X(pgrp, int32_t) X(pgi, int32_t) X(pscale, double) \
     X(it_elem, Item) X(it_ladder, Item) X(it_sz0, int32_t) X(it_dchi, Item) \
     X(it_direct, Item) X(it_ring_s, Item) X(it_ring_b, Item) X(it_lg, Item) X(it_ue, Item) \
-    X(it_dsub, Item) X(it_dsum, Item) X(ppinfo, int32_t) X(lpinfo, int32_t) X(it_ladder64, Item) \
-    X(it_lg64, Item)
+    X(it_dsub, Item) X(it_dsum, Item) X(lpinfo, int32_t)
 
 static DevPtrs make_ptrs(ccd_ctx* c) {
     DevPtrs d;
@@ -1636,8 +1646,8 @@ static DevPtrs make_ptrs(ccd_ctx* c) {
     const void* p_it_elem; const void* p_it_ladder; const void* p_it_sz0;
     const void* p_it_dchi; const void* p_it_direct; const void* p_it_ring_s; const void* p_it_ring_b;
     const void* p_it_lg; const void* p_it_ue; const void* p_zs; const void* p_rowE; const void* p_colE;
-    const void* p_pscale; const void* p_it_dsub; const void* p_it_dsum; const void* p_ppinfo;
-    const void* p_lpinfo; const void* p_it_ladder64; const void* p_it_lg64;
+    const void* p_pscale; const void* p_it_dsub; const void* p_it_dsum;
+    const void* p_lpinfo;
 #define TAKE(name, T)             \
     p_##name = base + o;          \
     o += align256(c->name.size() * sizeof(T));
@@ -1657,9 +1667,7 @@ static DevPtrs make_ptrs(ccd_ctx* c) {
     d.rowE = (const double*)p_rowE; d.colE = (const double*)p_colE;
     d.pscale = (const double*)p_pscale;
     d.it_dsub = (const Item*)p_it_dsub; d.it_dsum = (const Item*)p_it_dsum;
-    d.ppinfo = (const int2*)p_ppinfo;
     d.lpinfo = (const int4*)p_lpinfo;
-    d.it_ladder64 = (const Item*)p_it_ladder64; d.it_lg64 = (const Item*)p_it_lg64;
     d.dpart = (double*)(base + c->r_dpart.off);
     d.dcolp = (double*)(base + c->r_dcolp.off);
     d.t[0] = (double*)(base + c->r_t0.off);
@@ -1795,8 +1803,8 @@ static ccd_status assemble(ccd_ctx* c) {
     c->pgi.assign(P, 0);
     c->prob_t0.assign(P, 0);
     c->slot_of.assign(P, 0);
-    std::vector<std::pair<int, Item>> lg, lg64, ue, dir, dsum, rs, rb[4];
-    std::vector<double> lg_cost, lg64_cost;
+    std::vector<std::pair<int, Item>> lg, ue, dir, dsum, rs, rb[4];
+    std::vector<double> lg_cost, dir_cost;
     int64_t t_base = 0;
     int gi = 0, slot0 = 0;
     for (auto& kv : by_structure) {
@@ -1826,14 +1834,7 @@ static ccd_status assemble(ccd_ctx* c) {
         // direct channels
         const int hh0 = (int)c->hh.size(), pp0 = (int)c->pp.size();
         for (size_t k = 0; k < H.hh.size() / 2; k++) c->hh.push_back(pack_pair(H.hh[2 * k], H.hh[2 * k + 1]));
-        for (size_t k = 0; k < H.pp.size() / 2; k++) {
-            const int a = H.pp[2 * k], b = H.pp[2 * k + 1];
-            c->pp.push_back(pack_pair(a, b));
-            const int A2 = H.nx[a] * H.nx[a] + H.ny[a] * H.ny[a] + H.nz[a] * H.nz[a];
-            const int B2 = H.nx[b] * H.nx[b] + H.ny[b] * H.ny[b] + H.nz[b] * H.nz[b];
-            c->ppinfo.push_back(pack_state(H.nx[a], H.ny[a], H.nz[a], 0));
-            c->ppinfo.push_back(A2 | (B2 << 10) | ((H.sz[a] > 0 ? 1 : 0) << 20));
-        }
+        for (size_t k = 0; k < H.pp.size() / 2; k++) c->pp.push_back(pack_pair(H.pp[2 * k], H.pp[2 * k + 1]));
         int rows = 0, cols = 0, chh = 0, dpart = 0, dcolp = 0;
         std::vector<std::vector<int32_t>> lists(H.ns);
         D.ladder_lo = (int)c->it_ladder.size();
@@ -1871,21 +1872,18 @@ static ccd_status assemble(ccd_ctx* c) {
                 for (int k0 = 0; k0 < h.npp; k0 += kDirSplit) {
                     const int si = (int)c->it_dsub.size();
                     c->it_dsub.push_back({id, k0});
-                    for (int g = 0; g < D.G; g++) dir.push_back({slot0 + g, Item{si, g}});
+                    // staged rows times output tiles: the long items go first,
+                    // so that they do not run alone at the end of the launch
+                    const int nt = (h.nhh + 15) / 16;
+                    for (int g = 0; g < D.G; g++) {
+                        dir.push_back({slot0 + g, Item{si, g}});
+                        dir_cost.push_back((double)std::min(kDirSplit, h.npp - k0) * nt * nt + 64.0);
+                    }
                     dpart += h.nhh * h.nhh;
                     dcolp += h.nhh;
                 }
                 dc.dsub_n = (int)c->it_dsub.size() - dc.dsub_lo;
                 for (int g = 0; g < D.G; g++) dsum.push_back({slot0 + g, Item{id, g}});
-                for (int r0 = 0; r0 < h.npp; r0 += kLadderRows)
-                    for (int ct = 0; ct < (h.nhh + 15) / 16; ct++) {
-                        const int li = (int)c->it_ladder.size();
-                        c->it_ladder.push_back({id, r0 | (ct << 20)});
-                        for (int g = 0; g < D.G; g++) {
-                            lg.push_back({slot0 + g, Item{li, g}});
-                            lg_cost.push_back((double)h.npp);  // MFMA steps of the item
-                        }
-                    }
                 // momentum pairs {n_a, n_b} of the rows, in order of first row;
                 // a row's pair is keyed by n_a (b follows from K and the spins)
                 if (h.npp >= 0xffff) {  // rows travel as 16-bit fields in the kernel
@@ -1916,13 +1914,14 @@ static ccd_status assemble(ccd_ctx* c) {
                 }
                 for (auto& e : lps) c->lpinfo.insert(c->lpinfo.end(), e.begin(), e.end());
                 dc.n_lp = h.nlp;
+                // ladder items: kLadderRows pairs by 16 columns
                 for (int r0 = 0; r0 < h.nlp; r0 += kLadderRows)
                     for (int ct = 0; ct < (h.nhh + 15) / 16; ct++) {
-                        const int li = (int)c->it_ladder64.size();
-                        c->it_ladder64.push_back({id, r0 | (ct << 20)});
+                        const int li = (int)c->it_ladder.size();
+                        c->it_ladder.push_back({id, r0 | (ct << 20)});
                         for (int g = 0; g < D.G; g++) {
-                            lg64.push_back({slot0 + g, Item{li, g}});
-                            lg64_cost.push_back((double)h.nlp);
+                            lg.push_back({slot0 + g, Item{li, g}});
+                            lg_cost.push_back((double)h.nlp);  // MFMA steps of the item
                         }
                     }
             }
@@ -2006,9 +2005,8 @@ static ccd_status assemble(ccd_ctx* c) {
 
     if (c->csr_idx.empty()) c->csr_idx.push_back(0);
     c->it_lg = xcd_order_cost(lg, lg_cost);
-    c->it_lg64 = xcd_order_cost(lg64, lg64_cost);
     c->it_ue = xcd_order(ue);
-    c->it_direct = xcd_order(dir);
+    c->it_direct = xcd_order_cost(dir, dir_cost);
     c->it_dsum = xcd_order(dsum);
     c->it_ring_s = xcd_order(rs, 4);
     c->it_ring_b.clear();
@@ -2152,12 +2150,11 @@ static ccd_status L_ring(ccd_ctx* c, const DevPtrs& d, int cur, uint32_t mask, i
 
 template <int P>
 static ccd_status L_ladder(ccd_ctx* c, const DevPtrs& d, int cur, uint32_t mask) {
+    const int n = (int)c->it_lg.size();
     if (mask & (CCD_T_PP | CCD_T_HH | CCD_T_QHH)) {
         if constexpr (P == P_F64) {
-            const int n = (int)c->it_lg64.size();
             LAUNCH(F_LADDER, k_ladder64, grid_for(c, CCD_TUNE_LADDER, n), 256, 0, d, cur, mask, n);
         } else {
-            const int n = (int)c->it_lg.size();
             LAUNCH(F_LADDER, k_ladder<P>, grid_for(c, CCD_TUNE_LADDER, n), 256, 0, d, cur, mask, n);
         }
     }
