@@ -73,6 +73,35 @@ def measured_traffic(family):
     return (rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"]) * 1024.0
 
 
+def ring_class_flops(ccd, ctx, p=0):
+    """FP64 flops of one sweep's ring per kernel (ring_small and the pair
+    blocks of padded order 32 .. 80), from problem p's cross channels."""
+    ph = ctx.export_map(ccd.CCD_MAP_PH_CHANNELS, p).reshape(-1, 6)
+    out = {}
+    for x in range(len(ph)):
+        y = int(ph[x, 5])
+        if y < x:
+            continue
+        n, m = float(ph[x, 4]), float(ph[y, 4])
+        nb = int(max(n, m))
+        k = "ring_small" if nb <= 16 else "ring%d" % (16 * ((nb + 15) // 16))
+        out[k] = out.get(k, 0.0) + (4 * n * m * m + (4 * m * n * n if y != x else 0.0))
+    return out
+
+
+def kernel_symbol(family, tuning):
+    """The kernel a family's single launch runs in the FP64 sweep, as rocprofv3
+    names it (the ring variant follows the tuned waves per block)."""
+    if family == "ladder":
+        return "k_ladder64"
+    if family == "direct":
+        return "void k_direct<0>"
+    n16 = int(family[4:])
+    k = (n16 - 32) // 16
+    nwa, nwb = {32: (4, 2), 48: (9, 3), 64: (16, 8), 80: (16, 9)}[n16]
+    return "void k_ringp<0, %d, %d>" % (n16, nwb if tuning[6 + k] else nwa)
+
+
 def cpu_baseline(budget_s=20.0):
     """The oracle (intermediates form, fourth index deduced) timed on the host
     cores: one density of the same workload, sweeps until the budget is spent."""
@@ -408,26 +437,27 @@ def main():
     total_ms = sum(v["ms_per_step"] for v in kernels.values())
     for v in kernels.values():
         v["share"] = v["ms_per_step"] / total_ms
-    # useful FP64 flops of one step, per family (unordered pairs, as executed)
+    # useful FP64 flops of one step, per family (unordered pairs, as executed;
+    # the pp ladder over momentum pairs); the ring per size class of its pair
+    # blocks {Q, -Q}: 4 n m (n + m) for cross channels of n and m pairs
+    ring_cls = ring_class_flops(ccd, ctx)
     fam_flops = {"ladder": nsolve * (info["flops_pp"] + info["flops_hh"] / 2),
-                 "direct": nsolve * info["flops_hh"] / 2,
-                 "ring": nsolve * info["flops_ring"]}
-    ring_ms = sum(kernels.get(k, {}).get("ms_per_step", 0.0) for k in ("ring", "ring_small"))
-    fam_ms = {"ladder": kernels.get("ladder", {}).get("ms_per_step", 0.0),
-              "direct": kernels.get("direct", {}).get("ms_per_step", 0.0), "ring": ring_ms}
+                 "direct": nsolve * info["flops_hh"] / 2}
+    for k, f in ring_cls.items():
+        fam_flops[k] = nsolve * f
+    fam_ms = {k: kernels.get(k, {}).get("ms_per_step", 0.0) for k in fam_flops}
     for k in fam_ms:
         if fam_ms[k] > 0:
-            kernels.setdefault(k, {})["tflops"] = fam_flops[k] / (fam_ms[k] * 1e-3) / 1e12
-    # dominant kernel: the longest average launch (the ring family is four
-    # launches of separate kernels, the ladder one launch)
-    per_launch = {k: fam_ms[k] / max(1.0, kernels.get(k, {}).get("launches_per_step", 1.0))
-                  for k in ("ladder", "direct") if fam_ms[k] > 0}
+            kernels[k]["tflops"] = fam_flops[k] / (fam_ms[k] * 1e-3) / 1e12
+    # dominant kernel: the longest single launch among the contraction kernels
+    per_launch = {k: fam_ms[k] / max(1.0, kernels[k]["launches_per_step"])
+                  for k in fam_ms if fam_ms[k] > 0 and k != "ring_small"}
     dom = max(per_launch, key=lambda k: per_launch[k])
     achieved = fam_flops[dom] / (per_launch[dom] * 1e-3) / 1e12
-    roof = {"kernel": "k_ladder64" if dom == "ladder" else "k_direct", "bound": "mfma",
+    roof = {"kernel": kernel_symbol(dom, tuning), "bound": "mfma",
             "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP64_TFLOPS, "traffic": measured_traffic(dom),
-            "ms_per_launch": per_launch[dom], "flops_per_launch": fam_flops[dom]}
+            "family": dom, "ms_per_launch": per_launch[dom], "flops_per_launch": fam_flops[dom]}
     # the same rate against what this part's FP64 matrix cores reach in a
     # resident loop of the instruction the kernel uses (context, not the peak)
     meas = ceilings["fp64_mfma_4x4x4_tflops"] if dom == "ladder" else ceilings["fp64_mfma_16x16x4_tflops"]

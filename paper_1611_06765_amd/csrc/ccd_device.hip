@@ -1556,11 +1556,16 @@ __global__ void __launch_bounds__(256) k_energy(DevPtrs d, double tol, double to
 // --------------------------------------------------------------------------
 // context
 // --------------------------------------------------------------------------
-enum Family { F_INIT = 0, F_DIRECT, F_DCHI, F_RING_S, F_RING_B, F_LADDER, F_UPDATE, F_ENERGY, F_NUM };
-// one name per family, in the order above (the ladder family is the pp + hh
-// ladder sums; update covers every amplitude)
-static const char* kFamilyNames[F_NUM] = {"init", "direct", "dchi", "ring_small", "ring", "ladder",
-                                          "update", "energy"};
+enum Family {
+    F_INIT = 0, F_DIRECT, F_DSUM, F_DCHI, F_RING_S, F_RING32, F_RING48, F_RING64, F_RING80, F_LADDER, F_UPDATE,
+    F_ENERGY, F_NUM
+};
+// one name per family, in the order above (direct is the chi_klij product
+// items, dsum their sums; ring32 .. ring80 are the pair blocks of padded order
+// 32 .. 80; the ladder family is the pp + hh ladder sums; update covers every
+// amplitude)
+static const char* kFamilyNames[F_NUM] = {"init", "direct", "dsum", "dchi", "ring_small", "ring32", "ring48",
+                                          "ring64", "ring80", "ladder", "update", "energy"};
 
 struct Region {
     size_t off = 0, bytes = 0;
@@ -2101,7 +2106,7 @@ static ccd_status L_direct(ccd_ctx* c, const DevPtrs& d, int cur, uint32_t mask)
     if (mask & (CCD_T_QHH | CCD_T_QHOLE | CCD_T_QPART))
         LAUNCH(F_DIRECT, k_direct<P>, grid_for(c, CCD_TUNE_DIRECT, n), 256, 0, d, cur, mask, n);
     if (mask & (CCD_T_HH | CCD_T_QHH | CCD_T_QHOLE))
-        LAUNCH(F_DIRECT, k_dsum, ns, 256, 0, d, mask, ns);
+        LAUNCH(F_DSUM, k_dsum, ns, 256, 0, d, mask, ns);
     return CCD_OK;
 }
 
@@ -2131,9 +2136,9 @@ static ccd_status L_ring_class(ccd_ctx* c, const DevPtrs& d, int cur, uint32_t m
     const int n = c->ring_n[k], lo = c->ring_lo[k];
     const int grid = grid_for(c, CCD_TUNE_RING, n);
     if (c->tune[CCD_TUNE_RING_NW32 + k] == 0)
-        LAUNCH(F_RING_B, (k_ringp<P, N16, NWA>), grid, 64 * NWA, pair_lds<P>(N16), d, cur, mask, lo, n);
+        LAUNCH(F_RING32 + k, (k_ringp<P, N16, NWA>), grid, 64 * NWA, pair_lds<P>(N16), d, cur, mask, lo, n);
     else
-        LAUNCH(F_RING_B, (k_ringp<P, N16, NWB>), grid, 64 * NWB, pair_lds<P>(N16), d, cur, mask, lo, n);
+        LAUNCH(F_RING32 + k, (k_ringp<P, N16, NWB>), grid, 64 * NWB, pair_lds<P>(N16), d, cur, mask, lo, n);
     return CCD_OK;
 }
 
