@@ -131,10 +131,10 @@ typedef struct {
     int64_t n_amplitudes;    /* elements of the canonical amplitude vector */
     int32_t lut_size;        /* entries of the interaction table W(m), m = |dn|^2 */
     double box_L;            /* fm */
-    double flops_pp;         /* FP64 flops of one sweep's pp ladder as executed:
+    double flops_pp;         /* flops of one sweep's pp ladder as executed:
                                 the product over the momentum pairs {n_a, n_b}
-                                of each S_z = 0 block (the FP32 / BF16 paths run
-                                the product over spin pairs, about 4x this) */
+                                of each S_z = 0 block (a quarter of the product
+                                over spin pairs) */
     double flops_hh;         /* hh ladder + chi_klij contraction */
     double flops_ring;       /* both ring contractions */
     double flops_ordered;    /* the same three with ordered pairs, the paper's

@@ -11,9 +11,11 @@
 //   k_ringp   per pair {Q, -Q} of cross channels: gather T~_Q, generate the
 //             interaction blocks, the two ring terms of every amplitude in three
 //             MFMA products in LDS, stored to the amplitude's ring slots
-//   k_ladder  per S_z = 0 block, 128-row and 16-column tile: pp ladder
-//             1/2 sum_cd <ab||cd> t_ij^cd on MFMA with <ab||cd> generated in
-//             registers from W(m), plus the hh ladder 1/2 sum_kl t_kl^ab chi_klij
+//   k_ladder  per S_z = 0 block, 128-pair and 16-column tile: pp ladder
+//             1/2 sum_cd <ab||cd> t_ij^cd as a product over the block's momentum
+//             pairs {p, K - p} on MFMA, the interaction generated in registers
+//             from W(m), plus the hh ladder 1/2 sum_kl t_kl^ab chi_klij
+//             (k_ladder64 in FP64)
 //   k_update  every amplitude: <ab||ij> + ladder sums + ring slots + one-body
 //             terms, t_new = R / eps_ij^ab, linear mixing, energy partial sums
 //   k_energy  deterministic per-problem energy and convergence flag

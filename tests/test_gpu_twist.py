@@ -50,7 +50,7 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("mask", [4, 16, 127])
+@pytest.mark.parametrize("mask", [1, 3, 4, 16, 127])
 @pytest.mark.parametrize("case", CASES)
 def test_twisted_terms_vs_oracle(orc, case, mask):
     N, n2, rho, tw = case
