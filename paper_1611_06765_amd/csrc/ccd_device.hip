@@ -2183,12 +2183,15 @@ struct StreamSwap {
 };
 
 // The ring reads only t[cur] and static tables and writes only the ring
-// slots; the ladder sums read t[cur] and chi_klij and write only rmm.  So the
-// ring size buckets run on two auxiliary streams from the start of the sweep,
-// the ladder on a third once chi_klij is complete, and the one-body sums on
-// the context's stream; the update waits for all of them.  With kernel timing
-// on, everything stays on the context's stream so that the per-family event
-// times are not overlapped.
+// slots; the ladder sums read t[cur] and chi_klij and write only rmm; the
+// one-body sums read the row and column sums and write only their own arrays.
+// So the ring size buckets run on two auxiliary streams from the start of the
+// sweep, and once chi_klij is complete the one-body sums fork to a third while
+// the ladder, the longest chain, stays on the context's stream (a cross-stream
+// wait costs ~10 us on this ROCm, and the chain direct -> dsum -> ladder ->
+// update is the critical one); the update waits for all of them.  With kernel
+// timing on, everything stays on the context's stream so that the per-family
+// event times are not overlapped.
 template <int P>
 static ccd_status launch_contractions(ccd_ctx* c, const DevPtrs& d, int cur, uint32_t mask) {
     const bool fork = c->aux_ok && !c->timing;
@@ -2212,13 +2215,19 @@ static ccd_status launch_contractions(ccd_ctx* c, const DevPtrs& d, int cur, uin
             HIP_TRY(hipEventRecord(c->ev_mid, c->stream));
             HIP_TRY(hipStreamWaitEvent(c->aux[2], c->ev_mid, 0));
             StreamSwap sw(c, c->aux[2]);
-            s = L_ladder<P>(c, d, cur, mask);
+            s = L_dchi(c, d, mask);
         }
-        if (s == CCD_OK) s = L_dchi(c, d, mask);
-        for (int k = 0; k < 3; k++) {
+        if (s == CCD_OK) s = L_ladder<P>(c, d, cur, mask);
+        // one join on the context's stream: the third stream, whose one-body
+        // sums end well before the ladder, takes the waits for the two ring
+        // streams (every wait is a barrier packet that costs a few us even when
+        // its event has completed)
+        for (int k = 0; k < 2; k++) {
             HIP_TRY(hipEventRecord(c->ev_join[k], c->aux[k]));
-            HIP_TRY(hipStreamWaitEvent(c->stream, c->ev_join[k], 0));
+            HIP_TRY(hipStreamWaitEvent(c->aux[2], c->ev_join[k], 0));
         }
+        HIP_TRY(hipEventRecord(c->ev_join[2], c->aux[2]));
+        HIP_TRY(hipStreamWaitEvent(c->stream, c->ev_join[2], 0));
     } else {
         s = L_direct<P>(c, d, cur, mask);
         if (s == CCD_OK) s = L_dchi(c, d, mask);
