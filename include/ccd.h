@@ -312,9 +312,14 @@ ccd_status ccd_export_tables(const ccd_ctx* ctx, int32_t problem, double* tkin, 
                              double* w_table);
 
 /* Per-kernel GPU timing with HIP events recorded on the context's stream.
- * While enabled every launch is bracketed by two events; ccd_kernel_times
- * returns, per kernel family, the summed milliseconds and launch counts since
- * the last reset (families: see ccd_kernel_name).  Synchronises the stream. */
+ * While enabled every launch is bracketed by two events and the sweep runs on
+ * the context's stream alone (no forked streams), so the times do not overlap;
+ * ccd_kernel_times returns, per kernel family, the summed milliseconds and
+ * launch counts since the last reset.  Families (ccd_kernel_name, in order):
+ * init, direct (the chi_klij product items), dsum (their column sums), dchi
+ * (one-body sums), ring_small, ring32, ring48, ring64, ring80 (the ring pair
+ * blocks by padded order), ladder, update, energy.  ms and launches hold
+ * ccd_kernel_families() entries.  Synchronises the stream. */
 ccd_status ccd_set_timing(ccd_ctx* ctx, int32_t enabled);
 int32_t ccd_kernel_families(void);
 const char* ccd_kernel_name(int32_t family);

@@ -14,7 +14,7 @@ namespace ccd {
 // Limits of the kernels (checked when the plan is built).
 constexpr int kMaxHH = 64;        // hole pairs of one direct channel (ladder tile width)
 constexpr int kMaxPH = 80;        // pairs of one particle-hole channel (2 N^2 doubles in LDS)
-constexpr int kLadderRows = 128;  // particle-pair rows per ladder work item
+constexpr int kLadderRows = 128;  // momentum pairs (rows of the pair product) per ladder work item
 constexpr int kElemChunk = 1024;  // amplitudes per elementwise work item
 constexpr int kDirSplit = 256;    // particle-pair rows per work item of the chi_klij product
 constexpr int kMaxNmax2 = 64;     // cutoff limit: W(m) tables of 4 nmax2 + 1 entries live in LDS

@@ -249,3 +249,11 @@ def test_pairing_hamiltonian_two_constructions_agree(orc):
         assert np.array_equal(h1, h2) and np.array_equal(v1, v2)
         eref = h1[:4].sum() + 0.5 * sum(v1[i, j, i, j] for i in range(4) for j in range(4))
         assert eref == pytest.approx(2.0 - g, abs=1e-14)
+
+
+def test_kernel_family_names():
+    """The timing families in the order the header documents them."""
+    names = [ccd._lib.ccd_kernel_name(i).decode() for i in range(ccd._lib.ccd_kernel_families())]
+    assert names == ["init", "direct", "dsum", "dchi", "ring_small", "ring32", "ring48", "ring64", "ring80",
+                     "ladder", "update", "energy"]
+    assert ccd._lib.ccd_kernel_name(-1) == b"" and ccd._lib.ccd_kernel_name(len(names)) == b""
