@@ -190,11 +190,14 @@ ccd_status ccd_iterate(ccd_ctx* ctx, const ccd_solver_opts* opts, int32_t* sweep
  *    blocks (padded order 32, 48, 64, 80): 0 or 1 picks one of two waves-per-
  *    workgroup shapes (32: 4|2, 48: 9|3, 64: 16|8, 80: 16|9).
  * Shapes change speed only: every choice gives bit-identical results.
- * ccd_autotune times the candidates of each slot on the context's own
- * problems (reps launches each, after a warm launch) and keeps the fastest;
- * best_ms (nullable, CCD_TUNE_LEN entries) receives each slot's best time per
- * launch.  It recomputes the sweep's intermediates from the current amplitudes
- * but does not advance the iteration.  A fresh context has all slots 0. */
+ * ccd_autotune times the candidates of each slot, one slot after another, on
+ * the context's own problems: reps passes of the sweep's contractions and
+ * update (forked streams included, since a shape that is faster alone can be
+ * slower beside the kernels it shares the GPU with), after a warm pass, and
+ * keeps a candidate only if it beats the current one by 2%; best_ms
+ * (nullable, CCD_TUNE_LEN entries) receives each slot's best time per pass.
+ * It recomputes the sweep's intermediates from the current amplitudes but does
+ * not advance the iteration.  A fresh context has all slots 0. */
 #define CCD_TUNE_DIRECT      0
 #define CCD_TUNE_DCHI        1
 #define CCD_TUNE_RING_SMALL  2

@@ -30,7 +30,6 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
-#include <functional>
 #include <map>
 #include <string>
 #include <thread>
@@ -729,18 +728,24 @@ __device__ __forceinline__ double pair_vph(const int32_t* s2, const double* lutS
     return vas_q(lutS, wq, s2[2 * x + 1], s2[2 * y], s2[2 * x], s2[2 * y + 1]);
 }
 
-template <int P, typename AT>
-__device__ __forceinline__ void pair_store(const PairCtx& r, AT acc, int tu, int ty, int lane) {
+// the ring slots of this lane's four output positions of tile (tu, ty), -1 for
+// none (a self pair holds both orders of one amplitude; only the p < p' one
+// has a slot); loaded before the products so that the stores do not wait
+template <int P>
+__device__ __forceinline__ void pair_slots(const PairCtx& r, int tu, int ty, int lane, int32_t* z) {
 #pragma unroll
     for (int q = 0; q < 4; q++) {
-        int u = tu * 16 + orow<P>(lane, q), y = ty * 16 + (lane & 15);
-        if (u < r.nq && y < r.np) {
-            // the position's ring slot (a self pair holds both orders of one
-            // amplitude; only the p < p' one has a slot)
-            const int32_t z = r.zs[u * r.np + y];
-            const double v = (double)acc[q];
-            if (z >= 0) r.zc[z >> 1] = (z & 1) ? -v : v;
-        }
+        const int u = tu * 16 + orow<P>(lane, q), y = ty * 16 + (lane & 15);
+        z[q] = (u < r.nq && y < r.np) ? r.zs[u * r.np + y] : -1;
+    }
+}
+
+template <typename AT>
+__device__ __forceinline__ void pair_store(const PairCtx& r, AT acc, const int32_t* z) {
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        const double v = (double)acc[q];
+        if (z[q] >= 0) r.zc[z[q] >> 1] = (z[q] & 1) ? -v : v;
     }
 }
 
@@ -831,6 +836,12 @@ __device__ __forceinline__ void pair_body(const DevPtrs& d, const Item it, int c
     // of Q: hole qs[1], particle qs[0])
     const double wq = live ? lutS[dist2(qs[1], qs[0])] : 0.0;
     if (live) pair_fill<E, n16, lda, 64 * NW, P == P_BF16>(r, qs, ps, lutS, wq, A, B, At, Bt, tid, qring);
+    int32_t zsl[TPW][4];
+#pragma unroll
+    for (int k = 0; k < TPW; k++) {
+        const int tile = w + NW * k;
+        if (live && tile < ntt) pair_slots<P>(r, tile / nt, tile - (tile / nt) * nt, lane, zsl[k]);
+    }
     __syncthreads();
     // K extents: the contracted size rounded up to the MFMA K step (n_P for
     // A B and A V_P, n_Q for X A)
@@ -903,7 +914,7 @@ __device__ __forceinline__ void pair_body(const DevPtrs& d, const Item it, int c
             const int tu = tile / nt, ty = tile - tu * nt;
             if constexpr (P == P_BF16) acc[k] = mmbf(A, XB, lda, tu, ty, kp, lane, acc[k]);
             else acc[k] = mm4<P>(A, XB, lda, tu, ty, kp, lane, acc[k]);
-            pair_store<P>(r, acc[k], tu, ty, lane);
+            pair_store(r, acc[k], zsl[k]);
         }
     }
 }
@@ -2364,19 +2375,20 @@ static ccd_status autotune_impl(ccd_ctx* c, int reps, double* best_ms, hipEvent_
     struct Spec {
         int slot, ncand;
         int cand[4];
-        std::function<ccd_status()> fn;
     };
     const Spec specs[] = {
-        {CCD_TUNE_DIRECT, 4, {0, 1, 2, 4}, [&] { return L_direct<P>(c, d, cur, mask); }},
-        {CCD_TUNE_DCHI, 4, {0, 1, 2, 4}, [&] { return L_dchi(c, d, mask); }},
-        {CCD_TUNE_RING_SMALL, 4, {0, 1, 2, 4}, [&] { return L_ring_small<P>(c, d, cur, mask); }},
-        {CCD_TUNE_RING_NW32, 2, {0, 1}, [&] { return L_ring<P>(c, d, cur, mask, 0); }},
-        {CCD_TUNE_RING_NW48, 2, {0, 1}, [&] { return L_ring<P>(c, d, cur, mask, 1); }},
-        {CCD_TUNE_RING_NW64, 2, {0, 1}, [&] { return L_ring<P>(c, d, cur, mask, 2); }},
-        {CCD_TUNE_RING_NW80, 2, {0, 1}, [&] { return L_ring<P>(c, d, cur, mask, 3); }},
-        {CCD_TUNE_RING, 4, {0, 1, 2, 4}, [&] { return L_ring<P>(c, d, cur, mask); }},
-        {CCD_TUNE_LADDER, 4, {0, 1, 2, 4}, [&] { return L_ladder<P>(c, d, cur, mask); }},
-        {CCD_TUNE_UPDATE, 4, {0, 1, 2, 4}, [&] { return L_update(c, d, cur, alpha, mask); }},
+        {CCD_TUNE_DIRECT, 4, {0, 1, 2, 4}},  {CCD_TUNE_DCHI, 4, {0, 1, 2, 4}},
+        {CCD_TUNE_RING_SMALL, 4, {0, 1, 2, 4}}, {CCD_TUNE_RING_NW32, 2, {0, 1}},
+        {CCD_TUNE_RING_NW48, 2, {0, 1}},     {CCD_TUNE_RING_NW64, 2, {0, 1}},
+        {CCD_TUNE_RING_NW80, 2, {0, 1}},     {CCD_TUNE_RING, 4, {0, 1, 2, 4}},
+        {CCD_TUNE_LADDER, 4, {0, 1, 2, 4}},  {CCD_TUNE_UPDATE, 4, {0, 1, 2, 4}},
+    };
+    // every candidate is timed on the sweep's contractions and update as they
+    // run (forked streams included): a shape that is faster alone can be slower
+    // beside the kernels it shares the compute units with
+    auto sweep_body = [&] {
+        ccd_status r = launch_contractions<P>(c, d, cur, mask);
+        return r == CCD_OK ? L_update(c, d, cur, alpha, mask) : r;
     };
     for (const Spec& sp : specs) {
         double best = 0.0;
@@ -2384,7 +2396,7 @@ static ccd_status autotune_impl(ccd_ctx* c, int reps, double* best_ms, hipEvent_
         for (int k = 0; k < sp.ncand; k++) {
             c->tune[sp.slot] = sp.cand[k];
             double ms = 0.0;
-            s = time_family(c, sp.fn, reps, e0, e1, ms);
+            s = time_family(c, sweep_body, reps, e0, e1, ms);
             if (s != CCD_OK) return s;
             if (k == 0 || ms < 0.98 * best) { best = ms; bestv = sp.cand[k]; }
         }
