@@ -108,7 +108,7 @@ struct DevPtrs {
     const DevPh* ph;
     const int32_t* hh;       // packed pairs (per structure)
     const int32_t* pp;
-    const int32_t* phmem;
+    const int32_t* phst;     // per member (p, h) of a cross channel: the packed states of p and h
     const int32_t* phmap;
     const int32_t* csr_ptr;
     const int32_t* csr_idx;
@@ -649,7 +649,7 @@ struct PairCtx {
 };
 
 __device__ __forceinline__ bool pair_ctx(const DevPtrs& d, const Item it, int cur, PairCtx& r,
-                                         int32_t& memQ, int32_t& memP, int32_t& lut_off) {
+                                         int32_t& memQ, int32_t& memP, int32_t& lut_off, int32_t& nlut) {
     const DevPh q = d.ph[it.chan];
     const DevGroup G = d.groups[q.group];
     const int g = it.start;
@@ -661,26 +661,26 @@ __device__ __forceinline__ bool pair_ctx(const DevPtrs& d, const Item it, int cu
     r.np = q.m;
     r.self = q.partner == it.chan;
     memQ = q.mem_off;
-    memP = d.ph[q.partner].mem_off;
+    memP = q.pmem_off;
     lut_off = G.lut_base + g * G.nlut;
+    nlut = G.nlut;
     return d.active[G.p0 + g] != 0;
 }
 
-// stage (p, h) states of both member lists and the problem's W/2 table
-__device__ __forceinline__ void pair_stage(const DevPtrs& d, const Item it, int memQ, int memP, int lut_off,
+// stage the (p, h) states of both member lists and the problem's W/2 table
+__device__ __forceinline__ void pair_stage(const DevPtrs& d, int memQ, int memP, int lut_off, int nlut,
                                            int nq, int np, int32_t* qs, int32_t* ps, double* lutS, int t0,
                                            int stride) {
-    const DevGroup G = d.groups[d.ph[it.chan].group];
-    const int32_t* st = d.st + G.st_off;
+    const int2* ms = (const int2*)d.phst;
     for (int e = t0; e < nq; e += stride) {
-        const int32_t m = d.phmem[memQ + e];
-        qs[2 * e] = st[pa(m)]; qs[2 * e + 1] = st[pb(m)];
+        const int2 m = ms[memQ + e];
+        qs[2 * e] = m.x; qs[2 * e + 1] = m.y;
     }
     for (int e = t0; e < np; e += stride) {
-        const int32_t o = d.phmem[memP + e];
-        ps[2 * e] = st[pa(o)]; ps[2 * e + 1] = st[pb(o)];
+        const int2 o = ms[memP + e];
+        ps[2 * e] = o.x; ps[2 * e + 1] = o.y;
     }
-    for (int e = t0; e < G.nlut; e += stride) lutS[e] = d.lut[lut_off + e];
+    for (int e = t0; e < nlut; e += stride) lutS[e] = d.lut[lut_off + e];
 }
 
 // A = gathered T~_Q (signed), B = Vbar, zero padded; gathers issued 8 at a time.
@@ -810,9 +810,9 @@ __device__ __forceinline__ void pair_body(const DevPtrs& d, const Item it, int c
     constexpr int rows = P == P_BF16 ? kpad : N16;  // rows allocated per matrix
     PairCtx r;
     r.nq = 0; r.np = 0; r.self = false; r.map = nullptr; r.t = nullptr; r.zc = nullptr; r.zs = nullptr;
-    int32_t memQ = 0, memP = 0, lo = 0;
+    int32_t memQ = 0, memP = 0, lo = 0, nlut = 0;
     // every wave reaches every barrier below; only the work is guarded by live
-    const bool live = it.chan >= 0 && pair_ctx(d, it, cur, r, memQ, memP, lo);
+    const bool live = it.chan >= 0 && pair_ctx(d, it, cur, r, memQ, memP, lo, nlut);
     const int lane = tid & 63, w = tid >> 6;
     double* lutS = (double*)lds;
     int32_t* qs = (int32_t*)(lutS + kMaxLut);
@@ -825,7 +825,7 @@ __device__ __forceinline__ void pair_body(const DevPtrs& d, const Item it, int c
     E* Bt = At + rows * lda;  // BF16 only
     const bool qring = (mask & CCD_T_QRING) != 0, ring = (mask & CCD_T_RING) != 0;
     if (live) {
-        pair_stage(d, it, memQ, memP, lo, r.nq, r.np, qs, ps, lutS, tid, 64 * NW);
+        pair_stage(d, memQ, memP, lo, nlut, r.nq, r.np, qs, ps, lutS, tid, 64 * NW);
         if constexpr (P == P_BF16) {
             // zero the K padding (rows and columns n16 .. kpad) of all three matrices
             for (int e = tid; e < 3 * rows * lda; e += 64 * NW) A[e] = (E)0.0f;
@@ -1605,7 +1605,7 @@ struct ccd_ctx {
     std::vector<DevChan> dchans;
     std::vector<DevPh> dph;
     std::vector<int32_t> lpinfo;
-    std::vector<int32_t> st, hh, pp, phmem, phmap, zs, csr_ptr, csr_idx, pgrp, pgi, it_sz0;
+    std::vector<int32_t> st, hh, pp, phst, phmap, zs, csr_ptr, csr_idx, pgrp, pgi, it_sz0;
     std::vector<double> eps, lut, rowE, colE, pscale;
     std::vector<Item> it_elem, it_ladder, it_dchi, it_direct, it_ring_s, it_ring_b, it_lg, it_ue, it_dsub,
         it_dsum;
@@ -1647,7 +1647,7 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 #define STATIC_TABLES(X)                                                  \
     X(st, int32_t) X(eps, double) X(lut, double) X(dgroups, DevGroup)     \
     X(dchans, DevChan) X(dph, DevPh) X(hh, int32_t) X(pp, int32_t)        \
-    X(phmem, int32_t) X(phmap, int32_t) X(zs, int32_t) X(rowE, double) X(colE, double) \
+    X(phst, int32_t) X(phmap, int32_t) X(zs, int32_t) X(rowE, double) X(colE, double) \
     X(csr_ptr, int32_t)                                                   \
     X(csr_idx, int32_t) X(pgrp, int32_t) X(pgi, int32_t) X(pscale, double) \
     X(it_elem, Item) X(it_ladder, Item) X(it_sz0, int32_t) X(it_dchi, Item) \
@@ -1659,7 +1659,7 @@ static DevPtrs make_ptrs(ccd_ctx* c) {
     char* base = c->ws;
     size_t o = c->r_static.off;
     const void* p_st; const void* p_eps; const void* p_lut; const void* p_dgroups; const void* p_dchans;
-    const void* p_dph; const void* p_hh; const void* p_pp; const void* p_phmem; const void* p_phmap;
+    const void* p_dph; const void* p_hh; const void* p_pp; const void* p_phst; const void* p_phmap;
     const void* p_csr_ptr; const void* p_csr_idx; const void* p_pgrp; const void* p_pgi;
     const void* p_it_elem; const void* p_it_ladder; const void* p_it_sz0;
     const void* p_it_dchi; const void* p_it_direct; const void* p_it_ring_s; const void* p_it_ring_b;
@@ -1673,7 +1673,7 @@ static DevPtrs make_ptrs(ccd_ctx* c) {
 #undef TAKE
     d.st = (const int32_t*)p_st; d.eps = (const double*)p_eps; d.lut = (const double*)p_lut;
     d.groups = (const DevGroup*)p_dgroups; d.chans = (const DevChan*)p_dchans; d.ph = (const DevPh*)p_dph;
-    d.hh = (const int32_t*)p_hh; d.pp = (const int32_t*)p_pp; d.phmem = (const int32_t*)p_phmem;
+    d.hh = (const int32_t*)p_hh; d.pp = (const int32_t*)p_pp; d.phst = (const int32_t*)p_phst;
     d.phmap = (const int32_t*)p_phmap; d.csr_ptr = (const int32_t*)p_csr_ptr;
     d.csr_idx = (const int32_t*)p_csr_idx; d.pgrp = (const int32_t*)p_pgrp; d.pgi = (const int32_t*)p_pgi;
     d.it_elem = (const Item*)p_it_elem;
@@ -1984,7 +1984,7 @@ static ccd_status assemble(ccd_ctx* c) {
         D.zidx_off = (int64_t)c->zs.size();
         c->zs.insert(c->zs.end(), H.zs.begin(), H.zs.end());
         // cross channels and their pairs {Q, -Q}; the lower index is the primary
-        const int ph0 = (int)c->dph.size(), mem0 = (int)c->phmem.size();
+        const int ph0 = (int)c->dph.size(), mem0 = (int)c->phst.size() / 2;
         const int64_t map0 = (int64_t)c->phmap.size();
         const int64_t nzp = H.n_zp;
         for (size_t qi = 0; qi < H.ph.size(); qi++) {
@@ -1997,6 +1997,7 @@ static ccd_status assemble(ccd_ctx* c) {
             dp.m = H.ph[h.partner].n;
             dp.partner = ph0 + h.partner;
             dp.mem_off = mem0 + h.mem_off;
+            dp.pmem_off = mem0 + H.ph[h.partner].mem_off;
             dp.zp_off = h.zp_off;
             const int pid = (int)c->dph.size();
             if (h.zp_off >= 0) {
@@ -2009,7 +2010,10 @@ static ccd_status assemble(ccd_ctx* c) {
             c->dph.push_back(dp);
             c->max_ph = std::max(c->max_ph, h.n);
         }
-        for (size_t k = 0; k < H.phmem.size() / 2; k++) c->phmem.push_back(pack_pair(H.phmem[2 * k], H.phmem[2 * k + 1]));
+        for (size_t k = 0; k < H.phmem.size(); k++) {
+            const int x = H.phmem[k];
+            c->phst.push_back(pack_state(H.nx[x], H.ny[x], H.nz[x], H.sz[x]));
+        }
         c->phmap.insert(c->phmap.end(), H.phmap.begin(), H.phmap.end());
         D.phq_off = 0;
         D.ph_base = (int)map0;

@@ -78,8 +78,9 @@ struct DevPh {
     int64_t map_off;      // global offset of the [n][m] position map (shared)
     int64_t zp_off;       // offset of the [n][m] pair block if this channel is the
                           // primary of its pair {Q, -Q} (the lower index), else -1
-    int32_t group, n, partner, mem_off;  // partner / mem_off global
+    int32_t group, n, partner, mem_off;  // partner / mem_off global (members in the packed-state table)
     int32_t m;            // the partner's size (differs from n under a twist)
+    int32_t pmem_off;     // the partner's mem_off
 };
 
 struct Item {             // work item: a channel and a start (row or element)
