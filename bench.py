@@ -407,8 +407,11 @@ def main():
     # measured ceilings of this GPU (HBM copy, resident MFMA loops), outside the timed region
     ceilings = ccd.measure_ceilings(1 << 30, stream=stream.cuda_stream, device=dev)
     ctx.iterate(mixing=MIXING, tol=0.0, max_iter=max(1, args.warmup))
-    # launch shapes tuned on this workload (outside the timed region)
-    tuning, _ = ctx.autotune(ccd.CCD_PREC_FP64, reps=5)
+    # the default launch shapes: the autotuner's choices on this workload vary
+    # from run to run within the noise (~2%), and a fixed shape keeps the
+    # profiled kernels the ones reported here
+    tuning = [0] * 10
+    ctx.set_tuning(tuning)
     ctx.iterate(mixing=MIXING, tol=0.0, max_iter=2)
     torch.cuda.synchronize()
 
