@@ -1010,6 +1010,7 @@ __global__ void __launch_bounds__(256, 3) k_ladder(DevPtrs d, int cur, uint32_t 
     __shared__ __attribute__((aligned(16))) char tks[P == P_F32 ? kKP * 16 * 4 : 16 * (kKP + 8) * 2];
     // per staged pair: (4 p as int8, S |p|^2, S (|p|^2 + |q|^2), rows + 1 as two 16-bit fields)
     __shared__ int4 cvi[2][kKP];
+    __shared__ int2 prs[kLadderRows];  // the two spin rows of the tile's pairs
     const char* lutB = (const char*)lutS;
     for (int bi = blockIdx.x; bi < n_items; bi += gridDim.x) {
     const Item lg = d.it_lg[bi];
@@ -1096,9 +1097,13 @@ __global__ void __launch_bounds__(256, 3) k_ladder(DevPtrs d, int cur, uint32_t 
     const float lv1 = threadIdx.x + 256 < G.nlut ? (float)lutg[threadIdx.x + 256] : 0.0f;
     int4 lpc = cpad;
     if (pp_on && threadIdx.x < kKP && threadIdx.x < nlp) lpc = lp[threadIdx.x];
+    const int2* lpr = (const int2*)lp;
+    const int2 myr = (threadIdx.x < kLadderRows && r0 + threadIdx.x < nlp) ? lpr[2 * (r0 + threadIdx.x) + 1]
+                                                                           : make_int2(-1, -1);
     __syncthreads();  // the previous item's reads of LDS are done
     lutS[threadIdx.x] = lv0;
     if (threadIdx.x + 256 < kMaxLut) lutS[threadIdx.x + 256] = lv1;
+    if (threadIdx.x < kLadderRows) prs[threadIdx.x] = myr;
     if (pp_on) {
         if (threadIdx.x < kKP) cvi[0][threadIdx.x] = threadIdx.x < nlp ? cdesc(lpc) : cpad;
         lpc = cpad;
@@ -1185,14 +1190,10 @@ __global__ void __launch_bounds__(256, 3) k_ladder(DevPtrs d, int cur, uint32_t 
     }
     if (hh_on) {
         // 1/2 sum_kl t_kl^ab chi_klij per spin row: A = t rows, B = chi_klij columns
-        const int2* lpr = (const int2*)lp;
         const double* xg = d.chh + G.chh_base + g * G.n_chh + c.chh_off;
         int2 arow[2];
 #pragma unroll
-        for (int h = 0; h < 2; h++) {
-            const int pr = rbase + 16 * h + (lane & 15);
-            arow[h] = pr < nlp ? lpr[2 * pr + 1] : make_int2(-1, -1);
-        }
+        for (int h = 0; h < 2; h++) arow[h] = prs[32 * w + 16 * h + (lane & 15)];
         for (int k0 = 0; k0 < nhh; k0 += 16) {
             double bq[4];
 #pragma unroll
@@ -1219,14 +1220,13 @@ __global__ void __launch_bounds__(256, 3) k_ladder(DevPtrs d, int cur, uint32_t 
     }
     // this lane owns pairs orow(lane, r) of each tile, column col
     if (act) {
-        const int2* lpr = (const int2*)lp;
 #pragma unroll
         for (int h = 0; h < 2; h++)
 #pragma unroll
             for (int r = 0; r < 4; r++) {
                 const int po = rbase + 16 * h + orow<P>(lane, r);
                 if (po < nlp && col < nhh) {
-                    const int2 rr = lpr[2 * po + 1];
+                    const int2 rr = prs[32 * w + 16 * h + orow<P>(lane, r)];
                     if (rr.x >= 0) d.rmm[T0 + (int64_t)rr.x * nhh + col] = (double)acc[h][r];
                     if (rr.y >= 0) d.rmm[T0 + (int64_t)rr.y * nhh + col] = (double)acc2[h][r];
                 }
@@ -1261,7 +1261,7 @@ __global__ void __launch_bounds__(256, 3) k_ladder(DevPtrs d, int cur, uint32_t 
 template <int NG>
 __device__ __forceinline__ void ladder64_item(const DevPtrs& d, const DevChan& c, const DevGroup& G, int g, int cur,
                                               int r0, int ct, uint32_t mask, bool act, double* lutS,
-                                              double* tks, int4 (*cvi)[kKP]) {
+                                              double* tks, int4 (*cvi)[kKP], int2* prs) {
     constexpr int S = 8;
     const char* lutB = (const char*)lutS;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -1342,9 +1342,14 @@ __device__ __forceinline__ void ladder64_item(const DevPtrs& d, const DevChan& c
     const double lv1 = threadIdx.x + 256 < G.nlut ? lutg[threadIdx.x + 256] : 0.0;
     int4 lpc = cpad;
     if (pp_on && threadIdx.x < kKP && threadIdx.x < nlp) lpc = lp[threadIdx.x];
+    // the two spin rows of the tile's pairs, for the hh operands and the stores
+    const int2* lpr = (const int2*)lp;
+    const int2 myr = (threadIdx.x < kLadderRows && r0 + threadIdx.x < nlp) ? lpr[2 * (r0 + threadIdx.x) + 1]
+                                                                           : make_int2(-1, -1);
     __syncthreads();  // the previous item's reads of LDS are done
     lutS[threadIdx.x] = lv0;
     if (threadIdx.x + 256 < kMaxLut) lutS[threadIdx.x + 256] = lv1;
+    if (threadIdx.x < kLadderRows) prs[threadIdx.x] = myr;
     if (pp_on) {
         if (threadIdx.x < kKP) cvi[0][threadIdx.x] = threadIdx.x < nlp ? cdesc(lpc) : cpad;
         lpc = cpad;
@@ -1413,13 +1418,10 @@ __device__ __forceinline__ void ladder64_item(const DevPtrs& d, const DevChan& c
             }
     }
     // the two spin rows of the lane's A-operand pairs and of its output pairs
-    const int2* lpr = (const int2*)lp;
     int arow[2][2], orow[2][2];
 #pragma unroll
     for (int h = 0; h < 2; h++) {
-        const int pr = rbase + 16 * h + (lane & 15), po = rbase + 16 * h + orow4;
-        const int2 ra = (hh_on && pr < nlp) ? lpr[2 * pr + 1] : make_int2(-1, -1);
-        const int2 ro = po < nlp ? lpr[2 * po + 1] : make_int2(-1, -1);
+        const int2 ra = prs[32 * w + 16 * h + (lane & 15)], ro = prs[32 * w + 16 * h + orow4];
         arow[h][0] = ra.x; arow[h][1] = ra.y;
         orow[h][0] = ro.x; orow[h][1] = ro.y;
     }
@@ -1464,6 +1466,7 @@ __global__ void __launch_bounds__(256, 3) k_ladder64(DevPtrs d, int cur, uint32_
     __shared__ double lutS[kMaxLut];
     __shared__ __attribute__((aligned(16))) double tks[kKP * 16];
     __shared__ int4 cvi[2][kKP];
+    __shared__ int2 prs[kLadderRows];
     for (int bi = blockIdx.x; bi < n_items; bi += gridDim.x) {
         const Item lg = d.it_lg[bi];
         if (lg.chan < 0) continue;
@@ -1476,10 +1479,10 @@ __global__ void __launch_bounds__(256, 3) k_ladder64(DevPtrs d, int cur, uint32_
         // groups of four columns of this column tile that hold columns
         const int ng = min(4, (min(16, c.nhh - 16 * ct) + 3) >> 2);
         switch (ng) {
-            case 1: ladder64_item<1>(d, c, G, g, cur, r0, ct, mask, act, lutS, tks, cvi); break;
-            case 2: ladder64_item<2>(d, c, G, g, cur, r0, ct, mask, act, lutS, tks, cvi); break;
-            case 3: ladder64_item<3>(d, c, G, g, cur, r0, ct, mask, act, lutS, tks, cvi); break;
-            default: ladder64_item<4>(d, c, G, g, cur, r0, ct, mask, act, lutS, tks, cvi); break;
+            case 1: ladder64_item<1>(d, c, G, g, cur, r0, ct, mask, act, lutS, tks, cvi, prs); break;
+            case 2: ladder64_item<2>(d, c, G, g, cur, r0, ct, mask, act, lutS, tks, cvi, prs); break;
+            case 3: ladder64_item<3>(d, c, G, g, cur, r0, ct, mask, act, lutS, tks, cvi, prs); break;
+            default: ladder64_item<4>(d, c, G, g, cur, r0, ct, mask, act, lutS, tks, cvi, prs); break;
         }
     }
 }
