@@ -111,6 +111,25 @@ def test_c3_first_sweep(orc):
     assert np.max(np.abs(g[sel] - w)) <= RTOL * np.max(np.abs(g))
 
 
+@pytest.mark.parametrize("mask", [1, 3])
+def test_c3_ladder_terms_first_sweep(orc, mask):
+    """The ladders alone at N = 66, n^2 <= 36, where S_z = 0 blocks hold up to
+    ~450 momentum pairs, so the pp product runs over several staged chunks of
+    128 pairs (the pipelined path); MBPT2 start, one sweep, against the oracle's
+    intermediates form with the same term mask."""
+    ctx = _gpu_ctx([ccd.problem(66, 36, 0.16)])
+    o3 = orc.O3(orc.PNM(66, 36, 0.16))
+    # the largest block: 892 spin pairs = 446 momentum pairs, four chunks
+    assert max(ctx.export_map(ccd.CCD_MAP_CHANNELS).reshape(-1, 6)[:, 5]) // 2 > 3 * 128
+    res = ctx.iterate(mixing=1.0, tol=0.0, max_iter=1, terms=mask, history=True)
+    _assert_energy(res["history"][0, 0], o3.sweep(1.0, mask), f"mask {mask} sweep 1")
+    idx = ccd.canonical_index(ctx, 0)
+    g = ctx.get_amplitudes(0)
+    sel = np.random.default_rng(12).choice(len(g), 3000, replace=False)
+    w = np.array([o3.t(idx[k, 2], idx[k, 3], idx[k, 0], idx[k, 1]) for k in sel])
+    assert np.max(np.abs(g[sel] - w)) <= RTOL * np.max(np.abs(g))
+
+
 def test_batched_mixed_sizes_equal_single(orc):
     """Problems of different N and cutoff in one context give the same bits as
     each problem alone, and match the oracle."""
