@@ -2217,7 +2217,11 @@ static ccd_status launch_contractions(ccd_ctx* c, const DevPtrs& d, int cur, uin
     if (fork) {
         HIP_TRY(hipEventRecord(c->ev_fork, c->stream));
         for (int k = 0; k < 2; k++) HIP_TRY(hipStreamWaitEvent(c->aux[k], c->ev_fork, 0));
-        {
+        // the critical chain's first kernel is submitted before the rings: the
+        // dependencies are the same, but when the host runs close behind the
+        // GPU (a profiler, a busy host) it reaches the GPU first
+        s = L_direct<P>(c, d, cur, mask);
+        if (s == CCD_OK) {
             StreamSwap sw(c, c->aux[0]);
             s = L_ring<P>(c, d, cur, mask, 2);
             if (s == CCD_OK) s = L_ring<P>(c, d, cur, mask, 3);
@@ -2228,14 +2232,15 @@ static ccd_status launch_contractions(ccd_ctx* c, const DevPtrs& d, int cur, uin
             s = L_ring<P>(c, d, cur, mask, 1);
             if (s == CCD_OK) s = L_ring<P>(c, d, cur, mask, 0);
         }
-        if (s == CCD_OK) s = L_direct<P>(c, d, cur, mask);
         if (s == CCD_OK) {
             HIP_TRY(hipEventRecord(c->ev_mid, c->stream));
+            s = L_ladder<P>(c, d, cur, mask);  // submitted first, as k_direct above
+        }
+        if (s == CCD_OK) {
             HIP_TRY(hipStreamWaitEvent(c->aux[2], c->ev_mid, 0));
             StreamSwap sw(c, c->aux[2]);
             s = L_dchi(c, d, mask);
         }
-        if (s == CCD_OK) s = L_ladder<P>(c, d, cur, mask);
         // one join on the context's stream: the third stream, whose one-body
         // sums end well before the ladder, takes the waits for the two ring
         // streams (every wait is a barrier packet that costs a few us even when
