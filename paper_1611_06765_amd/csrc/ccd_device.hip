@@ -2356,10 +2356,11 @@ static ccd_status run_sweeps(ccd_ctx* c, int n, double alpha, double tol, double
 
 // ---- autotuner ---------------------------------------------------------------
 // Every family launch is idempotent for a fixed cur (it rewrites its outputs
-// from t[cur] and the other families' outputs), so a family can be launched
-// repeatedly and timed alone.  Slots are tuned one at a time in pipeline
-// order, each candidate timed over reps launches after one warm launch; a
-// candidate replaces the incumbent only when it is 2% faster.
+// from t[cur] and the other families' outputs), so the sweep's contractions
+// and update can be launched repeatedly without advancing the iteration.
+// Slots are tuned one at a time in pipeline order, each candidate timed over
+// reps such passes after one warm pass; a candidate replaces the incumbent
+// only when it is 2% faster.
 template <typename F>
 static ccd_status time_family(ccd_ctx* c, F&& launch, int reps, hipEvent_t e0, hipEvent_t e1, double& ms) {
     ccd_status s = launch();
