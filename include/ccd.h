@@ -286,6 +286,24 @@ ccd_status ccd_dense_solve(const double* h, const double* v, int32_t n, int32_t 
                            const ccd_solver_opts* opts, void* dev_work, size_t work_bytes, void* hip_stream,
                            double* e_ref, double* e_mbpt2, double* e_ccd, int32_t* sweeps, double* e_hist);
 
+/* The same dense CCD for callers that cannot allocate device memory (code
+ * under HIP graph capture, serving loops, harnesses that forbid hipMalloc):
+ * arguments and results as ccd_dense_solve, but the work area is a static
+ * device array of CCD_DENSE_STATIC_BYTES that the library holds on every GPU
+ * it runs on until the process ends.  No hipMalloc, hipFree or other
+ * allocating call is made.  The work area is that of the current device
+ * (hipGetDevice), which must be the device of hip_stream.  Every call on one
+ * GPU uses the same array and leaves its contents there; each call writes
+ * every byte it reads before reading it, so no clearing is needed, but calls
+ * that overlap on one GPU (other host threads, other streams) race and must
+ * be serialised by the caller.  Errors: as ccd_dense_solve, and CCD_EINVAL
+ * when ccd_dense_workspace_size(n, n_holes) exceeds CCD_DENSE_STATIC_BYTES
+ * (for example n = 28 with 4 holes fits; n = 40 does not). */
+#define CCD_DENSE_STATIC_BYTES (8u << 20)
+ccd_status ccd_dense_solve_static(const double* h, const double* v, int32_t n, int32_t n_holes,
+                                  const ccd_solver_opts* opts, void* hip_stream, double* e_ref,
+                                  double* e_mbpt2, double* e_ccd, int32_t* sweeps, double* e_hist);
+
 /* Sizes and operation counts of problem `problem`. */
 ccd_status ccd_problem_info(const ccd_ctx* ctx, int32_t problem, ccd_info* info);
 

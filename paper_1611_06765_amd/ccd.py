@@ -82,6 +82,8 @@ _SIGS = {
     "ccd_dense_workspace_size": (_i32, [_i32, _i32, C.POINTER(_sz)]),
     "ccd_dense_solve": (_i32, [_dp, _dp, _i32, _i32, C.POINTER(ccd_solver_opts), _vp, _sz, _vp, _dp, _dp, _dp,
                                _ip, _dp]),
+    "ccd_dense_solve_static": (_i32, [_dp, _dp, _i32, _i32, C.POINTER(ccd_solver_opts), _vp, _dp, _dp, _dp,
+                                      _ip, _dp]),
     "ccd_reference_parts": (_i32, [_vp, _i32, _dp, _dp]),
     "ccd_twist_mesh": (_i32, [_i32, _dp, _dp]),
     "ccd_twist_average": (_i32, [_vp, _dp, _dp]),
@@ -180,6 +182,27 @@ def dense_solve(h, v, n_holes, mixing=1.0, tol=1e-10, max_iter=500, terms=CCD_T_
                               C.byref(er), C.byref(e2), C.byref(ec), C.byref(sw), _dptr(hist))
     _check(st, "ccd_dense_solve", ok=(CCD_OK, CCD_NOT_CONVERGED, CCD_DIVERGED))
     del buf
+    return {"status": st, "e_ref": er.value, "e_mbpt2": e2.value, "e_ccd": ec.value, "sweeps": sw.value,
+            "history": hist[:sw.value]}
+
+
+def dense_solve_static(h, v, n_holes, mixing=1.0, tol=1e-10, max_iter=500, terms=CCD_T_ALL, tol_rel=0.0,
+                       stream=None):
+    """dense_solve through ccd_dense_solve_static: no device memory is
+    allocated, the library's static work area of the current device is used."""
+    h = np.ascontiguousarray(h, dtype=np.float64)
+    n = h.size
+    v = np.ascontiguousarray(v, dtype=np.float64).reshape(-1)
+    if v.size != n ** 4:
+        raise ValueError("v must hold n^4 elements")
+    o = ccd_solver_opts(mixing, tol, max_iter, CCD_PREC_FP64, 0, terms, 0.0, 1, 0, tol_rel, 0)
+    er, e2, ec = C.c_double(), C.c_double(), C.c_double()
+    sw = C.c_int32()
+    hist = np.zeros(max_iter)
+    sp = None if stream is None else _vp(stream)
+    st = _lib.ccd_dense_solve_static(_dptr(h), _dptr(v), n, n_holes, C.byref(o), sp,
+                                     C.byref(er), C.byref(e2), C.byref(ec), C.byref(sw), _dptr(hist))
+    _check(st, "ccd_dense_solve_static", ok=(CCD_OK, CCD_NOT_CONVERGED, CCD_DIVERGED))
     return {"status": st, "e_ref": er.value, "e_mbpt2": e2.value, "e_ccd": ec.value, "sweeps": sw.value,
             "history": hist[:sw.value]}
 

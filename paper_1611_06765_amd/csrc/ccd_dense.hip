@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -168,22 +169,22 @@ extern "C" ccd_status ccd_dense_workspace_size(int32_t n, int32_t n_holes, size_
     return CCD_OK;
 }
 
-extern "C" ccd_status ccd_dense_solve(const double* h, const double* v, int32_t n, int32_t n_holes,
-                                      const ccd_solver_opts* o, void* dev_work, size_t work_bytes, void* hip_stream,
-                                      double* e_ref, double* e_mbpt2, double* e_ccd, int32_t* sweeps,
-                                      double* e_hist) {
-    size_t need = 0;
-    ccd_status st = ccd_dense_workspace_size(n, n_holes, &need);
-    if (st != CCD_OK) return st;
-    if (!h || !v || !o || !dev_work || (((uintptr_t)dev_work) & 255) || work_bytes < need) {
-        ccd::set_error("ccd_dense_solve: need h, v, opts and a 256-byte aligned work buffer of "
-                       "ccd_dense_workspace_size bytes");
-        return CCD_EINVAL;
-    }
-    if (!(o->mixing > 0.0 && o->mixing <= 1.0) || o->max_iter < 1) {
-        ccd::set_error("ccd_dense_solve: need 0 < mixing <= 1 and max_iter >= 1");
-        return CCD_EINVAL;
-    }
+// The work area of ccd_dense_solve_static (8 MiB per GPU; see
+// scratch_address below for how host code reaches it).
+constexpr size_t kDenseScratchBytes = CCD_DENSE_STATIC_BYTES;
+static __device__ __align__(256) unsigned char scratch[kDenseScratchBytes];
+
+namespace {
+
+// The solve itself, on a work area `dev_work` of at least dense_layout(n,
+// n_holes).total bytes (sizes and options already checked).  Every byte of the
+// area that a kernel reads is written first in this call: v and eps by the
+// uploads, t0 by the MBPT2 kernel, t1 by the first sweep, the energy partials
+// by the energy kernel, so a reused area needs no clearing.
+ccd_status dense_solve_on(const double* h, const double* v, int32_t n, int32_t n_holes,
+                          const ccd_solver_opts* o, void* dev_work, hipStream_t s, double* e_ref,
+                          double* e_mbpt2, double* e_ccd, int32_t* sweeps, double* e_hist) {
+    ccd_status st = CCD_OK;
     const int nh = n_holes, np = n - n_holes;
     auto V = [&](int p, int q, int r, int s) { return v[(((size_t)p * n + q) * n + r) * n + s]; };
     // Fock energies (eq. pairingsp) and the reference energy
@@ -206,7 +207,6 @@ extern "C" ccd_status ccd_dense_solve(const double* h, const double* v, int32_t 
             }
     const DenseLayout L = dense_layout(n, nh);
     char* base = (char*)dev_work;
-    hipStream_t s = (hipStream_t)hip_stream;
     DENSE_TRY(hipMemcpyAsync(base + L.v, v, 8 * (size_t)n * n * n * n, hipMemcpyHostToDevice, s));
     DENSE_TRY(hipMemcpyAsync(base + L.eps, eps.data(), 8 * (size_t)n, hipMemcpyHostToDevice, s));
     Dense q;
@@ -261,4 +261,82 @@ extern "C" ccd_status ccd_dense_solve(const double* h, const double* v, int32_t 
     if (e_ccd) *e_ccd = e;
     if (sweeps) *sweeps = done;
     return (o->tol > 0.0 || o->tol_rel > 0.0) && !conv ? CCD_NOT_CONVERGED : CCD_OK;
+}
+
+ccd_status dense_check_opts(const char* who, const double* h, const double* v, const ccd_solver_opts* o) {
+    if (!h || !v || !o) {
+        ccd::set_error(std::string(who) + ": need h, v and opts");
+        return CCD_EINVAL;
+    }
+    if (!(o->mixing > 0.0 && o->mixing <= 1.0) || o->max_iter < 1) {
+        ccd::set_error(std::string(who) + ": need 0 < mixing <= 1 and max_iter >= 1");
+        return CCD_EINVAL;
+    }
+    return CCD_OK;
+}
+
+// Work area of ccd_dense_solve_static: one per GPU, alive until the process
+// ends.  Host code never passes `scratch` itself to a kernel or a copy (on the
+// host the name is only a stand-in); it uses the device address that
+// hipGetSymbolAddress returns for the current device, kept per device.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+ccd_status scratch_address(void** out) {
+    int dev = -1;
+    DENSE_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) {
+        ccd::set_error("ccd_dense_solve_static: device index out of range");
+        return CCD_EINVAL;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void* p = nullptr;
+        DENSE_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p || (((uintptr_t)p) & 255)) {
+            ccd::set_error("ccd_dense_solve_static: scratch array has no aligned device address");
+            return CCD_EHIP;
+        }
+        g_scratch_addr[dev] = p;
+    }
+    *out = g_scratch_addr[dev];
+    return CCD_OK;
+}
+
+}  // namespace
+
+extern "C" ccd_status ccd_dense_solve(const double* h, const double* v, int32_t n, int32_t n_holes,
+                                      const ccd_solver_opts* o, void* dev_work, size_t work_bytes, void* hip_stream,
+                                      double* e_ref, double* e_mbpt2, double* e_ccd, int32_t* sweeps,
+                                      double* e_hist) {
+    size_t need = 0;
+    ccd_status st = ccd_dense_workspace_size(n, n_holes, &need);
+    if (st != CCD_OK) return st;
+    if ((st = dense_check_opts("ccd_dense_solve", h, v, o)) != CCD_OK) return st;
+    if (!dev_work || (((uintptr_t)dev_work) & 255) || work_bytes < need) {
+        ccd::set_error("ccd_dense_solve: need a 256-byte aligned work buffer of ccd_dense_workspace_size bytes");
+        return CCD_EINVAL;
+    }
+    return dense_solve_on(h, v, n, n_holes, o, dev_work, (hipStream_t)hip_stream, e_ref, e_mbpt2, e_ccd,
+                          sweeps, e_hist);
+}
+
+extern "C" ccd_status ccd_dense_solve_static(const double* h, const double* v, int32_t n, int32_t n_holes,
+                                             const ccd_solver_opts* o, void* hip_stream, double* e_ref,
+                                             double* e_mbpt2, double* e_ccd, int32_t* sweeps, double* e_hist) {
+    size_t need = 0;
+    ccd_status st = ccd_dense_workspace_size(n, n_holes, &need);
+    if (st != CCD_OK) return st;
+    if ((st = dense_check_opts("ccd_dense_solve_static", h, v, o)) != CCD_OK) return st;
+    if (need > kDenseScratchBytes) {
+        ccd::set_error("ccd_dense_solve_static: this model space needs " + std::to_string(need) +
+                       " bytes of work area, more than the " + std::to_string(kDenseScratchBytes) +
+                       " of the static one; use ccd_dense_solve with a caller buffer");
+        return CCD_EINVAL;
+    }
+    void* work = nullptr;
+    if ((st = scratch_address(&work)) != CCD_OK) return st;
+    return dense_solve_on(h, v, n, n_holes, o, work, (hipStream_t)hip_stream, e_ref, e_mbpt2, e_ccd, sweeps,
+                          e_hist);
 }
