@@ -10,17 +10,20 @@
  * the GPU path.
  *
  * Contents (each function cites the passage it follows):
- *   - pure neutron matter (PNM) model space: plane waves in a periodic box,
- *     spherical cutoff, holes = lowest N states            (sec. "Single-particle
+ *   - nuclear matter model space: plane waves in a periodic box, spherical
+ *     cutoff, spin, and for symmetric nuclear matter (SNM) isospin; holes =
+ *     lowest A states; pure neutron matter (PNM) has neutrons only
+ *                                                          (sec. "Single-particle
  *     basis for infinite matter"; the model-space loop of sec. "Developing a CCD
- *     code for infinite matter")
+ *     code for infinite matter" with its extra isospin loop; Table 1's magic
+ *     numbers doubled for SNM)
  *   - twisted boundary conditions: momenta k = (2 pi n + theta) / L, states
  *     ordered by energy and the lowest N filled for each twist  (the
  *     twist-averaging passage and its algorithm, sec. "Developing a CCD code
  *     for infinite matter")
- *   - Minnesota interaction from its operator form, with the spin-exchange
- *     algebra evaluated as explicit 4x4 matrices in two-spin space and the
- *     Gaussian Fourier transform                         (sec. "Two-body
+ *   - Minnesota interaction from its operator form, with the spin- and
+ *     isospin-exchange algebra evaluated as explicit 16x16 matrices in
+ *     two-nucleon spin-isospin space and the Gaussian Fourier transform                         (sec. "Two-body
  *     interaction", Table "Parameters used to define the Minnesota interaction")
  *   - antisymmetrised elements <pq||rs> = <pq|v|rs> - <pq|v|sr>
  *   - Fock energies and reference energy                 (normal-ordering section)
@@ -28,9 +31,9 @@
  *     over dense four-index arrays indexed p*n^3+q*n^2+r*n+s, usable for any
  *     Hamiltonian given as dense arrays (pairing model, tiny PNM bases)
  *   - O3: the same iteration in the intermediates form (chi(b,c), chi(k,j),
- *     chi(kl,ij), chi(kb,cj)) for PNM, where the fourth index of every
- *     amplitude and matrix element is deduced from momentum and spin
- *     conservation (elements that violate it are zero).
+ *     chi(kl,ij), chi(kb,cj)) for nuclear matter, where the fourth index of
+ *     every amplitude and matrix element is deduced from momentum, spin and
+ *     isospin conservation (elements that violate it are zero).
  *
  * Precision: IEEE binary64, fixed loop order, no fast-math.
  */
@@ -70,9 +73,11 @@ typedef struct {
     int R;         /* floor(sqrt(nmax2)) */
     double rho, L, hb2m; /* density (fm^-3), box side (fm), hbar^2/m (MeV fm^2) */
     double theta[3];     /* twist angles (radians); 0 = periodic, pi = antiperiodic */
+    int species;         /* 1: neutrons only (PNM); 2: protons and neutrons */
     double Va[3], ka[3]; /* Minnesota strengths / ranges, channels R, T, S */
-    double Oa[3][4][4];  /* spin operators of the three channels, two-spin basis */
+    double Oa[3][16][16];/* spin-isospin operators of the three channels, two-nucleon basis */
     int *nx, *ny, *nz, *sz; /* sz = -1 or +1 (twice s_z) */
+    int *tz;             /* twice t_z: -1 proton, +1 neutron */
     double *tkin;        /* kinetic energies */
     double *eps;         /* Fock energies */
     int *grid;           /* (n, s) -> state index or -1 */
@@ -86,15 +91,17 @@ static int isqrt_floor(int x) {
     return r;
 }
 
-/* two-spin basis index |s1 s2>, s in {-1,+1} -> 0/1 */
-static int sidx(int s1, int s2) { return 2 * (s1 > 0) + (s2 > 0); }
+/* internal state of one nucleon, c = 2 [s_z > 0] + [t_z > 0], and of two
+ * nucleons, 4 c1 + c2 (16 states: spin and isospin of both) */
+static int cint(int s, int t) { return 2 * (s > 0) + (t > 0); }
+static int cidx(const void* hv, int p, int q);
 
-static void mat4_mul(double a[4][4], double b[4][4], double c[4][4]) {
-    double t[4][4];
-    for (int i = 0; i < 4; i++)
-        for (int j = 0; j < 4; j++) {
+static void mat16_mul(double a[16][16], double b[16][16], double c[16][16]) {
+    double t[16][16];
+    for (int i = 0; i < 16; i++)
+        for (int j = 0; j < 16; j++) {
             double s = 0.0;
-            for (int k = 0; k < 4; k++) s += a[i][k] * b[k][j];
+            for (int k = 0; k < 16; k++) s += a[i][k] * b[k][j];
             t[i][j] = s;
         }
     memcpy(c, t, sizeof(t));
@@ -103,45 +110,63 @@ static void mat4_mul(double a[4][4], double b[4][4], double c[4][4]) {
 /* Spin/isospin operator of the Minnesota potential (sec. "Two-body
  * interaction"):
  *   V = 1/2 ( V_R + 1/2(1+P_s) V_T + 1/2(1-P_s) V_S ) (1 - P_s P_t).
- * Between two neutrons the isospin exchange P_t acts as +1.  P_s swaps the two
- * spins.  Each channel's operator is built as an explicit 4x4 matrix. */
+ * P_s swaps the spins of the two nucleons, P_t their isospins.  Both are built
+ * as explicit 16x16 permutation matrices on |s1 t1, s2 t2>, and each channel's
+ * operator as a product of such matrices.  Between two neutrons P_t acts as
+ * +1, which leaves only the spin singlet in the R and S channels and nothing
+ * in the T channel. */
 static void build_spin_operators(orc_pnm* h) {
-    double one[4][4] = {{0}}, Ps[4][4] = {{0}};
-    for (int i = 0; i < 4; i++) one[i][i] = 1.0;
+    double one[16][16] = {{0}}, Ps[16][16] = {{0}}, Pt[16][16] = {{0}};
+    for (int i = 0; i < 16; i++) one[i][i] = 1.0;
     for (int s1 = -1; s1 <= 1; s1 += 2)
-        for (int s2 = -1; s2 <= 1; s2 += 2) Ps[sidx(s2, s1)][sidx(s1, s2)] = 1.0;
-    double Pt = 1.0; /* two neutrons */
-    double ex[4][4], plus[4][4], minus[4][4];
-    for (int i = 0; i < 4; i++)
-        for (int j = 0; j < 4; j++) {
-            ex[i][j] = one[i][j] - Ps[i][j] * Pt;
+        for (int t1 = -1; t1 <= 1; t1 += 2)
+            for (int s2 = -1; s2 <= 1; s2 += 2)
+                for (int t2 = -1; t2 <= 1; t2 += 2) {
+                    int ket = 4 * cint(s1, t1) + cint(s2, t2);
+                    Ps[4 * cint(s2, t1) + cint(s1, t2)][ket] = 1.0;
+                    Pt[4 * cint(s1, t2) + cint(s2, t1)][ket] = 1.0;
+                }
+    double PsPt[16][16], ex[16][16], plus[16][16], minus[16][16], tmp[16][16];
+    mat16_mul(Ps, Pt, PsPt);
+    for (int i = 0; i < 16; i++)
+        for (int j = 0; j < 16; j++) {
+            ex[i][j] = one[i][j] - PsPt[i][j];
             plus[i][j] = 0.5 * (one[i][j] + Ps[i][j]);
             minus[i][j] = 0.5 * (one[i][j] - Ps[i][j]);
         }
-    double tmp[4][4];
     /* R: 1/2 * (1 - P_s P_t) */
-    for (int i = 0; i < 4; i++)
-        for (int j = 0; j < 4; j++) h->Oa[0][i][j] = 0.5 * ex[i][j];
+    for (int i = 0; i < 16; i++)
+        for (int j = 0; j < 16; j++) h->Oa[0][i][j] = 0.5 * ex[i][j];
     /* T: 1/2 * 1/2(1+P_s) * (1 - P_s P_t) */
-    mat4_mul(plus, ex, tmp);
-    for (int i = 0; i < 4; i++)
-        for (int j = 0; j < 4; j++) h->Oa[1][i][j] = 0.5 * tmp[i][j];
+    mat16_mul(plus, ex, tmp);
+    for (int i = 0; i < 16; i++)
+        for (int j = 0; j < 16; j++) h->Oa[1][i][j] = 0.5 * tmp[i][j];
     /* S: 1/2 * 1/2(1-P_s) * (1 - P_s P_t) */
-    mat4_mul(minus, ex, tmp);
-    for (int i = 0; i < 4; i++)
-        for (int j = 0; j < 4; j++) h->Oa[2][i][j] = 0.5 * tmp[i][j];
+    mat16_mul(minus, ex, tmp);
+    for (int i = 0; i < 16; i++)
+        for (int j = 0; j < 16; j++) h->Oa[2][i][j] = 0.5 * tmp[i][j];
 }
 
-static int grid_index(const orc_pnm* h, int x, int y, int z, int s) {
+static int grid_slot(const orc_pnm* h, int x, int y, int z, int s, int t) {
     int R = h->R, W = 2 * R + 1;
+    return (((((x + R) * W) + (y + R)) * W + (z + R)) * 2 + (s > 0)) * 2 + (t > 0);
+}
+
+static int grid_index(const orc_pnm* h, int x, int y, int z, int s, int t) {
+    int R = h->R;
     if (x < -R || x > R || y < -R || y > R || z < -R || z > R) return -1;
-    if (s != -1 && s != 1) return -1;
-    return h->grid[((((x + R) * W) + (y + R)) * W + (z + R)) * 2 + (s > 0)];
+    if ((s != -1 && s != 1) || (t != -1 && t != 1)) return -1;
+    return h->grid[grid_slot(h, x, y, z, s, t)];
+}
+
+static int cidx(const void* hv, int p, int q) {
+    const orc_pnm* h = (const orc_pnm*)hv;
+    return 4 * cint(h->sz[p], h->tz[p]) + cint(h->sz[q], h->tz[q]);
 }
 
 void orc_pnm_free(orc_pnm* h) {
     if (!h) return;
-    free(h->nx); free(h->ny); free(h->nz); free(h->sz);
+    free(h->nx); free(h->ny); free(h->nz); free(h->sz); free(h->tz);
     free(h->tkin); free(h->eps); free(h->grid);
     for (int a = 0; a < 3; a++) free(h->gcache[a]);
     free(h);
@@ -150,24 +175,31 @@ void orc_pnm_free(orc_pnm* h) {
 double orc_pnm_vas_direct(const orc_pnm* h, int p, int q, int r, int s);
 
 /* Model space: the loop over shells, then n_x, n_y, n_z, then s_z = -1/2, +1/2,
- * of sec. "Developing a CCD code for infinite matter".  Box side from
- * rho = N / L^3, momenta k = (2 pi n + theta) / L, kinetic energy
- * hbar^2 k^2 / 2m (sec. "Single-particle basis for infinite matter" and the
- * twist-averaging passage).  The states are then ordered by single-particle
- * energy and the first N are holes ("Order States by Energy and Fill Holes").
- * The order is decided on the exact-shaped key |n|^2 + 2 n.phi, phi = theta/2pi
- * (the kinetic energy is (hbar^2/2m)(2pi/L)^2 (key + |phi|^2)), evaluated in
- * FP64 left to right; equal keys keep the loop order.  Without a twist the key
- * is the integer shell, so the loop order is kept as it is.
- * Returns NULL if N leaves no particle states, if N is odd, or, without a
- * twist, if N does not close a shell. */
-orc_pnm* orc_pnm_new_twist(int nmax2, int nparticles, double rho, double hb2m,
-                           double VR, double kR, double VT, double kT, double VS, double kS,
-                           double thx, double thy, double thz) {
-    if (nmax2 < 0 || nparticles <= 0 || rho <= 0.0 || (nparticles & 1)) return NULL;
+ * of sec. "Developing a CCD code for infinite matter", with the extra innermost
+ * loop over isospin (t_z = -1/2 proton, +1/2 neutron) that the passage asks for
+ * symmetric nuclear matter; pure neutron matter has neutrons only.  Box side
+ * from rho = A / L^3 (A = all nucleons), momenta k = (2 pi n + theta) / L,
+ * kinetic energy hbar^2 k^2 / 2m with one mass for both species (sec.
+ * "Single-particle basis for infinite matter" and the twist-averaging
+ * passage).  The states are then ordered by single-particle energy and the
+ * first A are holes ("Order States by Energy and Fill Holes").  The order is
+ * decided on the exact-shaped key |n|^2 + 2 n.phi, phi = theta/2pi (the
+ * kinetic energy is (hbar^2/2m)(2pi/L)^2 (key + |phi|^2)), evaluated in FP64
+ * left to right; equal keys keep the loop order.  Without a twist the key is
+ * the integer shell, so the loop order is kept as it is, and with both species
+ * the first A states fill whole momenta with all four spin-isospin states.
+ * Returns NULL if A leaves no particle states, if A is not a multiple of the
+ * 2 species spins, or, without a twist and unless open_ok, if A does not close
+ * a shell. */
+static orc_pnm* nm_build(int nmax2, int nparticles, int species, double rho, double hb2m,
+                         double VR, double kR, double VT, double kT, double VS, double kS,
+                         double thx, double thy, double thz, int open_ok) {
+    if (nmax2 < 0 || nparticles <= 0 || rho <= 0.0 || (species != 1 && species != 2)) return NULL;
+    if (species == 1 && (nparticles & 1)) return NULL;
     orc_pnm* h = (orc_pnm*)calloc(1, sizeof(orc_pnm));
     h->nmax2 = nmax2;
     h->nh = nparticles;
+    h->species = species;
     h->rho = rho;
     h->hb2m = hb2m;
     h->theta[0] = thx; h->theta[1] = thy; h->theta[2] = thz;
@@ -178,11 +210,12 @@ orc_pnm* orc_pnm_new_twist(int nmax2, int nparticles, double rho, double hb2m,
     h->L = cbrt((double)nparticles / rho);
     int R = isqrt_floor(nmax2);
     h->R = R;
-    int cap = (2 * R + 1) * (2 * R + 1) * (2 * R + 1) * 2;
+    int cap = (2 * R + 1) * (2 * R + 1) * (2 * R + 1) * 4;
     h->nx = (int*)malloc(sizeof(int) * cap);
     h->ny = (int*)malloc(sizeof(int) * cap);
     h->nz = (int*)malloc(sizeof(int) * cap);
     h->sz = (int*)malloc(sizeof(int) * cap);
+    h->tz = (int*)malloc(sizeof(int) * cap);
     h->grid = (int*)malloc(sizeof(int) * cap);
     for (int i = 0; i < cap; i++) h->grid[i] = -1;
     int n = 0;
@@ -191,10 +224,11 @@ orc_pnm* orc_pnm_new_twist(int nmax2, int nparticles, double rho, double hb2m,
             for (int y = -R; y <= R; y++)
                 for (int z = -R; z <= R; z++)
                     for (int s = -1; s <= 1; s += 2)
-                        if (x * x + y * y + z * z == shell) {
-                            h->nx[n] = x; h->ny[n] = y; h->nz[n] = z; h->sz[n] = s;
-                            n++;
-                        }
+                        for (int t = (species == 2 ? -1 : 1); t <= 1; t += 2)
+                            if (x * x + y * y + z * z == shell) {
+                                h->nx[n] = x; h->ny[n] = y; h->nz[n] = z; h->sz[n] = s; h->tz[n] = t;
+                                n++;
+                            }
     h->ns = n;
     if (nparticles >= n) { orc_pnm_free(h); return NULL; }
     /* order by energy: insertion sort on the key, stable */
@@ -207,25 +241,23 @@ orc_pnm* orc_pnm_new_twist(int nmax2, int nparticles, double rho, double hb2m,
         }
         for (int p = 1; p < n; p++) {
             double k = key[p];
-            int x = h->nx[p], y = h->ny[p], z = h->nz[p], s = h->sz[p];
+            int x = h->nx[p], y = h->ny[p], z = h->nz[p], s = h->sz[p], t = h->tz[p];
             int q = p - 1;
             while (q >= 0 && key[q] > k) {
                 key[q + 1] = key[q];
-                h->nx[q + 1] = h->nx[q]; h->ny[q + 1] = h->ny[q]; h->nz[q + 1] = h->nz[q]; h->sz[q + 1] = h->sz[q];
+                h->nx[q + 1] = h->nx[q]; h->ny[q + 1] = h->ny[q]; h->nz[q + 1] = h->nz[q];
+                h->sz[q + 1] = h->sz[q]; h->tz[q + 1] = h->tz[q];
                 q--;
             }
             key[q + 1] = k;
-            h->nx[q + 1] = x; h->ny[q + 1] = y; h->nz[q + 1] = z; h->sz[q + 1] = s;
+            h->nx[q + 1] = x; h->ny[q + 1] = y; h->nz[q + 1] = z; h->sz[q + 1] = s; h->tz[q + 1] = t;
         }
         free(key);
     }
-    for (int p = 0; p < n; p++) {
-        int W = 2 * R + 1;
-        h->grid[((((h->nx[p] + R) * W) + (h->ny[p] + R)) * W + (h->nz[p] + R)) * 2 + (h->sz[p] > 0)] = p;
-    }
+    for (int p = 0; p < n; p++) h->grid[grid_slot(h, h->nx[p], h->ny[p], h->nz[p], h->sz[p], h->tz[p])] = p;
     /* periodic box: closed shell, i.e. last hole and first particle lie in
      * different shells */
-    if (!twisted) {
+    if (!twisted && !open_ok) {
         int a = nparticles - 1, b = nparticles;
         int sa = h->nx[a] * h->nx[a] + h->ny[a] * h->ny[a] + h->nz[a] * h->nz[a];
         int sb = h->nx[b] * h->nx[b] + h->ny[b] * h->ny[b] + h->nz[b] * h->nz[b];
@@ -260,6 +292,21 @@ orc_pnm* orc_pnm_new_twist(int nmax2, int nparticles, double rho, double hb2m,
     return h;
 }
 
+/* pure neutron matter, periodic or twisted */
+orc_pnm* orc_pnm_new_twist(int nmax2, int nparticles, double rho, double hb2m,
+                           double VR, double kR, double VT, double kT, double VS, double kS,
+                           double thx, double thy, double thz) {
+    return nm_build(nmax2, nparticles, 1, rho, hb2m, VR, kR, VT, kT, VS, kS, thx, thy, thz, 0);
+}
+
+/* nuclear matter: species = 1 (neutrons) or 2 (protons and neutrons, A/2
+ * of each when A fills whole momenta), periodic box; open_ok accepts an A
+ * that does not close a shell (small exact test systems) */
+orc_pnm* orc_nm_new(int nmax2, int nparticles, int species, double rho, double hb2m,
+                    double VR, double kR, double VT, double kT, double VS, double kS, int open_ok) {
+    return nm_build(nmax2, nparticles, species, rho, hb2m, VR, kR, VT, kT, VS, kS, 0.0, 0.0, 0.0, open_ok);
+}
+
 /* periodic boundary conditions: no twist */
 orc_pnm* orc_pnm_new(int nmax2, int nparticles, double rho, double hb2m,
                      double VR, double kR, double VT, double kT, double VS, double kS) {
@@ -268,8 +315,8 @@ orc_pnm* orc_pnm_new(int nmax2, int nparticles, double rho, double hb2m,
 
 /* Non-antisymmetrised element <pq|v|rs> of the Minnesota interaction:
  * V_a/L^3 (pi/kappa_a)^{3/2} exp(-q^2 / 4 kappa_a) delta_{k_p+k_q, k_r+k_s}
- * with q = (k_p - k_q - k_r + k_s)/2, times the spin matrix element of each
- * channel's operator (sec. "Two-body interaction"). */
+ * with q = (k_p - k_q - k_r + k_s)/2, times the spin-isospin matrix element of
+ * each channel's operator (sec. "Two-body interaction"). */
 static double kmom(const orc_pnm* h, int n, int d) { return (2.0 * M_PI * n + h->theta[d]) / h->L; }
 
 static double v_direct(const orc_pnm* h, int p, int q, int r, int s) {
@@ -282,7 +329,7 @@ static double v_direct(const orc_pnm* h, int p, int q, int r, int s) {
     double qz = 0.5 * (kmom(h, h->nz[p], 2) - kmom(h, h->nz[q], 2) - kmom(h, h->nz[r], 2) + kmom(h, h->nz[s], 2));
     double q2 = qx * qx + qy * qy + qz * qz;
     double L3 = h->L * h->L * h->L;
-    int bra = sidx(h->sz[p], h->sz[q]), ket = sidx(h->sz[r], h->sz[s]);
+    int bra = cidx(h, p, q), ket = cidx(h, r, s);
     double v = 0.0;
     for (int a = 0; a < 3; a++) {
         double spin = h->Oa[a][bra][ket];
@@ -300,8 +347,8 @@ double orc_pnm_vas_direct(const orc_pnm* h, int p, int q, int r, int s) {
 /* Same value, for callers that guarantee momentum conservation, with the
  * Gaussian factors read from the per-|2q|^2 cache built in orc_pnm_new. */
 static inline double vas_fast(const orc_pnm* h, int p, int q, int r, int s) {
-    int bra = sidx(h->sz[p], h->sz[q]);
-    int k1 = sidx(h->sz[r], h->sz[s]), k2 = sidx(h->sz[s], h->sz[r]);
+    int bra = cidx(h, p, q);
+    int k1 = cidx(h, r, s), k2 = cidx(h, s, r);
     int dx = h->nx[p] - h->nx[q] - h->nx[r] + h->nx[s];
     int dy = h->ny[p] - h->ny[q] - h->ny[r] + h->ny[s];
     int dz = h->nz[p] - h->nz[q] - h->nz[r] + h->nz[s];
@@ -334,6 +381,11 @@ void orc_pnm_states(const orc_pnm* h, int* nx, int* ny, int* nz, int* sz) {
         nx[p] = h->nx[p]; ny[p] = h->ny[p]; nz[p] = h->nz[p]; sz[p] = h->sz[p];
     }
 }
+
+void orc_pnm_isospins(const orc_pnm* h, int* tz) {
+    for (int p = 0; p < h->ns; p++) tz[p] = h->tz[p];
+}
+int orc_pnm_species(const orc_pnm* h) { return h->species; }
 
 void orc_pnm_kinetic(const orc_pnm* h, double* out) { memcpy(out, h->tkin, sizeof(double) * h->ns); }
 void orc_pnm_fock(const orc_pnm* h, double* out) { memcpy(out, h->eps, sizeof(double) * h->ns); }
@@ -577,12 +629,13 @@ typedef struct {
 } orc_o3;
 
 static int partner(const orc_pnm* h, int p, int q, int r) {
-    /* state s with n_s = n_p + n_q - n_r and s_s = s_p + s_q - s_r */
+    /* state s with n_s = n_p + n_q - n_r, s_s = s_p + s_q - s_r, t_s = t_p + t_q - t_r */
     int x = h->nx[p] + h->nx[q] - h->nx[r];
     int y = h->ny[p] + h->ny[q] - h->ny[r];
     int z = h->nz[p] + h->nz[q] - h->nz[r];
     int s = h->sz[p] + h->sz[q] - h->sz[r];
-    return grid_index(h, x, y, z, s);
+    int t = h->tz[p] + h->tz[q] - h->tz[r];
+    return grid_index(h, x, y, z, s, t);
 }
 
 #define O3I(o, i, j, a) (((size_t)(i) * (o)->nh + (j)) * (o)->np + ((a) - (o)->nh))

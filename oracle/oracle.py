@@ -24,8 +24,10 @@ T_LINEAR = T_PP | T_HH | T_RING
 T_ALL = 127
 
 # Minnesota parameters (Table "Parameters used to define the Minnesota
-# interaction model"; V_S is attractive, hbar^2/m = 41.47 MeV fm^2).
-MINNESOTA = dict(VR=200.0, kR=1.487, VT=178.0, kT=0.639, VS=-91.85, kS=0.465)
+# interaction model"; V_T and V_S are attractive, hbar^2/m = 41.47 MeV fm^2).
+# The table prints both without a sign.  Between two neutrons the V_T channel
+# vanishes, so its sign matters only with protons and neutrons.
+MINNESOTA = dict(VR=200.0, kR=1.487, VT=-178.0, kT=0.639, VS=-91.85, kS=0.465)
 HBAR2_OVER_M = 41.47
 
 
@@ -53,6 +55,9 @@ def lib():
         sig = {
             "orc_pnm_new": (vp, [i, i, d, d, d, d, d, d, d, d]),
             "orc_pnm_new_twist": (vp, [i, i, d, d, d, d, d, d, d, d, d, d, d]),
+            "orc_nm_new": (vp, [i, i, i, d, d, d, d, d, d, d, d, i]),
+            "orc_pnm_isospins": (None, [vp, ip]),
+            "orc_pnm_species": (i, [vp]),
             "orc_pnm_free": (None, [vp]),
             "orc_pnm_vas_direct": (d, [vp, i, i, i, i]),
             "orc_pnm_vas_fast": (d, [vp, i, i, i, i]),
@@ -151,6 +156,33 @@ class PNM:
         out = np.zeros(n ** 4)
         lib().orc_pnm_dense_v(self.h, _dp(out))
         return out.reshape(n, n, n, n)
+
+
+class NM(PNM):
+    """Nuclear matter: species = 2 gives symmetric nuclear matter (A/2
+    protons and A/2 neutrons when A fills whole momenta; Table 1's magic
+    numbers doubled), species = 1 pure neutron matter.  open_ok accepts a
+    nucleon number that does not close a shell (small exact test systems).
+    Periodic box."""
+
+    def __init__(self, n_particles: int, nmax2: int, rho: float, species: int = 2, open_ok: bool = False,
+                 hbar2_over_m: float = HBAR2_OVER_M, **pot):
+        p = dict(MINNESOTA)
+        p.update(pot)
+        self.N, self.nmax2, self.rho = n_particles, nmax2, rho
+        self.twist = (0.0, 0.0, 0.0)
+        self.h = lib().orc_nm_new(nmax2, n_particles, species, rho, hbar2_over_m,
+                                  p["VR"], p["kR"], p["VT"], p["kT"], p["VS"], p["kS"], int(bool(open_ok)))
+        if not self.h:
+            raise ValueError("A leaves no particle states or does not close a shell")
+        self.ns = lib().orc_pnm_nstates(self.h)
+        self.L = lib().orc_pnm_L(self.h)
+
+    def isospins(self):
+        """twice t_z per state: -1 proton, +1 neutron"""
+        a = np.zeros(self.ns, dtype=np.int32)
+        lib().orc_pnm_isospins(self.h, _ip(a))
+        return a
 
 
 class O1:
