@@ -3,8 +3,8 @@
     python -m paper_1611_06765_amd.build_lib
 
 Produces paper_1611_06765_amd/libccd.so from csrc/ccd_plan.cpp,
-csrc/ccd_device.hip, csrc/ccd_mlp.hip, csrc/ccd_ceil.hip and
-csrc/ccd_dense.hip.  Packed FP32 instructions are disabled for all device
+csrc/ccd_device.hip, csrc/ccd_mlp.hip, csrc/ccd_ceil.hip, csrc/ccd_dense.hip
+and csrc/ccd_nm.hip.  Packed FP32 instructions are disabled for all device
 code.
 """
 import os
@@ -27,7 +27,7 @@ def build(verbose: bool = False) -> str:
            "-I", os.path.join(HERE, "..", "include"),
            os.path.join(CSRC, "ccd_plan.cpp"), os.path.join(CSRC, "ccd_device.hip"),
            os.path.join(CSRC, "ccd_mlp.hip"), os.path.join(CSRC, "ccd_ceil.hip"),
-           os.path.join(CSRC, "ccd_dense.hip"),
+           os.path.join(CSRC, "ccd_dense.hip"), os.path.join(CSRC, "ccd_nm.hip"),
            "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)

@@ -66,6 +66,21 @@ class ccd_adam_opts(C.Structure):
                 ("batch", C.c_int32)]
 
 
+class ccd_nm_problem(C.Structure):
+    _fields_ = [("n_nucleons", C.c_int32), ("species", C.c_int32), ("nmax2", C.c_int32),
+                ("density", C.c_double), ("hbar2_over_m", C.c_double), ("V_R", C.c_double),
+                ("kappa_R", C.c_double), ("V_T", C.c_double), ("kappa_T", C.c_double),
+                ("V_S", C.c_double), ("kappa_S", C.c_double)]
+
+
+class ccd_nm_info(C.Structure):
+    _fields_ = [("n_states", C.c_int32), ("n_holes", C.c_int32), ("n_channels", C.c_int32),
+                ("n_ph_channels", C.c_int32), ("max_hh", C.c_int32), ("max_pp", C.c_int32),
+                ("max_ph", C.c_int32), ("n_amplitudes", C.c_int64), ("box_L", C.c_double),
+                ("flops_per_sweep", C.c_double)]
+
+
+CCD_NM_MAP_STATES, CCD_NM_MAP_CHANNELS, CCD_NM_MAP_HH, CCD_NM_MAP_PP = range(4)
 CCD_MLP_NPACK, CCD_MLP_NPARAM = 8, 17800
 
 _vp, _i32, _sz = C.c_void_p, C.c_int32, C.c_size_t
@@ -106,6 +121,19 @@ _SIGS = {
     "ccd_kernel_families": (_i32, []),
     "ccd_kernel_name": (C.c_char_p, [_i32]),
     "ccd_kernel_times": (_i32, [_vp, _dp, C.POINTER(C.c_int64), _i32]),
+    "ccd_nm_build": (_i32, [C.POINTER(ccd_nm_problem), _vp, C.POINTER(_vp)]),
+    "ccd_nm_info_get": (_i32, [_vp, C.POINTER(ccd_nm_info)]),
+    "ccd_nm_workspace_size": (_i32, [_vp, C.POINTER(_sz)]),
+    "ccd_nm_bind_workspace": (_i32, [_vp, _vp, _sz]),
+    "ccd_nm_iterate": (_i32, [_vp, C.POINTER(ccd_solver_opts), _ip, _dp]),
+    "ccd_nm_energy": (_i32, [_vp, _dp, _dp, _dp]),
+    "ccd_nm_get_amplitudes": (_i32, [_vp, _dp, _sz]),
+    "ccd_nm_set_amplitudes": (_i32, [_vp, _dp, _sz]),
+    "ccd_nm_export_maps": (_i32, [_vp, _i32, _ip, _sz, C.POINTER(_sz)]),
+    "ccd_nm_export_tables": (_i32, [_vp, _dp, _dp, _dp]),
+    "ccd_nm_element": (_i32, [_vp, _i32, _i32, _i32, _i32, _dp]),
+    "ccd_nm_last_ms": (_i32, [_vp, _dp]),
+    "ccd_nm_destroy": (None, [_vp]),
     "ccd_last_error": (C.c_char_p, []),
     "ccd_version": (C.c_char_p, []),
     "ccd_destroy": (None, [_vp]),
@@ -448,6 +476,105 @@ def mlp_train(params, state, feat, target, order, batch, lr, beta1=0.9, beta2=0.
                               _vp(order.data_ptr()), order.shape[0], C.byref(o), _vp(ptr), nb, C.byref(loss),
                               _stream_of(feat)), "ccd_mlp_train")
     return loss.value
+
+
+MINNESOTA_NM = dict(V_R=200.0, kappa_R=1.487, V_T=-178.0, kappa_T=0.639, V_S=-91.85, kappa_S=0.465)
+
+
+def nm_problem(n_nucleons, nmax2, density, species=2, hbar2_over_m=HBAR2_OVER_M, **pot):
+    """ccd_nm_problem: species 2 = A/2 protons and A/2 neutrons, 1 = neutrons."""
+    p = dict(MINNESOTA_NM)
+    p.update(pot)
+    return ccd_nm_problem(n_nucleons, species, nmax2, density, hbar2_over_m, p["V_R"], p["kappa_R"],
+                          p["V_T"], p["kappa_T"], p["V_S"], p["kappa_S"])
+
+
+class NMContext:
+    """One ccd_nm_ctx: a nuclear-matter problem with isospin (include/ccd_nm.h)."""
+
+    def __init__(self, problem, stream=None):
+        self._h = _vp()
+        sp = None if stream is None else _vp(stream)
+        _check(_lib.ccd_nm_build(C.byref(problem), sp, C.byref(self._h)), "ccd_nm_build")
+        self.workspace = None
+
+    def __del__(self):
+        self.close()
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value and _lib is not None:
+            _lib.ccd_nm_destroy(self._h)
+            self._h = _vp()
+
+    def info(self):
+        i = ccd_nm_info()
+        _check(_lib.ccd_nm_info_get(self._h, C.byref(i)), "ccd_nm_info_get")
+        return {k: getattr(i, k) for k, _ in ccd_nm_info._fields_}
+
+    def export_map(self, which):
+        need = _sz()
+        _check(_lib.ccd_nm_export_maps(self._h, which, None, 0, C.byref(need)), "ccd_nm_export_maps")
+        out = np.zeros(need.value, dtype=np.int32)
+        _check(_lib.ccd_nm_export_maps(self._h, which, out.ctypes.data_as(_ip), out.size, None),
+               "ccd_nm_export_maps")
+        return out
+
+    def export_tables(self):
+        n = self.info()["n_states"]
+        tk, eps, er = np.zeros(n), np.zeros(n), C.c_double()
+        _check(_lib.ccd_nm_export_tables(self._h, _dptr(tk), _dptr(eps), C.byref(er)), "ccd_nm_export_tables")
+        return tk, eps, er.value
+
+    def element(self, p, q, r, s):
+        v = C.c_double()
+        _check(_lib.ccd_nm_element(self._h, p, q, r, s, C.byref(v)), "ccd_nm_element")
+        return v.value
+
+    def canonical_index(self):
+        """(i, j, a, b) of every canonical amplitude."""
+        ch = self.export_map(CCD_NM_MAP_CHANNELS).reshape(-1, 7)
+        hh = self.export_map(CCD_NM_MAP_HH).reshape(-1, 2)
+        pp = self.export_map(CCD_NM_MAP_PP).reshape(-1, 2)
+        out, ho, po = [], 0, 0
+        for *_, nhh, npp in ch:
+            out.append(np.concatenate([np.tile(hh[ho:ho + nhh], (npp, 1)), np.repeat(pp[po:po + npp], nhh, axis=0)],
+                                      axis=1))
+            ho += nhh
+            po += npp
+        return np.concatenate(out, axis=0)
+
+    def bind(self, device="cuda"):
+        import torch
+        n = _sz()
+        _check(_lib.ccd_nm_workspace_size(self._h, C.byref(n)), "ccd_nm_workspace_size")
+        self.workspace = torch.empty(n.value + 256, dtype=torch.uint8, device=device)
+        ptr = (self.workspace.data_ptr() + 255) & ~255
+        _check(_lib.ccd_nm_bind_workspace(self._h, _vp(ptr), n.value), "ccd_nm_bind_workspace")
+        return self
+
+    def iterate(self, mixing=1.0, tol=0.0, max_iter=1, terms=CCD_T_ALL, tol_rel=0.0):
+        o = ccd_solver_opts(mixing, tol, max_iter, CCD_PREC_FP64, 0, terms, 0.0, 1, 0, tol_rel, 0)
+        sw = C.c_int32()
+        hist = np.zeros(max_iter)
+        st = _lib.ccd_nm_iterate(self._h, C.byref(o), C.byref(sw), _dptr(hist))
+        _check(st, "ccd_nm_iterate", ok=(CCD_OK, CCD_NOT_CONVERGED))
+        ms = C.c_double()
+        _check(_lib.ccd_nm_last_ms(self._h, C.byref(ms)), "ccd_nm_last_ms")
+        return {"status": st, "sweeps": sw.value, "history": hist, "gpu_ms": ms.value}
+
+    def energy(self):
+        a, b, c = C.c_double(), C.c_double(), C.c_double()
+        _check(_lib.ccd_nm_energy(self._h, C.byref(a), C.byref(b), C.byref(c)), "ccd_nm_energy")
+        return a.value, b.value, c.value
+
+    def get_amplitudes(self):
+        out = np.zeros(self.info()["n_amplitudes"])
+        _check(_lib.ccd_nm_get_amplitudes(self._h, _dptr(out), out.size), "ccd_nm_get_amplitudes")
+        return out
+
+    def set_amplitudes(self, t):
+        t = np.ascontiguousarray(t, dtype=np.float64)
+        _check(_lib.ccd_nm_set_amplitudes(self._h, _dptr(t), t.size), "ccd_nm_set_amplitudes")
 
 
 def canonical_index(ctx: Context, p=0):
