@@ -18,7 +18,7 @@ ccd = pytest.importorskip("paper_1611_06765_amd.ccd")
 
 def header_functions():
     names = set()
-    for h in ("ccd.h", "ccd_mlp.h"):
+    for h in ("ccd.h", "ccd_mlp.h", "ccd_nm.h"):
         src = open(os.path.join(ROOT, "include", h)).read()
         src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
         names |= set(re.findall(r"\b(ccd_[a-z_0-9]+)\s*\(", src))
