@@ -213,6 +213,44 @@ def sweep_rate_c3(ccd, stream, steps, warmup, ceilings):
             "amplitudes": info["n_amplitudes"], "kernels": m["kernels"], "roofline": m["roofline"]}
 
 
+def snm_rate(ccd, stream, steps, warmup):
+    """Symmetric nuclear matter through the isospin path: A = 108 (54 protons,
+    54 neutrons), n^2 <= 20 (1556 states), rho = 0.16, FP64, mixing 0.5: sweeps
+    per second, the executed FP64 rate and the roofline of its longest launch
+    (per-launch HIP events on the library's stream).  (At A = 76 and 132 the
+    iteration diverges in this basis through the V_T channel.)"""
+    import torch
+    c = ccd.NMContext(ccd.nm_problem(108, 20, 0.16), stream=stream).bind()
+    info = c.info()
+    c.iterate(mixing=MIXING, max_iter=max(1, warmup))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = c.iterate(mixing=MIXING, max_iter=steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    c.set_timing(True)
+    c.kernel_times(reset=True)
+    c.iterate(mixing=MIXING, max_iter=steps)
+    kt = c.kernel_times(reset=True)
+    c.set_timing(False)
+    er, e2, ec = c.energy()
+    c.close()
+    kernels = {k: {"ms_per_sweep": v[0] / steps, "launches_per_sweep": v[1] / steps} for k, v in kt.items() if v[1]}
+    per_launch = {k: kt[k][0] / kt[k][1] for k in kt if kt[k][1] and kt[k][2] > 0}
+    dom = max(per_launch, key=lambda k: per_launch[k])
+    achieved = kt[dom][2] / (per_launch[dom] * 1e-3) / 1e12
+    return {"workload": "SNM A=108 (54 p + 54 n), n^2<=20 (1556 states), rho=0.16, Minnesota with V_T, FP64, "
+                        "mixing 0.5, one solve",
+            "ccd_iterations_per_s": steps / el, "ms_per_sweep": el * 1e3 / steps,
+            "gpu_ms_per_sweep": r["gpu_ms"] / steps,
+            "tflops": info["flops_per_sweep"] / (el / steps) / 1e12, "amplitudes": info["n_amplitudes"],
+            "e_per_nucleon_after_mev": (er + ec) / 108, "sweeps_run": steps + warmup,
+            "kernels": kernels,
+            "roofline": {"kernel": "k_nm_gemm (" + dom + ")", "bound": "mfma", "achieved": achieved,
+                         "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+                         "ms_per_launch": per_launch[dom], "flops_per_launch": kt[dom][2]}}
+
+
 def cpu_baseline(budget_s=20.0):
     """The oracle (intermediates form, fourth index deduced) timed on the host
     cores: one density of the same workload, sweeps until the budget is spent."""
@@ -563,6 +601,7 @@ def main():
     }
     ctx.close()
     out["c3_fp64"] = sweep_rate_c3(ccd, stream.cuda_stream, args.steps, args.warmup, ceilings)
+    out["snm"] = snm_rate(ccd, stream.cuda_stream, min(args.steps, 40), min(args.warmup, 5))
     if not args.no_forms:
         out["convergence_c2"] = convergence_c2(ccd, stream.cuda_stream)
         out["mixed_c3"] = form_mixed_c3(ccd, stream.cuda_stream)

@@ -133,6 +133,9 @@ _SIGS = {
     "ccd_nm_export_tables": (_i32, [_vp, _dp, _dp, _dp]),
     "ccd_nm_element": (_i32, [_vp, _i32, _i32, _i32, _i32, _dp]),
     "ccd_nm_last_ms": (_i32, [_vp, _dp]),
+    "ccd_nm_set_timing": (_i32, [_vp, _i32]),
+    "ccd_nm_kernel_times": (_i32, [_vp, _dp, C.POINTER(C.c_int64), _dp, _i32]),
+    "ccd_nm_kernel_name": (C.c_char_p, [_i32]),
     "ccd_nm_destroy": (None, [_vp]),
     "ccd_last_error": (C.c_char_p, []),
     "ccd_version": (C.c_char_p, []),
@@ -561,6 +564,17 @@ class NMContext:
         ms = C.c_double()
         _check(_lib.ccd_nm_last_ms(self._h, C.byref(ms)), "ccd_nm_last_ms")
         return {"status": st, "sweeps": sw.value, "history": hist, "gpu_ms": ms.value}
+
+    def set_timing(self, on):
+        _check(_lib.ccd_nm_set_timing(self._h, int(bool(on))), "ccd_nm_set_timing")
+
+    def kernel_times(self, reset=False):
+        """{family: (ms summed, launches, FP64 flops per launch)}"""
+        n = 7
+        ms, ln, fl = np.zeros(n), np.zeros(n, dtype=np.int64), np.zeros(n)
+        _check(_lib.ccd_nm_kernel_times(self._h, _dptr(ms), ln.ctypes.data_as(C.POINTER(C.c_int64)), _dptr(fl),
+                                        int(bool(reset))), "ccd_nm_kernel_times")
+        return {_lib.ccd_nm_kernel_name(f).decode(): (ms[f], int(ln[f]), fl[f]) for f in range(n)}
 
     def energy(self):
         a, b, c = C.c_double(), C.c_double(), C.c_double()

@@ -465,8 +465,16 @@ inline size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace
 
+// kernel families of a sweep, for per-launch timing
+enum { NF_GATHER = 0, NF_ROWCOL, NF_DCHI, NF_GEMM1, NF_GEMM2, NF_UPDATE, NF_ENERGY, NF_NUM };
+const char* const kNmFamily[NF_NUM] = {"gather", "rowcol", "dchi", "gemm_chi", "gemm_ladder_ring", "update", "energy"};
+
 struct ccd_nm_ctx {
     ccd_nm_problem par;
+    bool timing = false;
+    double fam_ms[NF_NUM] = {0};
+    int64_t fam_n[NF_NUM] = {0};
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;  // (family, events)
     hipStream_t stream = nullptr;
     int ns = 0, nh = 0, nlut = 0;
     double L = 0.0, eref = 0.0, emp2 = 0.0, ecorr = 0.0, last_ms = 0.0;
@@ -483,7 +491,7 @@ struct ccd_nm_ctx {
     int tiles_a = 0, tiles_b = 0;  // tiles of the first launch, then of the second
     int64_t n_amp = 0, n_chh = 0, n_tq = 0, n_cp = 0;
     int n_rows = 0, n_cols = 0, max_hh = 0, max_pp = 0, max_ph = 0;
-    double flops = 0.0;
+    double flops = 0.0, flops_a = 0.0;  // all products; those of the first launch
     // workspace
     char* ws = nullptr;
     size_t ws_bytes = 0;
@@ -776,6 +784,7 @@ ccd_status nm_plan(ccd_nm_ctx* c) {
         c->flops += 2.0 * nP * nP * nQ;
     }
     c->tiles_a = (int)c->tiles.size();
+    c->flops_a = c->flops;
     for (size_t k = 0; k < c->ch.size(); k++) {  // ladders
         const NmChanD& C = c->chd[k];
         NmJob J = blank();
@@ -914,20 +923,77 @@ ccd_status nm_energy_now(ccd_nm_ctx* c, int slot, double* e) {
     return CCD_OK;
 }
 
+// with timing on, every launch is bracketed by two events (collected when
+// the stream is next synchronised)
+struct NmTimed {
+    ccd_nm_ctx* c;
+    int fam;
+    hipEvent_t a = nullptr, b = nullptr;
+    NmTimed(ccd_nm_ctx* cc, int f) : c(cc), fam(f) {
+        if (c->timing && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess)
+            (void)hipEventRecord(a, c->stream);
+    }
+    ~NmTimed() {
+        if (a && b) {
+            (void)hipEventRecord(b, c->stream);
+            c->pending.push_back({fam, {a, b}});
+        } else {
+            if (a) (void)hipEventDestroy(a);
+            if (b) (void)hipEventDestroy(b);
+        }
+    }
+};
+
+ccd_status nm_harvest(ccd_nm_ctx* c) {
+    if (c->pending.empty()) return CCD_OK;
+    NM_TRY(hipStreamSynchronize(c->stream));
+    for (auto& p : c->pending) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, p.second.first, p.second.second) == hipSuccess) {
+            c->fam_ms[p.first] += ms;
+            c->fam_n[p.first] += 1;
+        }
+        (void)hipEventDestroy(p.second.first);
+        (void)hipEventDestroy(p.second.second);
+    }
+    c->pending.clear();
+    return CCD_OK;
+}
+
 // one sweep from t[cur] into t[cur ^ 1]; the energy lands in ehist[slot]
 ccd_status nm_sweep(ccd_nm_ctx* c, double alpha, uint32_t mask, int slot) {
     NmDev& d = c->dev;
     hipStream_t s = c->stream;
     const int cur = c->cur;
-    if (d.n_tq > 0) k_nm_gather<<<nm_grid(d.n_tq, 256), 256, 0, s>>>(d, cur);
-    k_nm_rowcol<<<nm_grid(std::max(c->n_rows, c->n_cols * 64), 256), 256, 0, s>>>(d, cur, (int)c->ch.size(),
-                                                                                  c->n_rows, c->n_cols);
-    k_nm_dchi<<<nm_grid(c->ns, 256), 256, 0, s>>>(d, mask, c->nh);
-    if (c->tiles_a > 0) k_nm_gemm<<<std::min(c->tiles_a, 8192), 256, 0, s>>>(d, cur, mask, 0, c->tiles_a);
-    if (c->tiles_b > 0)
+    if (d.n_tq > 0) {
+        NmTimed tm(c, NF_GATHER);
+        k_nm_gather<<<nm_grid(d.n_tq, 256), 256, 0, s>>>(d, cur);
+    }
+    {
+        NmTimed tm(c, NF_ROWCOL);
+        k_nm_rowcol<<<nm_grid(std::max(c->n_rows, c->n_cols * 64), 256), 256, 0, s>>>(d, cur, (int)c->ch.size(),
+                                                                                      c->n_rows, c->n_cols);
+    }
+    {
+        NmTimed tm(c, NF_DCHI);
+        k_nm_dchi<<<nm_grid(c->ns, 256), 256, 0, s>>>(d, mask, c->nh);
+    }
+    if (c->tiles_a > 0) {
+        NmTimed tm(c, NF_GEMM1);
+        k_nm_gemm<<<std::min(c->tiles_a, 8192), 256, 0, s>>>(d, cur, mask, 0, c->tiles_a);
+    }
+    if (c->tiles_b > 0) {
+        NmTimed tm(c, NF_GEMM2);
         k_nm_gemm<<<std::min(c->tiles_b, 8192), 256, 0, s>>>(d, cur, mask, c->tiles_a, c->tiles_b);
-    k_nm_update<<<std::min<int>((int)c->items.size(), 8192), 256, 0, s>>>(d, cur, alpha, mask);
-    k_nm_energy<<<1, 256, 0, s>>>(d, slot);
+    }
+    {
+        NmTimed tm(c, NF_UPDATE);
+        k_nm_update<<<std::min<int>((int)c->items.size(), 8192), 256, 0, s>>>(d, cur, alpha, mask);
+    }
+    {
+        NmTimed tm(c, NF_ENERGY);
+        k_nm_energy<<<1, 256, 0, s>>>(d, slot);
+    }
     NM_TRY(hipGetLastError());
     c->cur ^= 1;
     return CCD_OK;
@@ -1173,6 +1239,37 @@ extern "C" ccd_status ccd_nm_element(const ccd_nm_ctx* c, int32_t p, int32_t q, 
     return CCD_OK;
 }
 
+extern "C" ccd_status ccd_nm_set_timing(ccd_nm_ctx* c, int32_t enabled) {
+    if (!c) {
+        ccd::set_error("ccd_nm_set_timing: NULL context");
+        return CCD_EINVAL;
+    }
+    ccd_status st = nm_harvest(c);
+    c->timing = enabled != 0;
+    return st;
+}
+
+extern "C" ccd_status ccd_nm_kernel_times(ccd_nm_ctx* c, double* ms, int64_t* launches, double* flops,
+                                          int32_t reset) {
+    if (!c) {
+        ccd::set_error("ccd_nm_kernel_times: NULL context");
+        return CCD_EINVAL;
+    }
+    ccd_status st = nm_harvest(c);
+    if (st != CCD_OK) return st;
+    for (int f = 0; f < NF_NUM; f++) {
+        if (ms) ms[f] = c->fam_ms[f];
+        if (launches) launches[f] = c->fam_n[f];
+        if (flops) flops[f] = f == NF_GEMM1 ? c->flops_a : (f == NF_GEMM2 ? c->flops - c->flops_a : 0.0);
+        if (reset) { c->fam_ms[f] = 0.0; c->fam_n[f] = 0; }
+    }
+    return CCD_OK;
+}
+
+extern "C" const char* ccd_nm_kernel_name(int32_t family) {
+    return family >= 0 && family < NF_NUM ? kNmFamily[family] : "";
+}
+
 extern "C" ccd_status ccd_nm_last_ms(const ccd_nm_ctx* c, double* ms) {
     if (!c || !ms) {
         ccd::set_error("ccd_nm_last_ms: NULL argument");
@@ -1184,6 +1281,7 @@ extern "C" ccd_status ccd_nm_last_ms(const ccd_nm_ctx* c, double* ms) {
 
 extern "C" void ccd_nm_destroy(ccd_nm_ctx* c) {
     if (!c) return;
+    (void)nm_harvest(c);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     delete c;

@@ -99,6 +99,30 @@ def test_snm_larger_basis_two_sweeps(orc):
     assert _amplitudes_match(c, o3)
 
 
+def test_snm_1556_states_three_sweeps(orc):
+    """A = 28, n^2 <= 20 (1556 states, blocks of up to hundreds of pairs):
+    MBPT2 and three sweeps against the oracle."""
+    c = _ctx(28, 20, 0.16)
+    o3 = orc.O3(orc.NM(28, 20, 0.16))
+    assert _close(c.energy()[1], o3.emp2)
+    r = c.iterate(mixing=0.5, max_iter=3)
+    for s in range(3):
+        assert _close(r["history"][s], o3.sweep(0.5)), s
+
+
+def test_snm_divergence_is_reported():
+    """A = 76, n^2 <= 12, rho = 0.16: the iteration diverges (through the V_T
+    channel; with V_T = 0 the same system converges), and the call says so
+    instead of returning non-finite energies as converged."""
+    c = _ctx(76, 12, 0.16)
+    with pytest.raises(ccd.CCDError) as e:
+        c.iterate(mixing=0.5, tol=1e-8, max_iter=200)
+    assert e.value.status == ccd.CCD_DIVERGED
+    import torch
+    q = ccd.NMContext(ccd.nm_problem(76, 12, 0.16, V_T=0.0), stream=torch.cuda.current_stream().cuda_stream).bind()
+    assert q.iterate(mixing=0.5, tol=1e-8, max_iter=400)["status"] == ccd.CCD_OK
+
+
 def test_neutron_species_equals_the_pnm_path():
     """Species 1 through the generic kernels against the specialised pure
     neutron matter path (N = 66, n^2 <= 20, rho = 0.16): energies sweep by
