@@ -297,16 +297,20 @@ __global__ void __launch_bounds__(256) k_nm_rowcol(NmDev d, int cur, int n_chan,
 // one-body intermediates, diagonal by momentum, spin and isospin conservation:
 //   chi_bb - f_bb = -1/2 sum_kld t_kl^bd <kl||bd> = -(sum of the row sums of
 //   the rows holding b), chi_jj - f_jj = +1/2 sum_cdl <jl||cd> t_jl^cd = +(sum of
-//   the column sums of the columns holding j); one thread per state, CSR order
+//   the column sums of the columns holding j); one wave per state: lane l sums
+//   entries l, l + 64, ... of its CSR list, then a fixed butterfly over the lanes
 __global__ void __launch_bounds__(256) k_nm_dchi(NmDev d, uint32_t mask, int nh) {
-    for (int s = blockIdx.x * 256 + threadIdx.x; s < d.ns; s += gridDim.x * 256) {
+    const int lane = threadIdx.x & 63;
+    const int wid = (blockIdx.x * 256 + threadIdx.x) >> 6, nw = (gridDim.x * 256) >> 6;
+    for (int s = wid; s < d.ns; s += nw) {
         double acc = 0.0;
         const bool hole = s < nh;
         if (hole ? (mask & CCD_T_QHOLE) : (mask & CCD_T_QPART)) {
-            for (int k = d.csr_ptr[s]; k < d.csr_ptr[s + 1]; k++)
+            for (int k = d.csr_ptr[s] + lane; k < d.csr_ptr[s + 1]; k += 64)
                 acc += hole ? d.colsum[d.csr_idx[k]] : d.rowsum[d.csr_idx[k]];
         }
-        d.dchi[s] = hole ? acc : -acc;
+        acc = nm_wave_sum(acc);
+        if (lane == 0) d.dchi[s] = hole ? acc : -acc;
     }
 }
 
@@ -324,30 +328,49 @@ __device__ __forceinline__ double* nm_arr(const NmDev& d, int which, int cur) {
     }
 }
 
-__device__ __forceinline__ double nm_loadA(const NmDev& d, const NmSeg& s, const double* A, int m, int k,
-                                           const double* u) {
-    switch (s.amode) {
-        case AM_ROW: return A[s.a_off + (int64_t)m * s.lda + k];
-        case AM_COL: return A[s.a_off + (int64_t)k * s.lda + m];
-        case AM_GPAIR: {
-            const int32_t R = d.pp[s.a_rows + m], C = d.pp[s.a_cols + k];
-            return nm_vas(u, d.nlut, d.st[pr_a(R)], d.st[pr_b(R)], d.st[pr_a(C)], d.st[pr_b(C)]);
+// the packed states (first, second) of entry x of a pair list (pp pairs for
+// AM_GPAIR, cross-channel members (particle, hole) for AM_GVBAR)
+__device__ __forceinline__ int2 nm_pair_states(const NmDev& d, int amode, int list, int x) {
+    const int32_t P = amode == AM_GPAIR ? d.pp[list + x] : d.mem[list + x];
+    return make_int2(d.st[pr_a(P)], d.st[pr_b(P)]);
+}
+
+// element (m, k) of a generated A operand from the staged pair states:
+// AM_GPAIR <ab||cd> with row (a, b), column (c, d); AM_GVBAR <kl||cd> with row
+// x = (c, k) of P and column m = (d, l) of Q
+__device__ __forceinline__ double nm_genA(int amode, const double* u, int nlut, int2 R, int2 C) {
+    return amode == AM_GPAIR ? nm_vas(u, nlut, R.x, R.y, C.x, C.y) : nm_vas(u, nlut, R.y, C.y, R.x, C.x);
+}
+
+// this thread's two A and two B entries of the chunk at k0 (array operands;
+// zero outside the block); generated A entries are made when staged
+__device__ __forceinline__ void nm_fetch(const NmSeg& S, const NmJob& J, const double* A, const double* B, int m0,
+                                         int n0, int k0, double* ra, double* rb) {
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        const int q = threadIdx.x + 256 * h;
+        const int am = q >> 4, ak = q & 15, m = m0 + am, kk = k0 + ak;
+        ra[h] = 0.0;
+        if (m < J.M && kk < S.K) {
+            if (S.amode == AM_ROW) ra[h] = A[S.a_off + (int64_t)m * S.lda + kk];
+            else if (S.amode == AM_COL) ra[h] = A[S.a_off + (int64_t)kk * S.lda + m];
         }
-        default: {  // AM_GVBAR: row x = (c, k) of P, column m = (d, l) of Q: <kl||cd>
-            const int32_t X = d.mem[s.a_rows + m], Y = d.mem[s.a_cols + k];
-            return nm_vas(u, d.nlut, d.st[pr_b(X)], d.st[pr_b(Y)], d.st[pr_a(X)], d.st[pr_a(Y)]);
-        }
+        const int bk = q >> 5, bn = q & 31, kb = k0 + bk, n = n0 + bn;
+        rb[h] = (kb < S.K && n < J.N) ? B[S.b_off + (int64_t)kb * S.ldb + n] : 0.0;
     }
 }
 
 // One 32 x 32 output tile of one job per workgroup, four waves of 16 x 16;
-// K in chunks of 16 staged in LDS, four FP64 16x16x4 MFMA steps per chunk.
+// K in chunks of 16 staged in LDS, four FP64 16x16x4 MFMA steps per chunk;
+// the array operands of chunk c + 1 are loaded into registers before chunk c
+// is multiplied.
 // Lane l of a wave supplies A[l%16][l/16], B[l/16][l%16] and receives
 // D[l/16 + 4r][l%16].
 __global__ void __launch_bounds__(256) k_nm_gemm(NmDev d, int cur, uint32_t mask, int tile0, int n_tiles) {
     __shared__ double u[4 * (4 * kNmMaxNmax2 + 1)];
     __shared__ double sA[32][17];
     __shared__ double sB[16][33];
+    __shared__ int2 rst[32], cst[16];  // pair states of a generated A operand: tile rows, chunk columns
     for (int k = threadIdx.x; k < 4 * d.nlut; k += 256) u[k] = d.u[k];
     __syncthreads();
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wm = w >> 1, wn = w & 1;
@@ -361,17 +384,29 @@ __global__ void __launch_bounds__(256) k_nm_gemm(NmDev d, int cur, uint32_t mask
             if (!(mask & (uint32_t)S.term)) continue;
             const double* A = nm_arr(d, S.a_arr, cur);
             const double* B = nm_arr(d, S.b_arr, cur);
+            const bool gen = S.amode == AM_GPAIR || S.amode == AM_GVBAR;
+            double ra[2], rb[2];
+            nm_fetch(S, J, A, B, m0, n0, 0, ra, rb);
             for (int k0 = 0; k0 < S.K; k0 += 16) {
                 __syncthreads();  // the previous chunk's reads are done
-                for (int q = threadIdx.x; q < 512; q += 256) {
+                if (gen) {
+                    if (k0 == 0 && threadIdx.x < 32 && m0 + (int)threadIdx.x < J.M)
+                        rst[threadIdx.x] = nm_pair_states(d, S.amode, S.a_rows, m0 + threadIdx.x);
+                    if (threadIdx.x >= 64 && threadIdx.x < 80 && k0 + (int)threadIdx.x - 64 < S.K)
+                        cst[threadIdx.x - 64] = nm_pair_states(d, S.amode, S.a_cols, k0 + threadIdx.x - 64);
+                    __syncthreads();
+                }
+#pragma unroll
+                for (int h = 0; h < 2; h++) {
+                    const int q = threadIdx.x + 256 * h;
                     const int am = q >> 4, ak = q & 15;
-                    const int m = m0 + am, kk = k0 + ak;
-                    sA[am][ak] = (m < J.M && kk < S.K) ? S.alpha * nm_loadA(d, S, A, m, kk, u) : 0.0;
-                    const int bk = q >> 5, bn = q & 31;
-                    const int kb = k0 + bk, n = n0 + bn;
-                    sB[bk][bn] = (kb < S.K && n < J.N) ? B[S.b_off + (int64_t)kb * S.ldb + n] : 0.0;
+                    double av = ra[h];
+                    if (gen) av = (m0 + am < J.M && k0 + ak < S.K) ? nm_genA(S.amode, u, d.nlut, rst[am], cst[ak]) : 0.0;
+                    sA[am][ak] = S.alpha * av;
+                    sB[q >> 5][q & 31] = rb[h];
                 }
                 __syncthreads();
+                if (k0 + 16 < S.K) nm_fetch(S, J, A, B, m0, n0, k0 + 16, ra, rb);
 #pragma unroll
                 for (int s = 0; s < 4; s++) {
                     const double a = sA[wm * 16 + (lane & 15)][4 * s + (lane >> 4)];
@@ -976,7 +1011,7 @@ ccd_status nm_sweep(ccd_nm_ctx* c, double alpha, uint32_t mask, int slot) {
     }
     {
         NmTimed tm(c, NF_DCHI);
-        k_nm_dchi<<<nm_grid(c->ns, 256), 256, 0, s>>>(d, mask, c->nh);
+        k_nm_dchi<<<nm_grid((int64_t)c->ns * 64, 256), 256, 0, s>>>(d, mask, c->nh);
     }
     if (c->tiles_a > 0) {
         NmTimed tm(c, NF_GEMM1);
