@@ -532,6 +532,8 @@ def main():
                     help="skip the mixed / batched / learned wall-time comparisons")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--only", choices=["c2", "c3", "snm"], default=None,
+                    help="profiling runs: only this sweep measurement (no JSON line)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -545,6 +547,26 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
+    if args.only:
+        # one workload's sweeps alone, for counter and trace runs of the profiler
+        if args.copy_probe:
+            x = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+            y = torch.empty_like(x)
+            y.copy_(x)
+            torch.cuda.synchronize()
+            del x, y
+        fake = {"fp64_mfma_4x4x4_tflops": 1.0, "fp64_mfma_16x16x4_tflops": 1.0}
+        if args.only == "c2":
+            c = ccd.Context([ccd.problem(N, NMAX2, r) for r in DENSITIES], stream=stream.cuda_stream).bind(dev)
+            measure_sweeps(ccd, c, args.steps, args.warmup, [0] * 10, fake, TRAFFIC_C2)
+            c.close()
+        elif args.only == "c3":
+            sweep_rate_c3(ccd, stream.cuda_stream, args.steps, args.warmup, fake)
+        else:
+            snm_rate(ccd, stream.cuda_stream, args.steps, args.warmup)
+        torch.cuda.synchronize()
+        print(f"bench.py --only {args.only}: done", flush=True)
+        return
     ctx = ccd.Context([ccd.problem(N, NMAX2, r) for r in DENSITIES], stream=stream.cuda_stream)
     ctx.bind(dev)
     info = ctx.info(0)

@@ -30,3 +30,12 @@ def test_kernel_symbols():
     assert bench.kernel_symbol("ring64", t) == "void k_ringp<0, 64, 8>"
     t[7] = 1
     assert bench.kernel_symbol("ring48", t) == "void k_ringp<0, 48, 3>"
+
+
+def test_traffic_records_match_the_current_source():
+    """The committed counter records are keyed by workload and kernel family
+    and hold for the current kernel source (else bench.py reports null)."""
+    t = bench.measured_traffic("ring64", bench.TRAFFIC_C2)
+    assert t is not None and 50e6 < t < 500e6
+    assert bench.measured_traffic("ladder", bench.TRAFFIC_C3) is not None
+    assert bench.measured_traffic("ring64", "no such workload") is None
