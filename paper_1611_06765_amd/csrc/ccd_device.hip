@@ -19,10 +19,12 @@
 //   k_update  every amplitude: <ab||ij> + ladder sums + ring slots + one-body
 //             terms, t_new = R / eps_ij^ab, linear mixing, energy partial sums
 //   k_energy  deterministic per-problem energy and convergence flag
-// Problems with the same (N, nmax2, twist) share the integer tables; every work
-// item serves all problems of its group, so index arithmetic is done once for
-// all densities.  Reductions are fixed-order trees (no floating-point atomics):
-// energies are bit-identical from run to run.
+// Problems with the same (N, nmax2, twist) form a group that shares the integer
+// tables (states, pair lists, position maps, work lists); the sweep kernels'
+// work items are (item, problem) pairs over them, and the work lists are cut
+// per XCD by problem so each XCD's L2 sees about one problem's amplitudes.
+// Reductions are fixed-order trees (no floating-point atomics): energies are
+// bit-identical from run to run.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
