@@ -136,20 +136,20 @@ def ring_class_flops(ccd, ctx, p=0):
     return out
 
 
-def kernel_symbol(family, tuning):
-    """The kernel a family's single launch runs in the FP64 sweep, as rocprofv3
+def kernel_symbol(family, tuning, precision=0):
+    """The kernel a family's single launch runs in the sweep, as rocprofv3
     names it (the ring variant follows the tuned waves per block)."""
     if family == "ladder":
-        return "k_ladder64"
+        return "k_ladder64" if precision == 0 else "void k_ladder<%d>" % precision
     if family == "direct":
-        return "void k_direct<0>"
+        return "void k_direct<%d>" % precision
     n16 = int(family[4:])
     k = (n16 - 32) // 16
     nwa, nwb = {32: (4, 2), 48: (9, 3), 64: (16, 8), 80: (16, 9)}[n16]
-    return "void k_ringp<0, %d, %d>" % (n16, nwb if tuning[6 + k] else nwa)
+    return "void k_ringp<%d, %d, %d>" % (precision, n16, nwb if tuning[6 + k] else nwa)
 
 
-def measure_sweeps(ccd, ctx, steps, warmup, tuning, ceilings, workload):
+def measure_sweeps(ccd, ctx, steps, warmup, tuning, ceilings, workload, precision=0):
     """Time `steps` FP64 sweeps of every problem of ctx (inputs resident), then
     the same sweeps again with the library's per-kernel HIP events on its own
     stream; per-family times, the useful FP64 flops of each contraction family
@@ -157,18 +157,18 @@ def measure_sweeps(ccd, ctx, steps, warmup, tuning, ceilings, workload):
     import torch
     info = ctx.info(0)
     nsolve = ctx.n
-    ctx.iterate(mixing=MIXING, tol=0.0, max_iter=max(1, warmup))
+    ctx.iterate(mixing=MIXING, tol=0.0, max_iter=max(1, warmup), precision=precision)
     ctx.set_tuning(tuning)
-    ctx.iterate(mixing=MIXING, tol=0.0, max_iter=2)
+    ctx.iterate(mixing=MIXING, tol=0.0, max_iter=2, precision=precision)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ctx.iterate(mixing=MIXING, tol=0.0, max_iter=steps)
+    ctx.iterate(mixing=MIXING, tol=0.0, max_iter=steps, precision=precision)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     ctx.set_timing(True)
     ctx.kernel_times(reset=True)
     t1 = time.perf_counter()
-    ctx.iterate(mixing=MIXING, tol=0.0, max_iter=steps)
+    ctx.iterate(mixing=MIXING, tol=0.0, max_iter=steps, precision=precision)
     torch.cuda.synchronize()
     el_ev = time.perf_counter() - t1
     kt = ctx.kernel_times(reset=True)
@@ -196,28 +196,37 @@ def measure_sweeps(ccd, ctx, steps, warmup, tuning, ceilings, workload):
                   for k in fam_ms if fam_ms[k] > 0 and k != "ring_small"}
     dom = max(per_launch, key=lambda k: per_launch[k])
     achieved = fam_flops[dom] / (per_launch[dom] * 1e-3) / 1e12
-    roof = {"kernel": kernel_symbol(dom, tuning), "bound": "mfma",
-            "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP64_TFLOPS, "traffic": measured_traffic(dom, workload),
+    # the contraction precision's published dense peak: FP64 (the direct
+    # product and the one-body terms stay FP64 in every mode), FP32 or BF16
+    peak = PEAK_FP64_TFLOPS if precision == 0 or dom == "direct" else {1: 157.3, 2: 2500.0}[precision]
+    roof = {"kernel": kernel_symbol(dom, tuning, precision), "bound": "mfma",
+            "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+            "frac": achieved / peak, "traffic": measured_traffic(dom, workload) if workload else None,
             "family": dom, "ms_per_launch": per_launch[dom], "flops_per_launch": fam_flops[dom]}
-    # the same rate against what this part's FP64 matrix cores reach in a
-    # resident loop of the instruction the kernel uses (context, not the peak)
-    meas = ceilings["fp64_mfma_4x4x4_tflops"] if dom == "ladder" else ceilings["fp64_mfma_16x16x4_tflops"]
+    # the same rate against what this part's matrix cores reach in a resident
+    # loop of the instruction the kernel uses (context, not the peak)
+    if precision == 0 or dom == "direct":
+        meas = ceilings["fp64_mfma_4x4x4_tflops"] if dom == "ladder" else ceilings["fp64_mfma_16x16x4_tflops"]
+    else:
+        meas = ceilings.get("fp32_mfma_16x16x4_tflops" if precision == 1 else "bf16_mfma_16x16x32_tflops", 1.0)
     roof["measured_ceiling"] = meas
     roof["frac_of_measured_ceiling"] = achieved / meas
     return {"elapsed_s": el, "ms_per_step": el * 1e3 / steps, "ms_per_step_with_events": el_ev * 1e3 / steps,
             "kernels": kernels, "roofline": roof}
 
 
-def sweep_rate_c3(ccd, stream, steps, warmup, ceilings):
-    """FP64 sweeps of one solve at N=66, n^2<=36 (1850 states), rho=0.16, with
-    its per-kernel times and the roofline of its longest launch."""
+def sweep_rate_c3(ccd, stream, steps, warmup, ceilings, precision=0):
+    """Sweeps of one solve at N=66, n^2<=36 (1850 states), rho=0.16 (FP64, or
+    the given contraction precision), with its per-kernel times and the
+    roofline of its longest launch (against the FP64 peak)."""
     c = ccd.Context([ccd.problem(66, 36, 0.16)], stream=stream).bind()
     info = c.info(0)
-    m = measure_sweeps(ccd, c, steps, warmup, [0] * 10, ceilings, TRAFFIC_C3)
+    m = measure_sweeps(ccd, c, steps, warmup, [0] * 10, ceilings, TRAFFIC_C3 if precision == 0 else None,
+                       precision)
     c.close()
     fl = info["flops_pp"] + info["flops_hh"] + info["flops_ring"]
-    return {"workload": "PNM N=66, n^2<=36 (1850 states), rho=0.16, FP64, mixing 0.5, one solve",
+    return {"workload": "PNM N=66, n^2<=36 (1850 states), rho=0.16, %s, mixing 0.5, one solve"
+                        % {0: "FP64", 1: "FP32 contractions", 2: "BF16 contractions"}[precision],
             "ccd_iterations_per_s": 1e3 / m["ms_per_step"], "ms_per_sweep": m["ms_per_step"],
             "tflops": fl / (m["ms_per_step"] * 1e-3) / 1e12,
             "context_tflops_ordered_pair_form": info["flops_ordered"] / (m["ms_per_step"] * 1e-3) / 1e12,
@@ -492,16 +501,22 @@ def form_learned_c5(ccd, stream, epochs=24, batch=16384, lr=2e-3):
 
         t_ws = [0.0]
 
+        e_start = []
+
         def run():
             used = None
             if name == "learned_start":
                 used, t_ws[0] = _timed(lambda: c.warm_start(params, ccd.CCD_PREC_BF16))
+            e_start.extend(c.energy(p)[2] for p in range(len(specs)))
             return used, c.iterate(mixing=MIXING, tol=0.0, tol_rel=CONV_REL, stop_rule=STOP_RULE, max_iter=3000,
                                    check_every=8, graph=GRAPH)
         (used, r), el = _timed(run)
         e = [c.energy(p)[2] for p in range(len(specs))]
         out[name] = {"wall_s": el, "sweeps": [int(x) for x in r["sweeps"]], "sweeps_total": int(r["sweeps"].sum()),
-                     "status": int(r["status"]), "max_rel_err_vs_oracle": _err_vs_oracle(e, specs, e_orc)}
+                     "status": int(r["status"]), "max_rel_err_vs_oracle": _err_vs_oracle(e, specs, e_orc),
+                     # the starting correlation energy's relative error against the oracle's converged one
+                     "start_rel_err_vs_oracle": ([_rel(a, e_orc[k]) for a, k in zip(e_start, specs)]
+                                                 if all(k in e_orc for k in specs) else None)}
         if used is not None:
             out[name]["network_kept"] = int(used.sum())
             out[name]["warm_start_s"] = t_ws[0]
@@ -543,7 +558,7 @@ def main():
                     help="skip the mixed / batched / learned wall-time comparisons")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
-    ap.add_argument("--only", choices=["c2", "c3", "snm"], default=None,
+    ap.add_argument("--only", choices=["c2", "c3", "c3bf16", "snm"], default=None,
                     help="profiling runs: only this sweep measurement (no JSON line)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -573,6 +588,8 @@ def main():
             c.close()
         elif args.only == "c3":
             sweep_rate_c3(ccd, stream.cuda_stream, args.steps, args.warmup, fake)
+        elif args.only == "c3bf16":
+            sweep_rate_c3(ccd, stream.cuda_stream, args.steps, args.warmup, fake, ccd.CCD_PREC_BF16)
         else:
             snm_rate(ccd, stream.cuda_stream, args.steps, args.warmup)
         torch.cuda.synchronize()
@@ -634,6 +651,7 @@ def main():
     }
     ctx.close()
     out["c3_fp64"] = sweep_rate_c3(ccd, stream.cuda_stream, args.steps, args.warmup, ceilings)
+    out["c3_bf16"] = sweep_rate_c3(ccd, stream.cuda_stream, args.steps, args.warmup, ceilings, ccd.CCD_PREC_BF16)
     out["snm"] = snm_rate(ccd, stream.cuda_stream, min(args.steps, 40), min(args.warmup, 5))
     if not args.no_forms:
         out["convergence_c2"] = convergence_c2(ccd, stream.cuda_stream)

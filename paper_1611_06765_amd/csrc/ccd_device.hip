@@ -345,19 +345,23 @@ __global__ void __launch_bounds__(256) k_features(DevPtrs d, int cur, int gi, in
 // of four amplitudes go through the network (W2 staged once per block) and
 // the decoded amplitudes replace the current ones
 template <bool BF16>
-__global__ void __launch_bounds__(256, 3) k_warm(DevPtrs d, int cur, const float* __restrict__ P, int n_items) {
+__global__ void __launch_bounds__(256, 3) k_warm(DevPtrs d, int cur, const float* __restrict__ P, int n_items,
+                                                int max_g) {
     extern __shared__ __attribute__((aligned(16))) char lds[];
     const mlp::Lds s = mlp::lds_carve<BF16>(lds);
     mlp::lds_load<BF16>(P, s, threadIdx.x, 256);
     __syncthreads();
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, kq = lane >> 4;
-    for (int bi = blockIdx.x; bi < n_items; bi += gridDim.x) {
+    // work units (elementwise item, problem of its group), max_g problem slots per item
+    for (int wi = blockIdx.x; wi < n_items * max_g; wi += gridDim.x) {
+        const int bi = wi / max_g, g = wi - bi * max_g;
         const Item it = d.it_elem[bi];
         const DevChan c = d.chans[it.chan];
         const DevGroup G = d.groups[c.group];
+        if (g >= G.G) continue;
         const int nel = c.nhh * c.npp;
         const int lim = min(nel, it.start + kElemChunk);
-        for (int g = 0; g < G.G; g++) {
+        {
             for (int t = w; 4 * t + it.start < lim; t += 4) {
                 const int e = it.start + 4 * t + ((lane & 15) >> 2);
                 float f[mlp::kPack];
@@ -2854,11 +2858,13 @@ ccd_status ccd_warm_start(ccd_ctx* c, const float* params, int32_t precision, in
     }
     DevPtrs d = make_ptrs(c);
     const int n = (int)c->it_elem.size();
-    const int grid = std::min(n, 2048);
+    int max_g = 1;
+    for (const DevGroup& D : c->dgroups) max_g = std::max(max_g, D.G);
+    const int grid = (int)std::min<int64_t>((int64_t)n * max_g, 16384);
     if (precision == CCD_PREC_BF16)
-        LAUNCH(F_INIT, k_warm<true>, grid, 256, mlp::lds_bytes<true>(), d, c->cur, params, n);
+        LAUNCH(F_INIT, k_warm<true>, grid, 256, mlp::lds_bytes<true>(), d, c->cur, params, n, max_g);
     else
-        LAUNCH(F_INIT, k_warm<false>, grid, 256, mlp::lds_bytes<false>(), d, c->cur, params, n);
+        LAUNCH(F_INIT, k_warm<false>, grid, 256, mlp::lds_bytes<false>(), d, c->cur, params, n, max_g);
     ccd_status s = refresh_energy(c);
     if (s != CCD_OK) return s;
     std::vector<double> e(P);
