@@ -689,42 +689,51 @@ __device__ __forceinline__ void pair_stage(const DevPtrs& d, int memQ, int memP,
     for (int e = t0; e < nlut; e += stride) lutS[e] = d.lut[lut_off + e];
 }
 
-// A = gathered T~_Q (signed), B = Vbar, zero padded; gathers issued 8 at a time.
-// With TR set (BF16), A, At = A^T and Bt = B^T are written instead of A and B.
-template <typename E, int n16, int lda, int stride, bool TR>
-__device__ __forceinline__ void pair_fill(const PairCtx& r, const int32_t* qs, const int32_t* ps,
+// This thread's position-map entries of A, entries t0, t0 + stride, ...
+// (issued before the staging barrier, so that the amplitude gathers can start
+// right after it)
+template <int n16, int stride, int J>
+__device__ __forceinline__ void pair_maps(const PairCtx& r, int t0, int32_t* m) {
+    constexpr int tot = n16 * n16;
+#pragma unroll
+    for (int j = 0; j < J; j++) {
+        const int e = t0 + j * stride, u = e / n16, x = e - u * n16;
+        m[j] = (e < tot && u < r.nq && x < r.np) ? r.map[u * r.np + x] : -1;
+    }
+}
+
+// A = gathered T~_Q (signed), B = Vbar, zero padded.  The gathers are issued
+// first and B is generated while they are in flight.  With TR set (BF16), A,
+// At = A^T and Bt = B^T are written instead of A and B.
+template <typename E, int n16, int lda, int stride, int J, bool TR>
+__device__ __forceinline__ void pair_fill(const PairCtx& r, const int32_t* m, const int32_t* qs, const int32_t* ps,
                                           const double* lutS, double wq, E* A, E* B, E* At, E* Bt, int t0,
                                           bool qring) {
     const int nq = r.nq, np = r.np;
     constexpr int tot = n16 * n16;
-    for (int base = t0; base < tot; base += 8 * stride) {
-        int m[8];
-        double tv[8];
+    double tv[J];
 #pragma unroll
-        for (int j = 0; j < 8; j++) {
-            int e = base + j * stride;
-            int u = e / n16, x = e - u * n16;
-            m[j] = (e < tot && u < nq && x < np) ? r.map[u * np + x] : -1;
+    for (int j = 0; j < J; j++) tv[j] = m[j] >= 0 ? r.t[m[j] >> 3] : 0.0;
+#pragma unroll
+    for (int j = 0; j < J; j++) {
+        const int e = t0 + j * stride;
+        if (e < tot) {
+            const int u = e / n16, x = e - u * n16;
+            double b = 0.0;
+            if (qring && u < np && x < nq)  // <kl||cd>: (c,k) = P member u, (d,l) = Q member x
+                b = vas_q(lutS, wq, ps[2 * u + 1], qs[2 * x + 1], ps[2 * u], qs[2 * x]);
+            if constexpr (TR) Bt[x * lda + u] = (E)b;
+            else B[u * lda + x] = (E)b;
         }
+    }
 #pragma unroll
-        for (int j = 0; j < 8; j++) tv[j] = m[j] >= 0 ? r.t[m[j] >> 3] : 0.0;
-#pragma unroll
-        for (int j = 0; j < 8; j++) {
-            int e = base + j * stride;
-            if (e < tot) {
-                int u = e / n16, x = e - u * n16;
-                double b = 0.0;
-                if (qring && u < np && x < nq)  // <kl||cd>: (c,k) = P member u, (d,l) = Q member x
-                    b = vas_q(lutS, wq, ps[2 * u + 1], qs[2 * x + 1], ps[2 * u], qs[2 * x]);
-                const E av = (E)((m[j] & 1) ? -tv[j] : tv[j]), bv = (E)b;
-                A[u * lda + x] = av;
-                if constexpr (TR) {
-                    At[x * lda + u] = av;
-                    Bt[x * lda + u] = bv;
-                } else {
-                    B[u * lda + x] = bv;
-                }
-            }
+    for (int j = 0; j < J; j++) {
+        const int e = t0 + j * stride;
+        if (e < tot) {
+            const int u = e / n16, x = e - u * n16;
+            const E av = (E)((m[j] & 1) ? -tv[j] : tv[j]);
+            A[u * lda + x] = av;
+            if constexpr (TR) At[x * lda + u] = av;
         }
     }
 }
@@ -830,6 +839,11 @@ __device__ __forceinline__ void pair_body(const DevPtrs& d, const Item it, int c
     E* At = B;                // BF16 only (same storage as B)
     E* Bt = At + rows * lda;  // BF16 only
     const bool qring = (mask & CCD_T_QRING) != 0, ring = (mask & CCD_T_RING) != 0;
+    constexpr int J = (n16 * n16 + 64 * NW - 1) / (64 * NW);  // entries of A per thread
+    int32_t mp[J];
+#pragma unroll
+    for (int j = 0; j < J; j++) mp[j] = -1;
+    if (live) pair_maps<n16, 64 * NW, J>(r, tid, mp);
     if (live) {
         pair_stage(d, memQ, memP, lo, nlut, r.nq, r.np, qs, ps, lutS, tid, 64 * NW);
         if constexpr (P == P_BF16) {
@@ -841,7 +855,7 @@ __device__ __forceinline__ void pair_body(const DevPtrs& d, const Item it, int c
     // W(|Q|^2)/2, the first table entry of every element of the pair (member 0
     // of Q: hole qs[1], particle qs[0])
     const double wq = live ? lutS[dist2(qs[1], qs[0])] : 0.0;
-    if (live) pair_fill<E, n16, lda, 64 * NW, P == P_BF16>(r, qs, ps, lutS, wq, A, B, At, Bt, tid, qring);
+    if (live) pair_fill<E, n16, lda, 64 * NW, J, P == P_BF16>(r, mp, qs, ps, lutS, wq, A, B, At, Bt, tid, qring);
     int32_t zsl[TPW][4];
 #pragma unroll
     for (int k = 0; k < TPW; k++) {
