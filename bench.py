@@ -64,11 +64,20 @@ KERNEL_SRC = os.path.join(ROOT, "paper_1611_06765_amd", "csrc", "ccd_device.hip"
 
 
 def source_digest(path=KERNEL_SRC):
-    """sha256 of a kernel source with its comments and blank space removed, so
-    that a comment-only edit keeps the counters valid and any code edit does not."""
+    """sha256 of the sweep's device code with its comments and blank space
+    removed, so that a comment-only edit keeps the counters valid and any code
+    edit does not.  The set-up kernels (MBPT2 start, network warm start,
+    features), which do not run in a sweep, and the host code after the device
+    code are left out."""
     import hashlib
     import re
     src = open(path).read()
+    a, b = src.find("\n// set-up kernels\n"), src.find("\n// sweep kernels\n")
+    if 0 <= a < b:
+        src = src[:a] + src[b:]
+    h = src.find("\n// context\n")
+    if h >= 0:
+        src = src[:h]
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     src = re.sub(r"//[^\n]*", "", src)
     src = re.sub(r"\s+", " ", src).strip()
@@ -475,7 +484,7 @@ def form_twist_averaged(ccd, stream, n_mesh=5, rho=0.16):
                 "infinite_matter": {"T": t_inf, "HF_potential": hf_inf}}}
 
 
-def form_learned_c5(ccd, stream, epochs=24, batch=16384, lr=2e-3):
+def form_learned_c5(ccd, stream, epochs=72, batch=16384, lr=2e-3):
     """Train the warm-start network on the method's converged amplitudes
     (N=66, n^2<=20, 24 seeded densities), then solve 16 held-out densities at
     n^2<=36 from the MBPT2 start and from the network (BF16 inference)."""

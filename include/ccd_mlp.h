@@ -17,8 +17,8 @@
  * <ab|v|ij> (sec. "Two-body interaction"), q' = (k_b - k_a - k_i + k_j) / 2
  * that of the exchanged element, momenta in fm^-1, energies in MeV.
  *
- * Network: g(x) = W3 silu(W2 silu(W1 x + b1) + b2) + b3, 7 inputs, two hidden
- * layers of width 128, silu(z) = z / (1 + exp(-z)).  Prediction, antisymmetric
+ * Network: g(x) = W3 relu(W2 relu(W1 x + b1) + b2) + b3, 7 inputs, two hidden
+ * layers of width 128, relu(z) = max(z, 0).  Prediction, antisymmetric
  * under a <-> b and under i <-> j like t_ij^ab itself:
  *     y = ( g(x) - g(x_ab) - g(x_ij) + g(x_abij) ) / 4,
  * where a swap exchanges the two energies of the pair, takes |q| to |q'| (one

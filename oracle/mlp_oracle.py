@@ -21,9 +21,10 @@ momentum transfer q = (k_a - k_b - k_i + k_j) / 2 of <ab|v|ij>, k = 2 pi n / L):
 with q' = (k_b - k_a - k_i + k_j) / 2 the transfer of the exchanged element,
 energies in MeV and momenta in fm^-1.
 
-Network g: three linear layers, 7 -> 128 -> 128 -> 1, SiLU after the first
-two (silu(z) = z / (1 + exp(-z))).  The prediction is antisymmetrised over
-a <-> b and i <-> j, which swaps the corresponding energies, maps q to q'
+Network g: three linear layers, 7 -> 128 -> 128 -> 1, ReLU after the first
+two (relu(z) = max(z, 0); its derivative is taken as 0 at z = 0).  The
+prediction is antisymmetrised over a <-> b and i <-> j, which swaps the
+corresponding energies, maps q to q'
 (either single swap) or to -q (both) and flips the sign of v:
     y = ( g(x) - g(x_ab) - g(x_ij) + g(x_abij) ) / 4,
 so y (and t) change sign under either swap, as t_ij^ab must.
@@ -105,21 +106,20 @@ def variants(F):
     return X.reshape(-1, N_IN)
 
 
-def silu(z):
-    return z / (1.0 + np.exp(-z))
+def relu(z):
+    return np.maximum(z, 0.0)
 
 
-def dsilu(z):
-    sg = 1.0 / (1.0 + np.exp(-z))
-    return sg * (1.0 + z * (1.0 - sg))
+def drelu(z):
+    return (z > 0.0).astype(np.float64)
 
 
 def g_forward(P, X):
     """Raw network output per input row, with the intermediates."""
     z1 = X @ P["W1"].T + P["b1"]
-    h1 = silu(z1)
+    h1 = relu(z1)
     z2 = h1 @ P["W2"].T + P["b2"]
-    h2 = silu(z2)
+    h2 = relu(z2)
     g = h2 @ P["W3"] + P["b3"]
     return g, (X, z1, h1, z2, h2)
 
@@ -138,10 +138,10 @@ def loss_and_grad(P, F, Y):
     L = 0.5 * np.mean(res ** 2)
     dg = (res[:, None] * SIGNS[None, :] / (4.0 * M)).reshape(-1)
     G = {"W3": h2.T @ dg, "b3": np.sum(dg)}
-    dz2 = np.outer(dg, P["W3"]) * dsilu(z2)
+    dz2 = np.outer(dg, P["W3"]) * drelu(z2)
     G["W2"] = dz2.T @ h1
     G["b2"] = dz2.sum(0)
-    dz1 = (dz2 @ P["W2"]) * dsilu(z1)
+    dz1 = (dz2 @ P["W2"]) * drelu(z1)
     G["W1"] = dz1.T @ X
     G["b1"] = dz1.sum(0)
     return L, G

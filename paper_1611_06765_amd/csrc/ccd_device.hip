@@ -341,17 +341,27 @@ __global__ void __launch_bounds__(256) k_features(DevPtrs d, int cur, int gi, in
     }
 }
 
-// warm start of every problem: per (elementwise item, problem) the wave tiles
-// of four amplitudes go through the network (W2 staged once per block) and
-// the decoded amplitudes replace the current ones
+// warm start of every problem: per (elementwise item, problem), chunks of 256
+// amplitudes: every thread gathers the features of one amplitude into LDS
+// (the table loads of a whole chunk in flight at once), then the wave tiles of
+// four amplitudes go through the network (W2 staged once per block) and the
+// decoded amplitudes replace the current ones
+constexpr int kWarmChunk = 256;  // amplitudes per feature chunk (one per thread)
+template <bool BF16> __host__ __device__ constexpr size_t warm_lds() {
+    return mlp::lds_bytes<BF16>() + (size_t)kWarmChunk * (mlp::kPack * 4 + 16);
+}
 template <bool BF16>
 __global__ void __launch_bounds__(256, 3) k_warm(DevPtrs d, int cur, const float* __restrict__ P, int n_items,
                                                 int max_g) {
     extern __shared__ __attribute__((aligned(16))) char lds[];
     const mlp::Lds s = mlp::lds_carve<BF16>(lds);
+    float* Fs = (float*)(lds + mlp::lds_bytes<BF16>());    // [kWarmChunk][kPack] features
+    double* Ds = (double*)(Fs + kWarmChunk * mlp::kPack);  // [kWarmChunk] eps_ij^ab
+    double* Vs = Ds + kWarmChunk;                          // [kWarmChunk] <ab||ij>
     mlp::lds_load<BF16>(P, s, threadIdx.x, 256);
-    __syncthreads();
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, kq = lane >> 4;
+    mlp::W1Reg w1{};
+    if constexpr (BF16) w1 = mlp::w1_regs(P, lane);
     // work units (elementwise item, problem of its group), max_g problem slots per item
     for (int wi = blockIdx.x; wi < n_items * max_g; wi += gridDim.x) {
         const int bi = wi / max_g, g = wi - bi * max_g;
@@ -361,19 +371,32 @@ __global__ void __launch_bounds__(256, 3) k_warm(DevPtrs d, int cur, const float
         if (g >= G.G) continue;
         const int nel = c.nhh * c.npp;
         const int lim = min(nel, it.start + kElemChunk);
-        {
-            for (int t = w; 4 * t + it.start < lim; t += 4) {
-                const int e = it.start + 4 * t + ((lane & 15) >> 2);
+        const double sc = d.pscale[3 * (G.p0 + g) + 2];
+        double* tout = d.t[cur] + G.t_base + g * G.n_amp + c.t_off;
+        for (int c0 = it.start; c0 < lim; c0 += kWarmChunk) {
+            const int n = min(kWarmChunk, lim - c0);
+            __syncthreads();  // the previous chunk's reads of LDS are done
+            {
                 float f[mlp::kPack];
-                double D = 1.0, v = 0.0, sc = 1.0;
-                if (e < lim) amp_features(d, c, G, g, e, f, D, v, sc);
-                else
+                double D = 1.0, v = 0.0, scx;
 #pragma unroll
-                    for (int q = 0; q < mlp::kPack; q++) f[q] = 0.f;
-                const float y = mlp::tile_predict<BF16>(f, s, lane);
+                for (int q = 0; q < mlp::kPack; q++) f[q] = 0.f;
+                if ((int)threadIdx.x < n) amp_features(d, c, G, g, c0 + threadIdx.x, f, D, v, scx);
+#pragma unroll
+                for (int q = 0; q < mlp::kPack; q++) Fs[threadIdx.x * mlp::kPack + q] = f[q];
+                Ds[threadIdx.x] = D;
+                Vs[threadIdx.x] = v;
+            }
+            __syncthreads();
+            // wave w: amplitudes 64 w .. 64 w + 63 of the chunk, four per tile
+            for (int a0 = 64 * w; a0 < min(n, 64 * w + 64); a0 += 4) {
+                const float4* fr = (const float4*)&Fs[(a0 + ((lane & 15) >> 2)) * mlp::kPack];
+                const float4 f0 = fr[0], f1 = fr[1];
+                const float f[mlp::kPack] = {f0.x, f0.y, f0.z, f0.w, f1.x, f1.y, f1.z, f1.w};
+                const float y = mlp::tile_predict<BF16>(f, s, lane, w1);
                 // lane 20 kq: A-operand row 4 kq, i.e. amplitude kq of the tile, variant 0
-                if ((lane & 15) == 4 * kq && e < lim)
-                    d.t[cur][G.t_base + g * G.n_amp + c.t_off + e] = (v + (double)y / sc) / D;
+                const int o = a0 + kq;
+                if ((lane & 15) == 4 * kq && o < n) tout[c0 + o] = (Vs[o] + (double)y / sc) / Ds[o];
             }
         }
     }
@@ -2867,7 +2890,9 @@ ccd_status ccd_warm_start(ccd_ctx* c, const float* params, int32_t precision, in
     static bool attr = false;
     if (!attr) {
         HIP_TRY(hipFuncSetAttribute((const void*)k_warm<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)mlp::lds_bytes<false>()));
+                                    (int)warm_lds<false>()));
+        HIP_TRY(hipFuncSetAttribute((const void*)k_warm<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)warm_lds<true>()));
         attr = true;
     }
     DevPtrs d = make_ptrs(c);
@@ -2876,9 +2901,9 @@ ccd_status ccd_warm_start(ccd_ctx* c, const float* params, int32_t precision, in
     for (const DevGroup& D : c->dgroups) max_g = std::max(max_g, D.G);
     const int grid = (int)std::min<int64_t>((int64_t)n * max_g, 16384);
     if (precision == CCD_PREC_BF16)
-        LAUNCH(F_INIT, k_warm<true>, grid, 256, mlp::lds_bytes<true>(), d, c->cur, params, n, max_g);
+        LAUNCH(F_INIT, k_warm<true>, grid, 256, warm_lds<true>(), d, c->cur, params, n, max_g);
     else
-        LAUNCH(F_INIT, k_warm<false>, grid, 256, mlp::lds_bytes<false>(), d, c->cur, params, n, max_g);
+        LAUNCH(F_INIT, k_warm<false>, grid, 256, warm_lds<false>(), d, c->cur, params, n, max_g);
     ccd_status s = refresh_energy(c);
     if (s != CCD_OK) return s;
     std::vector<double> e(P);

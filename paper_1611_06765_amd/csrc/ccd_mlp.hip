@@ -36,13 +36,15 @@ __global__ void __launch_bounds__(256) k_mlp_fwd(const float* __restrict__ P, co
     lds_load<BF16>(P, s, threadIdx.x, 256);
     __syncthreads();
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    W1Reg w1{};
+    if constexpr (BF16) w1 = w1_regs(P, lane);
     const int64_t ntile = (n + 3) / 4;
     for (int64_t t = (int64_t)blockIdx.x * 4 + w; t < ntile; t += (int64_t)gridDim.x * 4) {
         const int64_t e = 4 * t + ((lane & 15) >> 2);
         float f[kPack];
 #pragma unroll
         for (int q = 0; q < kPack; q++) f[q] = e < n ? feat[e * kPack + q] : 0.0f;
-        const float yp = tile_predict<BF16>(f, s, lane);
+        const float yp = tile_predict<BF16>(f, s, lane, w1);
         const int64_t eo = 4 * t + (lane >> 4);
         if ((lane & 15) == 0 && eo < n) y[eo] = yp;
     }
@@ -53,13 +55,13 @@ __global__ void __launch_bounds__(256) k_mlp_fwd(const float* __restrict__ P, co
 // amplitudes x 4 swap variants).  Wave w = (rt, ch): row tile rt = w / 2
 // (amplitudes 4 rt .. 4 rt + 3 of the chunk) and column half ch = w % 2 of the
 // 128 x 128 layer.  Per chunk:
-//   h1 = silu(W1 x + b1)                       (VALU, into LDS)
-//   z2 = h1 W2^T + b2, g = W3 silu(z2)         (MFMA, W2 in LDS)
+//   h1 = relu(W1 x + b1)                      (VALU, into LDS)
+//   z2 = h1 W2^T + b2, g = W3 relu(z2)        (MFMA, W2 in LDS)
 //   y = sum_k sign_k g_k / 4, dL/dg_k = sign_k (y - y*) / (4 M)
-//   dz2 = dg W3 silu'(z2)                      (into LDS)
+//   dz2 = dg W3 relu'(z2)                     (into LDS)
 //   dW2 += dz2^T h1                            (MFMA, 16 tiles per wave held in registers)
-//   dh1 = dz2 W2, dz1 = dh1 silu'(z1)          (MFMA; z1 recomputed)
-//   dW1 += dz1^T x, db1 += sum dz1, db2 += sum dz2, dW3 += dg^T silu(z2)
+//   dh1 = dz2 W2, dz1 = dh1 relu'(z1)         (MFMA; z1 recomputed)
+//   dW1 += dz1^T x, db1 += sum dz1, db2 += sum dz2, dW3 += dg^T relu(z2)
 // The block's sums go to its row of the partial-gradient buffer.
 constexpr int kEPB = 64;   // amplitudes per block
 constexpr int kLdH = kW + 4;
@@ -126,7 +128,7 @@ __global__ void __launch_bounds__(256) k_mlp_grad(const float* __restrict__ P, c
             for (int r = tid >> 7; r < 32; r += 2) {
                 float x[7];
                 variant_inputs(&Fs[(r >> 2) * kPack], r & 3, x);
-                H1[r * kLdH + c] = silu(layer1(s.W1, s.b1, c, x));
+                H1[r * kLdH + c] = act(layer1(s.W1, s.b1, c, x));
             }
         }
         __syncthreads();
@@ -148,7 +150,7 @@ __global__ void __launch_bounds__(256) k_mlp_grad(const float* __restrict__ P, c
 #pragma unroll
             for (int i = 0; i < 4; i++) {
                 z2[j][i] += b2;
-                gp[i] += silu(z2[j][i]) * w3;
+                gp[i] += act(z2[j][i]) * w3;
             }
         }
 #pragma unroll
@@ -177,8 +179,8 @@ __global__ void __launch_bounds__(256) k_mlp_grad(const float* __restrict__ P, c
             const float w3 = s.W3[col];
 #pragma unroll
             for (int i = 0; i < 4; i++) {
-                const float dz = dg[i] * w3 * dsilu(z2[j][i]);
-                aW3[j] += dg[i] * silu(z2[j][i]);
+                const float dz = dg[i] * w3 * dact(z2[j][i]);
+                aW3[j] += dg[i] * act(z2[j][i]);
                 aB2[j] += dz;
                 DZ2[(rt * 16 + 4 * kq + i) * kLdH + col] = dz;
             }
@@ -207,7 +209,7 @@ __global__ void __launch_bounds__(256) k_mlp_grad(const float* __restrict__ P, c
             for (int j = 0; j < 4; j++)
                 dh[j] = mfma_f32(a, W2[(4 * st + kq) * kLd32 + (ch * 4 + j) * 16 + r16], dh[j]);
         }
-        // dz1 = dh1 silu'(z1), rows 4 el + i (variant i of amplitude el)
+        // dz1 = dh1 relu'(z1), rows 4 el + i (variant i of amplitude el)
         float xv[4][7];
 #pragma unroll
         for (int i = 0; i < 4; i++) variant_inputs(&Fs[el * kPack], i, xv[i]);
@@ -216,7 +218,7 @@ __global__ void __launch_bounds__(256) k_mlp_grad(const float* __restrict__ P, c
             const int c = (ch * 4 + j) * 16 + r16;
 #pragma unroll
             for (int i = 0; i < 4; i++) {
-                const float dz1 = dh[j][i] * dsilu(layer1(s.W1, s.b1, c, xv[i]));
+                const float dz1 = dh[j][i] * dact(layer1(s.W1, s.b1, c, xv[i]));
                 aB1[j] += dz1;
 #pragma unroll
                 for (int q = 0; q < 7; q++) aW1[j][q] += dz1 * xv[i][q];

@@ -1,14 +1,18 @@
 // Device code of the warm-start network (declared in include/ccd_mlp.h):
-// g(x) = W3 silu(W2 silu(W1 x + b1) + b2) + b3 on 7 inputs, width 128, and
+// g(x) = W3 relu(W2 relu(W1 x + b1) + b2) + b3 on 7 inputs, width 128, and
 // its antisymmetrised prediction y = (g(x) - g(x_ab) - g(x_ij) + g(x_abij))/4
 // over the swaps a <-> b and i <-> j of t_ij^ab.
 //
 // A wave evaluates 16 input rows at once: four amplitudes times their four
 // swap variants, row 4e + k.  The 128 x 128 layer runs on MFMA with W2 in LDS
-// (FP32 16x16x4, or BF16 16x16x32 with FP32 accumulation); the 7-input layer
-// is computed per lane straight into the A-operand layout, and the last layer
-// is a 16-lane reduction of the accumulator tiles, whose lane layout puts the
-// four variants of one amplitude in one lane group.
+// (FP32 16x16x4, or BF16 16x16x32 with FP32 accumulation).  In the FP32 form
+// the 7-input layer is computed per lane straight into the A-operand layout.
+// In the BF16 form it runs on FP32 MFMA too (W1 in registers, the output
+// transposed: units by rows), and W2 is stored with its K dimension permuted
+// so that each lane's accumulators are its A operand of the next layer
+// without any data movement.  The last layer is a 16-lane reduction of the
+// accumulator tiles, whose lane layout puts the four variants of one
+// amplitude in one lane group.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -44,13 +48,10 @@ __device__ __forceinline__ f4v mfma_bf16(bf8v a, bf8v b, f4v c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-// sigmoid through the hardware reciprocal (about 1 ulp); silu(z) = z sigmoid(z)
-__device__ __forceinline__ float sigm(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
-__device__ __forceinline__ float silu(float z) { return z * sigm(z); }
-__device__ __forceinline__ float dsilu(float z) {
-    const float s = sigm(z);
-    return s * (1.0f + z * (1.0f - s));
-}
+// the activation, relu(z) = max(z, 0), and its derivative (0 at z <= 0): one
+// full-rate VALU operation each
+__device__ __forceinline__ float act(float z) { return fmaxf(z, 0.0f); }
+__device__ __forceinline__ float dact(float z) { return z > 0.0f ? 1.0f : 0.0f; }
 
 // network inputs of swap variant k (0 identity, 1 a<->b, 2 i<->j, 3 both) from
 // the packed features (rho, |q|, |q'|, eps_i, eps_j, eps_a, eps_b, v)
@@ -116,16 +117,39 @@ __device__ __forceinline__ void lds_load(const float* __restrict__ P, const Lds&
     }
     for (int e = tid; e < kW * kW; e += nthreads) {
         const int n = e / kW, k = e - n * kW;
-        if constexpr (BF16) ((__bf16*)s.W2)[n * kLd16 + k] = (__bf16)P[OFF_W2 + e];
-        else ((float*)s.W2)[n * kLd32 + k] = P[OFF_W2 + e];
+        if constexpr (BF16) {
+            // stored column k = 32 st + 8 q + j holds unit 32 st + 16 (j / 4) + 4 q + j % 4
+            const int st = k >> 5, q = (k >> 3) & 3, j = k & 7;
+            const int u = 32 * st + 16 * (j >> 2) + 4 * q + (j & 3);
+            ((__bf16*)s.W2)[n * kLd16 + k] = (__bf16)P[OFF_W2 + n * kW + u];
+        } else {
+            ((float*)s.W2)[n * kLd32 + k] = P[OFF_W2 + e];
+        }
     }
+}
+
+// BF16 form: this lane's first-layer weights as the A operands of the FP32
+// MFMA of unit tile ct and input step ks: W1[16 ct + lane % 16][4 ks + lane / 16]
+struct W1Reg {
+    float w[8][2];
+};
+__device__ __forceinline__ W1Reg w1_regs(const float* __restrict__ P, int lane) {
+    W1Reg r;
+    const int row = lane & 15, kq = lane >> 4;
+#pragma unroll
+    for (int ct = 0; ct < 8; ct++) {
+        r.w[ct][0] = P[OFF_W1 + (16 * ct + row) * kPack + kq];
+        r.w[ct][1] = P[OFF_W1 + (16 * ct + row) * kPack + 4 + kq];  // column 7 is zero
+    }
+    return r;
 }
 
 // Prediction y of amplitude (lane >> 4) of a 16-row tile.  f: packed features
 // of the amplitude of this lane's A-operand row, i.e. amplitude (lane & 15) >> 2.
 // The result is valid in every lane of the 16-lane group.
+// w1: the lane's first-layer weights (BF16 form only; unused in the FP32 form).
 template <bool BF16>
-__device__ __forceinline__ float tile_predict(const float* f, const Lds& s, int lane) {
+__device__ __forceinline__ float tile_predict(const float* f, const Lds& s, int lane, const W1Reg& w1) {
     const int row = lane & 15, kq = lane >> 4;
     float x[7];
     variant_inputs(f, row & 3, x);
@@ -133,23 +157,39 @@ __device__ __forceinline__ float tile_predict(const float* f, const Lds& s, int 
 #pragma unroll
     for (int ct = 0; ct < 8; ct++) acc[ct] = f4v{0.f, 0.f, 0.f, 0.f};
     if constexpr (BF16) {
-        const __bf16* W2 = (const __bf16*)s.W2;
-#pragma unroll 1
-        for (int st = 0; st < 4; st++) {
-            bf8v a;
+        // layer 1, transposed: D[unit][row] = sum_k W1[unit][k] x_row[k]; the B
+        // operand of input step ks is this lane's input 4 ks + lane / 16 of its
+        // own row, and the lane receives units 16 ct + 4 (lane / 16) + i
+        const float xb0 = x[kq], xb1 = kq < 3 ? x[4 + kq] : 0.f;
+        bf8v a[4];
 #pragma unroll
-            for (int j = 0; j < 8; j++) a[j] = (__bf16)silu(layer1(s.W1, s.b1, 32 * st + 8 * kq + j, x));
+        for (int ct = 0; ct < 8; ct++) {
+            f4v z = f4v{0.f, 0.f, 0.f, 0.f};
+            z = mfma_f32(w1.w[ct][0], xb0, z);
+            z = mfma_f32(w1.w[ct][1], xb1, z);
+            const float4 bb = *(const float4*)&s.b1[16 * ct + 4 * kq];
+            // unit 16 ct + 4 kq + i is logical K index 8 kq + 4 (ct % 2) + i of step ct / 2
+            a[ct >> 1][4 * (ct & 1) + 0] = (__bf16)act(z[0] + bb.x);
+            a[ct >> 1][4 * (ct & 1) + 1] = (__bf16)act(z[1] + bb.y);
+            a[ct >> 1][4 * (ct & 1) + 2] = (__bf16)act(z[2] + bb.z);
+            a[ct >> 1][4 * (ct & 1) + 3] = (__bf16)act(z[3] + bb.w);
+        }
+        const __bf16* W2 = (const __bf16*)s.W2;
+#pragma unroll
+        for (int st = 0; st < 4; st++) {
 #pragma unroll
             for (int ct = 0; ct < 8; ct++) {
                 const bf8v b = *(const bf8v*)&W2[(ct * 16 + row) * kLd16 + 32 * st + 8 * kq];
-                acc[ct] = mfma_bf16(a, b, acc[ct]);
+                acc[ct] = mfma_bf16(a[st], b, acc[ct]);
             }
+            // keep the next step's W2 loads below this point (register pressure)
+            __builtin_amdgcn_sched_barrier(0);
         }
     } else {
         const float* W2 = (const float*)s.W2;
         for (int st = 0; st < 32; st++) {
             const int c = 4 * st + kq;
-            const float a = silu(layer1(s.W1, s.b1, c, x));
+            const float a = act(layer1(s.W1, s.b1, c, x));
 #pragma unroll
             for (int ct = 0; ct < 8; ct++) acc[ct] = mfma_f32(a, W2[(ct * 16 + row) * kLd32 + c], acc[ct]);
         }
@@ -161,7 +201,7 @@ __device__ __forceinline__ float tile_predict(const float* f, const Lds& s, int 
         const int col = ct * 16 + row;
         const float b2 = s.b2[col], w3 = s.W3[col];
 #pragma unroll
-        for (int i = 0; i < 4; i++) gp[i] += silu(acc[ct][i] + b2) * w3;
+        for (int i = 0; i < 4; i++) gp[i] += act(acc[ct][i] + b2) * w3;
     }
 #pragma unroll
     for (int i = 0; i < 4; i++) {

@@ -33,8 +33,8 @@ def _feats(m=23, seed=5):
 def _torch_loss(P, F, Y):
     T = {k: torch.tensor(np.asarray(v, dtype=np.float64), requires_grad=True) for k, v in P.items()}
     X = torch.tensor(M.variants(F))
-    h1 = torch.nn.functional.silu(X @ T["W1"].T + T["b1"])
-    h2 = torch.nn.functional.silu(h1 @ T["W2"].T + T["b2"])
+    h1 = torch.relu(X @ T["W1"].T + T["b1"])
+    h2 = torch.relu(h1 @ T["W2"].T + T["b2"])
     g = h2 @ T["W3"] + T["b3"]
     y = (g.reshape(-1, 4) * torch.tensor([1.0, -1.0, -1.0, 1.0])).sum(1) / 4
     L = 0.5 * ((y - torch.tensor(Y)) ** 2).mean()
