@@ -360,8 +360,6 @@ __global__ void __launch_bounds__(256, 3) k_warm(DevPtrs d, int cur, const float
     double* Vs = Ds + kWarmChunk;                          // [kWarmChunk] <ab||ij>
     mlp::lds_load<BF16>(P, s, threadIdx.x, 256);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, kq = lane >> 4;
-    mlp::W1Reg w1{};
-    if constexpr (BF16) w1 = mlp::w1_regs(P, lane);
     // work units (elementwise item, problem of its group), max_g problem slots per item
     for (int wi = blockIdx.x; wi < n_items * max_g; wi += gridDim.x) {
         const int bi = wi / max_g, g = wi - bi * max_g;
@@ -382,8 +380,9 @@ __global__ void __launch_bounds__(256, 3) k_warm(DevPtrs d, int cur, const float
 #pragma unroll
                 for (int q = 0; q < mlp::kPack; q++) f[q] = 0.f;
                 if ((int)threadIdx.x < n) amp_features(d, c, G, g, c0 + threadIdx.x, f, D, v, scx);
-#pragma unroll
-                for (int q = 0; q < mlp::kPack; q++) Fs[threadIdx.x * mlp::kPack + q] = f[q];
+                float4* fw = (float4*)&Fs[threadIdx.x * mlp::kPack];
+                fw[0] = make_float4(f[0], f[1], f[2], f[3]);
+                fw[1] = make_float4(f[4], f[5], f[6], f[7]);
                 Ds[threadIdx.x] = D;
                 Vs[threadIdx.x] = v;
             }
@@ -393,7 +392,7 @@ __global__ void __launch_bounds__(256, 3) k_warm(DevPtrs d, int cur, const float
                 const float4* fr = (const float4*)&Fs[(a0 + ((lane & 15) >> 2)) * mlp::kPack];
                 const float4 f0 = fr[0], f1 = fr[1];
                 const float f[mlp::kPack] = {f0.x, f0.y, f0.z, f0.w, f1.x, f1.y, f1.z, f1.w};
-                const float y = mlp::tile_predict<BF16>(f, s, lane, w1);
+                const float y = mlp::tile_predict<BF16>(f, s, lane);
                 // lane 20 kq: A-operand row 4 kq, i.e. amplitude kq of the tile, variant 0
                 const int o = a0 + kq;
                 if ((lane & 15) == 4 * kq && o < n) tout[c0 + o] = (Vs[o] + (double)y / sc) / Ds[o];
@@ -2899,7 +2898,12 @@ ccd_status ccd_warm_start(ccd_ctx* c, const float* params, int32_t precision, in
     const int n = (int)c->it_elem.size();
     int max_g = 1;
     for (const DevGroup& D : c->dgroups) max_g = std::max(max_g, D.G);
-    const int grid = (int)std::min<int64_t>((int64_t)n * max_g, 16384);
+    // persistent: three blocks per compute unit (the LDS of one block allows
+    // three), each staging the weights once for all its work units
+    int dev = 0, ncu = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    const int grid = (int)std::min<int64_t>((int64_t)n * max_g, (int64_t)std::max(ncu, 1) * 3);
     if (precision == CCD_PREC_BF16)
         LAUNCH(F_INIT, k_warm<true>, grid, 256, warm_lds<true>(), d, c->cur, params, n, max_g);
     else

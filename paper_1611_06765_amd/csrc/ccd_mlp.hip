@@ -36,15 +36,13 @@ __global__ void __launch_bounds__(256) k_mlp_fwd(const float* __restrict__ P, co
     lds_load<BF16>(P, s, threadIdx.x, 256);
     __syncthreads();
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    W1Reg w1{};
-    if constexpr (BF16) w1 = w1_regs(P, lane);
     const int64_t ntile = (n + 3) / 4;
     for (int64_t t = (int64_t)blockIdx.x * 4 + w; t < ntile; t += (int64_t)gridDim.x * 4) {
         const int64_t e = 4 * t + ((lane & 15) >> 2);
         float f[kPack];
 #pragma unroll
         for (int q = 0; q < kPack; q++) f[q] = e < n ? feat[e * kPack + q] : 0.0f;
-        const float yp = tile_predict<BF16>(f, s, lane, w1);
+        const float yp = tile_predict<BF16>(f, s, lane);
         const int64_t eo = 4 * t + (lane >> 4);
         if ((lane & 15) == 0 && eo < n) y[eo] = yp;
     }

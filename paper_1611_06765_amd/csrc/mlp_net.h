@@ -7,10 +7,11 @@
 // swap variants, row 4e + k.  The 128 x 128 layer runs on MFMA with W2 in LDS
 // (FP32 16x16x4, or BF16 16x16x32 with FP32 accumulation).  In the FP32 form
 // the 7-input layer is computed per lane straight into the A-operand layout.
-// In the BF16 form it runs on FP32 MFMA too (W1 in registers, the output
-// transposed: units by rows), and W2 is stored with its K dimension permuted
-// so that each lane's accumulators are its A operand of the next layer
-// without any data movement.  The last layer is a 16-lane reduction of the
+// In the BF16 form it runs on MFMA too, one FP16 16x16x32 step per unit tile
+// with the 7 inputs padded to K = 32 (W1 and the inputs in FP16, FP32
+// accumulation; the output transposed: units by rows), and W2 is stored with
+// its K dimension permuted so that each lane's accumulators are its A operand
+// of the next layer without any data movement.  The last layer is a 16-lane reduction of the
 // accumulator tiles, whose lane layout puts the four variants of one
 // amplitude in one lane group.
 #pragma once
@@ -40,12 +41,16 @@ constexpr double kVScale = 1000.0; // MeV fm^3: v and y are carried as v L^3 / k
 
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+typedef _Float16 h8v __attribute__((ext_vector_type(8)));
 
 __device__ __forceinline__ f4v mfma_f32(float a, float b, f4v c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 __device__ __forceinline__ f4v mfma_bf16(bf8v a, bf8v b, f4v c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4v mfma_f16(h8v a, h8v b, f4v c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
 }
 
 // the activation, relu(z) = max(z, 0), and its derivative (0 at z <= 0): one
@@ -84,7 +89,7 @@ __device__ __forceinline__ float layer1(const float* W1s, const float* b1s, int 
 
 // parameters staged in LDS; W2 as FP32 (ld kLd32) or BF16 (ld kLd16)
 struct Lds {
-    float* W1;   // [128][8]
+    float* W1;   // [128][8] (BF16 form: FP16 [128][8] in the same space)
     float* b1;   // [128]
     float* b2;   // [128]
     float* W3;   // [128]
@@ -109,7 +114,10 @@ __device__ __forceinline__ Lds lds_carve(char* base) {
 
 template <bool BF16>
 __device__ __forceinline__ void lds_load(const float* __restrict__ P, const Lds& s, int tid, int nthreads) {
-    for (int e = tid; e < kW * kPack; e += nthreads) s.W1[e] = P[OFF_W1 + e];
+    for (int e = tid; e < kW * kPack; e += nthreads) {
+        if constexpr (BF16) ((_Float16*)s.W1)[e] = (_Float16)P[OFF_W1 + e];
+        else s.W1[e] = P[OFF_W1 + e];
+    }
     for (int e = tid; e < kW; e += nthreads) {
         s.b1[e] = P[OFF_B1 + e];
         s.b2[e] = P[OFF_B2 + e];
@@ -128,28 +136,11 @@ __device__ __forceinline__ void lds_load(const float* __restrict__ P, const Lds&
     }
 }
 
-// BF16 form: this lane's first-layer weights as the A operands of the FP32
-// MFMA of unit tile ct and input step ks: W1[16 ct + lane % 16][4 ks + lane / 16]
-struct W1Reg {
-    float w[8][2];
-};
-__device__ __forceinline__ W1Reg w1_regs(const float* __restrict__ P, int lane) {
-    W1Reg r;
-    const int row = lane & 15, kq = lane >> 4;
-#pragma unroll
-    for (int ct = 0; ct < 8; ct++) {
-        r.w[ct][0] = P[OFF_W1 + (16 * ct + row) * kPack + kq];
-        r.w[ct][1] = P[OFF_W1 + (16 * ct + row) * kPack + 4 + kq];  // column 7 is zero
-    }
-    return r;
-}
-
 // Prediction y of amplitude (lane >> 4) of a 16-row tile.  f: packed features
 // of the amplitude of this lane's A-operand row, i.e. amplitude (lane & 15) >> 2.
 // The result is valid in every lane of the 16-lane group.
-// w1: the lane's first-layer weights (BF16 form only; unused in the FP32 form).
 template <bool BF16>
-__device__ __forceinline__ float tile_predict(const float* f, const Lds& s, int lane, const W1Reg& w1) {
+__device__ __forceinline__ float tile_predict(const float* f, const Lds& s, int lane) {
     const int row = lane & 15, kq = lane >> 4;
     float x[7];
     variant_inputs(f, row & 3, x);
@@ -157,16 +148,21 @@ __device__ __forceinline__ float tile_predict(const float* f, const Lds& s, int 
 #pragma unroll
     for (int ct = 0; ct < 8; ct++) acc[ct] = f4v{0.f, 0.f, 0.f, 0.f};
     if constexpr (BF16) {
-        // layer 1, transposed: D[unit][row] = sum_k W1[unit][k] x_row[k]; the B
-        // operand of input step ks is this lane's input 4 ks + lane / 16 of its
-        // own row, and the lane receives units 16 ct + 4 (lane / 16) + i
-        const float xb0 = x[kq], xb1 = kq < 3 ? x[4 + kq] : 0.f;
+        // layer 1, transposed: D[unit][row] = sum_k W1[unit][k] x_row[k].  Every
+        // lane supplies W1's row 16 ct + row as A[row][8 kq .. 8 kq + 7]; the B
+        // operand B[8 kq + j][row] is input j of this lane's own row in the
+        // lanes of group 0 and zero in the others, so only K = 0..7 counts.
+        // The lane receives units 16 ct + 4 (lane / 16) + i.
+        h8v xb;
+#pragma unroll
+        for (int j = 0; j < 7; j++) xb[j] = kq == 0 ? (_Float16)x[j] : (_Float16)0.f;
+        xb[7] = (_Float16)0.f;
+        const _Float16* W1h = (const _Float16*)s.W1;
         bf8v a[4];
 #pragma unroll
         for (int ct = 0; ct < 8; ct++) {
-            f4v z = f4v{0.f, 0.f, 0.f, 0.f};
-            z = mfma_f32(w1.w[ct][0], xb0, z);
-            z = mfma_f32(w1.w[ct][1], xb1, z);
+            const h8v wa = *(const h8v*)&W1h[(16 * ct + row) * kPack];
+            const f4v z = mfma_f16(wa, xb, f4v{0.f, 0.f, 0.f, 0.f});
             const float4 bb = *(const float4*)&s.b1[16 * ct + 4 * kq];
             // unit 16 ct + 4 kq + i is logical K index 8 kq + 4 (ct % 2) + i of step ct / 2
             a[ct >> 1][4 * (ct & 1) + 0] = (__bf16)act(z[0] + bb.x);
