@@ -204,3 +204,37 @@ def test_table_ecomparison_loose(nmax2, tol_mev):
     for p, (rho, _, e_ccd) in enumerate(rows):
         eref, _, ec = ctx.energy(p)
         assert abs((eref + ec) / 66 - e_ccd) <= tol_mev, (nmax2, rho, (eref + ec) / 66, e_ccd)
+
+
+@pytest.mark.skipif(not _have("oracle_c5_converged.txt", 16), reason="oracle C5 energies not generated")
+def test_c5_learned_and_mbpt2_starts_against_oracle():
+    """The 16 held-out densities (N = 66, n^2 <= 36) batched, from the MBPT2
+    start and from the warm-start network (trained briefly on 8 of the seeded
+    training densities at n^2 <= 20, BF16 inference), with the timed settings
+    of the learned form (tol_rel 1e-7, tail rule): every converged energy
+    within 1e-6 relative of the oracle's, and the network start needs fewer
+    sweeps in all."""
+    import torch
+    from paper_1611_06765_amd import warmstart
+    ref = _converged("oracle_c5_converged.txt")
+    train_d, held = inputs.c5_densities()
+    specs = [(66, 36, d) for d in held]
+    assert all(s in ref for s in specs)
+    s = torch.cuda.current_stream().cuda_stream
+    tctx, r = warmstart.converged_context([(66, 20, d) for d in train_d[:8]], s)
+    assert r["status"] == ccd.CCD_OK
+    F, Y = warmstart.training_set(tctx)
+    tctx.close()
+    params, _ = warmstart.train(F, Y, epochs=12, batch=16384)
+    sweeps = {}
+    for name in ("mbpt2", "learned"):
+        ctx = _ctx([ccd.problem(*sp) for sp in specs])
+        if name == "learned":
+            assert ctx.warm_start(params, ccd.CCD_PREC_BF16).all()
+        res = ctx.iterate(mixing=MIXING, tol=0.0, tol_rel=1e-7, stop_rule=1, max_iter=3000, check_every=8)
+        assert res["status"] == ccd.CCD_OK
+        for p, sp in enumerate(specs):
+            e = ctx.energy(p)[2]
+            assert abs(e - ref[sp]["eccd"]) <= 1e-6 * abs(ref[sp]["eccd"]), (name, sp, e, ref[sp]["eccd"])
+        sweeps[name] = int(res["sweeps"].sum())
+    assert sweeps["learned"] < sweeps["mbpt2"], sweeps
