@@ -567,7 +567,7 @@ def main():
                     help="skip the mixed / batched / learned wall-time comparisons")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
-    ap.add_argument("--only", choices=["c2", "c3", "c3bf16", "snm"], default=None,
+    ap.add_argument("--only", choices=["c2", "c3", "c3bf16", "snm", "warm"], default=None,
                     help="profiling runs: only this sweep measurement (no JSON line)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -599,6 +599,15 @@ def main():
             sweep_rate_c3(ccd, stream.cuda_stream, args.steps, args.warmup, fake)
         elif args.only == "c3bf16":
             sweep_rate_c3(ccd, stream.cuda_stream, args.steps, args.warmup, fake, ccd.CCD_PREC_BF16)
+        elif args.only == "warm":
+            # the network warm start of the 16 held-out densities (seeded
+            # initial parameters: the inference cost does not depend on them)
+            from paper_1611_06765_amd import inputs
+            c = ccd.Context([ccd.problem(66, 36, r) for r in inputs.c5_densities()[1]], stream=stream.cuda_stream).bind(dev)
+            params = torch.tensor(inputs.mlp_init(inputs.MLP_SEED), device=dev)
+            for _ in range(args.steps):
+                c.warm_start(params, ccd.CCD_PREC_BF16)
+            c.close()
         else:
             snm_rate(ccd, stream.cuda_stream, args.steps, args.warmup)
         torch.cuda.synchronize()
