@@ -342,14 +342,19 @@ __device__ __forceinline__ double nm_genA(int amode, const double* u, int nlut, 
     return amode == AM_GPAIR ? nm_vas(u, nlut, R.x, R.y, C.x, C.y) : nm_vas(u, nlut, R.y, C.y, R.x, C.x);
 }
 
-// this thread's two A and two B entries of the chunk at k0 (array operands;
-// zero outside the block); generated A entries are made when staged
+// K extent of a staged chunk, and each thread's share of its A (32 x kNmKC)
+// and B (kNmKC x 32) entries
+constexpr int kNmKC = 32;
+constexpr int kNmPer = 32 * kNmKC / 256;
+
+// this thread's A and B entries of the chunk at k0 (array operands; zero
+// outside the block); generated A entries are made when staged
 __device__ __forceinline__ void nm_fetch(const NmSeg& S, const NmJob& J, const double* A, const double* B, int m0,
                                          int n0, int k0, double* ra, double* rb) {
 #pragma unroll
-    for (int h = 0; h < 2; h++) {
+    for (int h = 0; h < kNmPer; h++) {
         const int q = threadIdx.x + 256 * h;
-        const int am = q >> 4, ak = q & 15, m = m0 + am, kk = k0 + ak;
+        const int am = q / kNmKC, ak = q % kNmKC, m = m0 + am, kk = k0 + ak;
         ra[h] = 0.0;
         if (m < J.M && kk < S.K) {
             if (S.amode == AM_ROW) ra[h] = A[S.a_off + (int64_t)m * S.lda + kk];
@@ -361,22 +366,24 @@ __device__ __forceinline__ void nm_fetch(const NmSeg& S, const NmJob& J, const d
 }
 
 // One 32 x 32 output tile of one job per workgroup, four waves of 16 x 16;
-// K in chunks of 16 staged in LDS, four FP64 16x16x4 MFMA steps per chunk;
+// K in chunks of kNmKC staged in LDS, kNmKC / 4 FP64 16x16x4 MFMA steps per chunk;
 // the array operands of chunk c + 1 are loaded into registers before chunk c
 // is multiplied.
 // Lane l of a wave supplies A[l%16][l/16], B[l/16][l%16] and receives
 // D[l/16 + 4r][l%16].
 __global__ void __launch_bounds__(256) k_nm_gemm(NmDev d, int cur, uint32_t mask, int tile0, int n_tiles) {
     __shared__ double u[4 * (4 * kNmMaxNmax2 + 1)];
-    __shared__ double sA[32][17];
-    __shared__ double sB[16][33];
-    __shared__ int2 rst[32], cst[16];  // pair states of a generated A operand: tile rows, chunk columns
+    __shared__ double sA[32][kNmKC + 1];
+    __shared__ double sB[kNmKC][33];
+    __shared__ int2 rst[32], cst[kNmKC];  // pair states of a generated A operand: tile rows, chunk columns
     for (int k = threadIdx.x; k < 4 * d.nlut; k += 256) u[k] = d.u[k];
     __syncthreads();
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, wm = w >> 1, wn = w & 1;
     for (int ti = blockIdx.x; ti < n_tiles; ti += gridDim.x) {
         const NmTile T = d.tiles[tile0 + ti];
-        const NmJob J = d.jobs[T.job];
+        // the job is read through a reference to the list: a local copy of it,
+        // whose segment array is indexed at run time, would live in scratch
+        const NmJob& J = d.jobs[T.job];
         const int m0 = T.tm * 32, n0 = T.tn * 32;
         nm_d4 acc = {0.0, 0.0, 0.0, 0.0};
         for (int sg = 0; sg < J.nseg; sg++) {
@@ -385,30 +392,30 @@ __global__ void __launch_bounds__(256) k_nm_gemm(NmDev d, int cur, uint32_t mask
             const double* A = nm_arr(d, S.a_arr, cur);
             const double* B = nm_arr(d, S.b_arr, cur);
             const bool gen = S.amode == AM_GPAIR || S.amode == AM_GVBAR;
-            double ra[2], rb[2];
+            double ra[kNmPer], rb[kNmPer];
             nm_fetch(S, J, A, B, m0, n0, 0, ra, rb);
-            for (int k0 = 0; k0 < S.K; k0 += 16) {
+            for (int k0 = 0; k0 < S.K; k0 += kNmKC) {
                 __syncthreads();  // the previous chunk's reads are done
                 if (gen) {
                     if (k0 == 0 && threadIdx.x < 32 && m0 + (int)threadIdx.x < J.M)
                         rst[threadIdx.x] = nm_pair_states(d, S.amode, S.a_rows, m0 + threadIdx.x);
-                    if (threadIdx.x >= 64 && threadIdx.x < 80 && k0 + (int)threadIdx.x - 64 < S.K)
+                    if (threadIdx.x >= 64 && threadIdx.x < 64 + kNmKC && k0 + (int)threadIdx.x - 64 < S.K)
                         cst[threadIdx.x - 64] = nm_pair_states(d, S.amode, S.a_cols, k0 + threadIdx.x - 64);
                     __syncthreads();
                 }
 #pragma unroll
-                for (int h = 0; h < 2; h++) {
+                for (int h = 0; h < kNmPer; h++) {
                     const int q = threadIdx.x + 256 * h;
-                    const int am = q >> 4, ak = q & 15;
+                    const int am = q / kNmKC, ak = q % kNmKC;
                     double av = ra[h];
                     if (gen) av = (m0 + am < J.M && k0 + ak < S.K) ? nm_genA(S.amode, u, d.nlut, rst[am], cst[ak]) : 0.0;
                     sA[am][ak] = S.alpha * av;
                     sB[q >> 5][q & 31] = rb[h];
                 }
                 __syncthreads();
-                if (k0 + 16 < S.K) nm_fetch(S, J, A, B, m0, n0, k0 + 16, ra, rb);
+                if (k0 + kNmKC < S.K) nm_fetch(S, J, A, B, m0, n0, k0 + kNmKC, ra, rb);
 #pragma unroll
-                for (int s = 0; s < 4; s++) {
+                for (int s = 0; s < kNmKC / 4; s++) {
                     const double a = sA[wm * 16 + (lane & 15)][4 * s + (lane >> 4)];
                     const double b = sB[4 * s + (lane >> 4)][wn * 16 + (lane & 15)];
                     acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
