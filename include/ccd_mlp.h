@@ -58,7 +58,8 @@ ccd_status ccd_mlp_features(const ccd_ctx* ctx, int32_t problem, float* dev_feat
 
 /* y for n amplitudes from packed features (16-byte aligned buffers), with the
  * 128 x 128 layer on FP32 (CCD_PREC_FP32) or BF16 (CCD_PREC_BF16, FP32
- * accumulation) MFMA.  dev_y [n]. */
+ * accumulation) MFMA; in the BF16 form the first layer runs on FP16 MFMA
+ * (FP32 accumulation), in the FP32 form in FP32.  dev_y [n]. */
 ccd_status ccd_mlp_forward(const float* dev_params, const float* dev_feat, int64_t n, int32_t precision,
                            float* dev_y, void* hip_stream);
 
