@@ -2575,6 +2575,15 @@ static ccd_status run_phase(ccd_ctx* c, const ccd_solver_opts* o, int prec, doub
     }
     bool all_done = false;
     used = 0;
+    // Chunk length: `every` sweeps, or fewer once the sweeps that the slowest
+    // problem still needs can be estimated from its geometric rate of
+    // convergence: sweeps launched after every problem has stopped still cost
+    // most of a live sweep (launches, barriers, the update's copy of t), while
+    // a short chunk costs one more host read.  Only the host's reads move; the
+    // device decides when each problem stops, so results do not change.
+    std::vector<double> ec(P), dq(P), d_then(P, 0.0);
+    std::vector<int32_t> sw_then(P, 0);
+    int next = every;
     while (used < budget && !all_done) {
         int n;
         double tol, rel;
@@ -2582,7 +2591,7 @@ static ccd_status run_phase(ccd_ctx* c, const ccd_solver_opts* o, int prec, doub
             n = std::min(std::min(min_sweeps - 1 - used, budget - used), every);
             tol = rel = 0.0;
         } else {
-            n = std::min(every, budget - used);
+            n = std::min(next, budget - used);
             tol = tol_phase;
             rel = rel_phase;
         }
@@ -2593,9 +2602,13 @@ static ccd_status run_phase(ccd_ctx* c, const ccd_solver_opts* o, int prec, doub
             sw0 = sw;
             HIP_TRY(hipMemcpyAsync(sw.data(), c->ws + c->r_sweeps.off, P * 4, hipMemcpyDeviceToHost, c->stream));
             HIP_TRY(hipMemcpyAsync(act.data(), c->ws + c->r_active.off, P * 4, hipMemcpyDeviceToHost, c->stream));
-            if (e_hist)
+            if (e_hist || stops)
                 HIP_TRY(hipMemcpyAsync(hb.data(), c->ws + c->r_ehist.off, hb.size() * 8, hipMemcpyDeviceToHost,
                                        c->stream));
+            if (stops) {
+                HIP_TRY(hipMemcpyAsync(ec.data(), c->ws + c->r_ecorr.off, P * 8, hipMemcpyDeviceToHost, c->stream));
+                HIP_TRY(hipMemcpyAsync(dq.data(), c->ws + c->r_dprev.off, P * 8, hipMemcpyDeviceToHost, c->stream));
+            }
             HIP_TRY(hipStreamSynchronize(c->stream));
             all_done = stops;
             for (int p = 0; p < P; p++) {
@@ -2604,6 +2617,35 @@ static ccd_status run_phase(ccd_ctx* c, const ccd_solver_opts* o, int prec, doub
                     for (int k = sw0[sl]; k < sw[sl] && k < o->max_iter; k++)
                         e_hist[(size_t)p * o->max_iter + k] = hb[(size_t)sl * kHistCap + k % kHistCap];
                 if (act[sl]) all_done = false;
+            }
+            if (stops && used + 1 >= min_sweeps) {
+                next = 0;
+                for (int sl = 0; sl < P; sl++) {
+                    if (!act[sl]) continue;
+                    const double de = dq[sl], thr = tol_phase + rel_phase * std::fabs(ec[sl]);
+                    int need = every;
+                    // the rate over the last chunk, else over the last sweep (the
+                    // energy history holds E after sweep s at (s - 1) mod kHistCap)
+                    double rate = -1.0;
+                    if (sw[sl] > sw_then[sl] && d_then[sl] > 0.0 && de > 0.0) {
+                        rate = std::pow(de / d_then[sl], 1.0 / (sw[sl] - sw_then[sl]));
+                    } else if (sw[sl] >= 3 && de > 0.0) {
+                        const double* h = hb.data() + (size_t)sl * kHistCap;
+                        const double d1 = std::fabs(h[(sw[sl] - 2) % kHistCap] - h[(sw[sl] - 3) % kHistCap]);
+                        if (d1 > 0.0) rate = de / d1;
+                    }
+                    if (std::isfinite(rate) && rate > 0.0 && rate < 1.0) {
+                        // rule 1 stops after two sweeps with |dE| r / (1 - r) < thr
+                        const double target = rule == 1 ? thr * (1.0 - rate) / rate : thr;
+                        const int extra = rule == 1 ? 2 : 1;
+                        need = de < target ? extra
+                                           : (int)std::floor(std::log(target / de) / std::log(rate)) + extra;
+                    }
+                    next = std::max(next, std::min(std::max(need, 1), every));
+                    d_then[sl] = de;
+                    sw_then[sl] = sw[sl];
+                }
+                if (next < 1) next = every;
             }
         }
     }
