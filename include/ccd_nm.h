@@ -108,11 +108,13 @@ ccd_status ccd_nm_last_ms(const ccd_nm_ctx* ctx, double* ms);
  * HIP events on the context's stream.  ccd_nm_kernel_times returns, per kernel
  * family (CCD_NM_FAMILIES of them, named by ccd_nm_kernel_name: gather,
  * rowcol, dchi, gemm_chi (chi_klij and the ring's C_P), gemm_ladder_ring (the
- * ladders and the ring's Z_Q), update, energy), the summed milliseconds, the
+ * hh ladder, the pp ladder of blocks without the momentum-pair form, and the
+ * ring's Z_Q), update, energy, ladder_pp (the pp ladder as products over the
+ * blocks' momentum pairs)), the summed milliseconds, the
  * launch count and the FP64 flops of one launch of that family (0 for the
  * non-product families), and optionally resets the sums.  Both synchronise the
  * stream. */
-#define CCD_NM_FAMILIES 7
+#define CCD_NM_FAMILIES 8
 ccd_status ccd_nm_set_timing(ccd_nm_ctx* ctx, int32_t enabled);
 ccd_status ccd_nm_kernel_times(ccd_nm_ctx* ctx, double* ms, int64_t* launches, double* flops, int32_t reset);
 const char* ccd_nm_kernel_name(int32_t family);

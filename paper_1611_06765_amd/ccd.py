@@ -570,7 +570,7 @@ class NMContext:
 
     def kernel_times(self, reset=False):
         """{family: (ms summed, launches, FP64 flops per launch)}"""
-        n = 7
+        n = 8
         ms, ln, fl = np.zeros(n), np.zeros(n, dtype=np.int64), np.zeros(n)
         _check(_lib.ccd_nm_kernel_times(self._h, _dptr(ms), ln.ctypes.data_as(C.POINTER(C.c_int64)), _dptr(fl),
                                         int(bool(reset))), "ccd_nm_kernel_times")

@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -72,15 +73,15 @@ __host__ __device__ inline int nm_d2(int32_t a, int32_t b) {
 // +-(1/2, 1/4, 1/4) and +-(0, 1/4, -1/4); u holds the four combined tables
 // U_k(m) = c . W(m) for k = 0..3 (nlut entries each), and the 4-bit code
 // (d_s, x_s, d_t, x_t) picks the table and the sign.
-__host__ __device__ inline double nm_vas(const double* u, int nlut, int32_t p, int32_t q, int32_t r, int32_t s) {
-    const int a = nm_st(p), b = nm_st(q), c = nm_st(r), d = nm_st(s);
+// The table k and sign of the element from the spin-isospin labels (bit 0 spin
+// up, bit 1 neutron) of p, q, r, s; false when the element is zero.
+__host__ __device__ inline bool nm_class(int a, int b, int c, int d, int& k, bool& neg) {
     const int ds = ((a & 1) == (c & 1)) & ((b & 1) == (d & 1));
     const int xs = ((a & 1) == (d & 1)) & ((b & 1) == (c & 1));
     const int dt = ((a >> 1) == (c >> 1)) & ((b >> 1) == (d >> 1));
     const int xt = ((a >> 1) == (d >> 1)) & ((b >> 1) == (c >> 1));
     const int code = (ds << 3) | (xs << 2) | (dt << 1) | xt;
-    int k = -1;
-    bool neg = false;
+    neg = false;
     switch (code) {
         case 11: k = 0; break;               // (1,0,1,1)
         case 7: k = 0; neg = true; break;    // (0,1,1,1)
@@ -90,8 +91,15 @@ __host__ __device__ inline double nm_vas(const double* u, int nlut, int32_t p, i
         case 5: k = 2; neg = true; break;    // (0,1,0,1)
         case 6: k = 3; break;                // (0,1,1,0)
         case 9: k = 3; neg = true; break;    // (1,0,0,1)
-        default: return 0.0;
+        default: return false;
     }
+    return true;
+}
+
+__host__ __device__ inline double nm_vas(const double* u, int nlut, int32_t p, int32_t q, int32_t r, int32_t s) {
+    int k = 0;
+    bool neg = false;
+    if (!nm_class(nm_st(p), nm_st(q), nm_st(r), nm_st(s), k, neg)) return 0.0;
     const double w = u[k * nlut + nm_d2(p, r)] + u[k * nlut + nm_d2(p, s)];
     return neg ? -w : w;
 }
@@ -116,7 +124,7 @@ enum { ARR_T = 0, ARR_VT = 1, ARR_CHH = 2, ARR_TQ = 3, ARR_CP = 4, ARR_LAD = 5 }
 // operand / output modes of the channel products
 enum { AM_ROW = 0, AM_COL = 1, AM_GPAIR = 2, AM_GVBAR = 3 };
 enum { CM_NONE = 0, CM_GPAIR = 1, CM_GVPH = 2 };
-enum { OM_ROW = 0, OM_SCATTER = 1 };
+enum { OM_ROW = 0, OM_SCATTER = 1, OM_ROW_ADD = 2 };  // OM_ROW_ADD: added to the output array's value
 
 struct NmSeg {
     int32_t K, amode, lda, term;   // term: mask bits that enable the segment
@@ -140,6 +148,23 @@ struct NmTile {
     int32_t job, tm, tn;
 };
 
+// The pp ladder of a direct channel as products over its momentum pairs (see
+// k_nm_ladpp).  Row slots 0..3 of a momentum pair are the rows X_0, Y_0, X_1,
+// Y_1 of the differences delta_j = t(X_j) - t(Y_j); rec[slot] gives, for j = 0
+// and 1, the coefficient of u_(class, j) in that row's sum (bits 0-1 and 3-4:
+// 0 none, 1 plus, 2 minus) and its class (bits 2 and 5).
+struct NmLadD {
+    int32_t chan, lp_off, n_lp;    // direct channel; its momentum pairs (offset in pairs, count)
+    int32_t nd, nk;                // differences (0..2) and element classes (0..2)
+    int32_t tab[2];                // the table of each class
+    int32_t kx, ky, kz;            // total momentum
+    int32_t rec[4];
+};
+
+struct NmLadItem {
+    int32_t lad, start;            // channel entry; first momentum pair | 16-column tile << 20
+};
+
 struct NmDev {
     const int32_t* st;      // packed states
     const double* u;        // the four element tables
@@ -152,6 +177,9 @@ struct NmDev {
     const NmItem* items;
     const NmJob* jobs;
     const NmTile* tiles;
+    const NmLadD* ladd;     // pp ladder over momentum pairs: channels,
+    const int4* ladlp;      // two int4 per momentum pair: (p packed, |p|^2 | |q|^2 << 10, X_0, Y_0), (X_1, Y_1, 0, 0)
+    const NmLadItem* ladit; // and work items
     const int32_t* csr_ptr; // per state: rows (particles) or columns (holes) holding it
     const int32_t* csr_idx;
     const int32_t* row_chan;  // global row -> channel ; global column -> channel
@@ -439,11 +467,250 @@ __global__ void __launch_bounds__(256) k_nm_gemm(NmDev d, int cur, uint32_t mask
             }
             if (J.omode == OM_ROW) {
                 nm_arr(d, J.o_arr, cur)[J.o_off + (int64_t)m * J.ldo + n] = v;
+            } else if (J.omode == OM_ROW_ADD) {
+                double* o = nm_arr(d, J.o_arr, cur) + J.o_off + (int64_t)m * J.ldo + n;
+                *o = *o + v;
             } else {
                 const int32_t z = d.pmap[J.o_off + (int64_t)m * J.ldo + n];
                 if (z >= 0) d.ring[4 * (int64_t)(z >> 3) + ((z >> 1) & 3)] = (z & 1) ? -v : v;
             }
         }
+    }
+}
+
+
+// pp ladder over momentum pairs.  In a direct channel (K, S_z, T_z) the element
+// <ab||cd> = +-(U_k(|n_a - n_c|^2) + U_k(|n_a - n_d|^2)) depends on the row only
+// through n_a and the labels of a and b, on the column through its momenta
+// {n_c, n_d} and labels, and its table k and sign only on the four labels.
+// The rows of a momentum pair P = {p, K - p} (the first state at p) are its
+// label pairs; with the channel's labels sorted into pairs (X_j, Y_j) whose
+// columns enter every row with the same table and opposite signs,
+//   sum_{c<d} <ab||cd> t_ij^cd = sum_j c_(ab, j) u_(k(ab, j), j)(n_a),
+//   u_(k, j)(p') = sum_P M_k[p'][P] delta_j(P),  M_k[p'][P] = U_k(|p' - p|^2) + U_k(|p' - q|^2),
+//   delta_j(P) = t(P, X_j) - t(P, Y_j),
+// a square product over the momentum pairs per (class, difference): one for
+// the S_z = 0 blocks of like particles and the |S_z| = 1 blocks of unlike ones,
+// four for the S_z = T_z = 0 blocks, against 4 x 4 and 16 x 16 times the
+// flops of the product over label pairs.  M_k is generated per lane with the
+// offsets of the neutron ladder (one sdot4 and three integer ops), the
+// differences are formed when a chunk of kNmKP pairs is staged, and each row
+// takes its combination of the products.  A wave holds one 16-row tile; the
+// 16-column tile is cut into NG groups of four for the 4x4x4 FP64 MFMA.
+constexpr int kNmKP = 128;       // column momentum pairs staged per chunk
+constexpr int kNmLadRows = 64;   // row momentum pairs per work item
+__device__ __forceinline__ double nm_mfma4(double a, double b, double c) {
+    return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
+}
+template <int NG, int ND, int NK>
+__device__ __forceinline__ void nm_ladpp_item(const NmDev& d, const NmLadD& L, const NmChanD& C, int cur, int r0,
+                                              int ct, bool pp_on, const double* lutS, double* tks,
+                                              int4 (*cvi)[kNmKP], int (*cvj)[kNmKP], int4* prs) {
+    constexpr int S = 8;  // bytes per table entry
+    constexpr int NA = ND * NK == 1 ? 2 : 1;  // independent accumulators per product
+    const char* lutB = (const char*)lutS;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int nhh = C.nhh, nlp = L.n_lp;
+    const double* tcur = d.t[cur] + C.t_off;
+    const int4* lp = d.ladlp + 2 * (int64_t)L.lp_off;
+    const int rbase = r0 + 16 * w;
+    const int bj = lane & 3;
+    const int orow4 = 4 * ((lane & 15) >> 2) + (lane >> 4);
+    int tb[2] = {0, 0};  // byte offsets of the classes' tables
+#pragma unroll
+    for (int c = 0; c < NK; c++) tb[c] = L.tab[c] * d.nlut * S;
+    const int32_t kpack = (int32_t)((uint32_t)(uint8_t)(int8_t)L.kx | ((uint32_t)(uint8_t)(int8_t)L.ky << 8) |
+                                    ((uint32_t)(uint8_t)(int8_t)L.kz << 16));
+    const int K2 = L.kx * L.kx + L.ky * L.ky + L.kz * L.kz;
+    auto times4 = [](int32_t x) { return (int32_t)(((uint32_t)x << 2) & 0xfcfcfcfcu); };
+    // generator row (A layout): -(S/2) p' packed, S |p'|^2, S (2 |p'|^2 - 2 p'.K)
+    int32_t apack = 0;
+    int rowA = 0, rowS = 0;
+    {
+        const int pr = rbase + (lane & 15);
+        const int4 li = pr < nlp ? lp[2 * pr] : make_int4(0, 0, -1, -1);
+        const int ax = (int8_t)(li.x & 0xff), ay = (int8_t)((li.x >> 8) & 0xff), az = (int8_t)((li.x >> 16) & 0xff);
+        apack = (int32_t)((uint32_t)(uint8_t)(int8_t)(-4 * ax) | ((uint32_t)(uint8_t)(int8_t)(-4 * ay) << 8) |
+                          ((uint32_t)(uint8_t)(int8_t)(-4 * az) << 16));
+        const int A2 = li.y & 1023;
+        rowA = S * A2;
+        rowS = S * (2 * A2 - 2 * (ax * L.kx + ay * L.ky + az * L.kz));
+    }
+    // column descriptor: (4 p packed, S |p|^2, S (|p|^2 + |q|^2), X_0 + 1 | (Y_0 + 1) << 16)
+    // and (X_1 + 1 | (Y_1 + 1) << 16); padding columns carry p = K, q = 0, no rows
+    const int4 cpad = make_int4(times4(kpack), S * K2, S * K2, 0);
+    auto cdesc = [&](const int4& li) {
+        const int C2 = li.y & 1023, D2 = (li.y >> 10) & 1023;
+        return make_int4(times4(li.x), S * C2, S * (C2 + D2),
+                         (int)((uint32_t)(li.z + 1) | ((uint32_t)(li.w + 1) << 16)));
+    };
+    auto cdesc2 = [&](const int4& lj) { return (int)((uint32_t)(lj.x + 1) | ((uint32_t)(lj.y + 1) << 16)); };
+    constexpr int kPer = kNmKP * 16 / 256;
+    double tv[ND][kPer];
+    auto load_delta = [&](int kp, int b) {
+        const int kn = min(kNmKP, nlp - kp);
+#pragma unroll
+        for (int i = 0; i < kPer; i++) {
+            const int e = threadIdx.x + 256 * i, kk = e >> 4, cc = ct * 16 + (e & 15);
+            const bool in = kk < kn && cc < nhh;
+#pragma unroll
+            for (int j = 0; j < ND; j++) {
+                const uint32_t rr = in ? (uint32_t)(j == 0 ? cvi[b][kk].w : cvj[b][kk]) : 0u;
+                const int rp = (int)(rr & 0xffff) - 1, rm = (int)(rr >> 16) - 1;
+                const double tp = rp >= 0 ? tcur[(int64_t)rp * nhh + cc] : 0.0;
+                const double tm = rm >= 0 ? tcur[(int64_t)rm * nhh + cc] : 0.0;
+                tv[j][i] = tp - tm;
+            }
+        }
+    };
+    auto store_delta = [&]() {
+#pragma unroll
+        for (int j = 0; j < ND; j++)
+#pragma unroll
+            for (int i = 0; i < kPer; i++) {
+                const int e = threadIdx.x + 256 * i;
+                tks[j * kNmKP * 16 + (e >> 4) * 16 + (e & 15)] = tv[j][i];
+            }
+    };
+    double acc[NK][ND][NG][NA];
+#pragma unroll
+    for (int c = 0; c < NK; c++)
+#pragma unroll
+        for (int j = 0; j < ND; j++)
+#pragma unroll
+            for (int q = 0; q < NG; q++)
+#pragma unroll
+                for (int a = 0; a < NA; a++) acc[c][j][q][a] = 0.0;
+    int4 lpc = cpad, lpd = make_int4(-1, -1, 0, 0);
+    if (pp_on && threadIdx.x < kNmKP && threadIdx.x < nlp) { lpc = lp[2 * threadIdx.x]; lpd = lp[2 * threadIdx.x + 1]; }
+    const int4 myr = (threadIdx.x < kNmLadRows && r0 + threadIdx.x < nlp)
+                         ? make_int4(lp[2 * (r0 + threadIdx.x)].z, lp[2 * (r0 + threadIdx.x)].w,
+                                     lp[2 * (r0 + threadIdx.x) + 1].x, lp[2 * (r0 + threadIdx.x) + 1].y)
+                         : make_int4(-1, -1, -1, -1);
+    __syncthreads();  // the previous item's reads of LDS are done
+    if (threadIdx.x < kNmLadRows) prs[threadIdx.x] = myr;
+    if (pp_on) {
+        if (threadIdx.x < kNmKP) {
+            cvi[0][threadIdx.x] = threadIdx.x < nlp ? cdesc(lpc) : cpad;
+            cvj[0][threadIdx.x] = threadIdx.x < nlp ? cdesc2(lpd) : 0;
+        }
+        lpc = cpad; lpd = make_int4(-1, -1, 0, 0);
+        if (threadIdx.x < kNmKP && kNmKP + threadIdx.x < nlp) {
+            lpc = lp[2 * (kNmKP + threadIdx.x)];
+            lpd = lp[2 * (kNmKP + threadIdx.x) + 1];
+        }
+    }
+    __syncthreads();
+    if (pp_on) {
+        load_delta(0, 0);
+        store_delta();
+        for (int kp = 0; kp < nlp; kp += kNmKP) {
+            const int b = (kp / kNmKP) & 1;
+            const bool more = kp + kNmKP < nlp;
+            if (more && threadIdx.x < kNmKP) {
+                const bool in = kp + kNmKP + threadIdx.x < nlp;
+                cvi[b ^ 1][threadIdx.x] = in ? cdesc(lpc) : cpad;
+                cvj[b ^ 1][threadIdx.x] = in ? cdesc2(lpd) : 0;
+                lpc = cpad; lpd = make_int4(-1, -1, 0, 0);
+                if (kp + 2 * kNmKP + threadIdx.x < nlp) {
+                    lpc = lp[2 * (kp + 2 * kNmKP + threadIdx.x)];
+                    lpd = lp[2 * (kp + 2 * kNmKP + threadIdx.x) + 1];
+                }
+            }
+            __syncthreads();  // this chunk's differences and the next chunk's descriptors are in LDS
+            if (more) load_delta(kp + kNmKP, b ^ 1);
+            const int kn = min(kNmKP, nlp - kp);
+            const int ksteps = (kn + 15) & ~15;
+            for (int kk = 0; kk < ksteps; kk += 16) {
+#pragma unroll
+                for (int s2 = 0; s2 < 4; s2++) {
+                    const int kc = kk + 4 * s2 + (lane >> 4);
+                    const int4 ci = cvi[b][kc];
+                    const int o1 = __builtin_amdgcn_sdot4(apack, ci.x, rowA + ci.y, false);
+                    const int o2 = rowS + ci.z - o1;
+                    double va[NK];
+#pragma unroll
+                    for (int c = 0; c < NK; c++)
+                        va[c] = *(const double*)(lutB + tb[c] + o1) + *(const double*)(lutB + tb[c] + o2);
+#pragma unroll
+                    for (int j = 0; j < ND; j++)
+#pragma unroll
+                        for (int q = 0; q < NG; q++) {
+                            const double vb = tks[j * kNmKP * 16 + kc * 16 + 4 * q + bj];
+#pragma unroll
+                            for (int c = 0; c < NK; c++)
+                                acc[c][j][q][s2 % NA] = nm_mfma4(va[c], vb, acc[c][j][q][s2 % NA]);
+                        }
+                }
+            }
+            __syncthreads();  // every wave is done with this chunk
+            if (more) store_delta();
+        }
+    }
+    // the four rows of the lane's output pair, each with its combination
+    const int4 ro = prs[16 * w + orow4];
+    const int rows[4] = {ro.x, ro.y, ro.z, ro.w};
+    double* lad = d.lad + C.t_off;
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+        if (rows[r] < 0) continue;
+        const int rc = L.rec[r];
+#pragma unroll
+        for (int q = 0; q < NG; q++) {
+            const int cc = ct * 16 + 4 * q + bj;
+            if (cc >= nhh) continue;
+            double v = 0.0;
+#pragma unroll
+            for (int j = 0; j < ND; j++) {
+                const int cf = (rc >> (3 * j)) & 3, cl = (rc >> (3 * j + 2)) & 1;
+                double u = 0.0;
+#pragma unroll
+                for (int c = 0; c < NK; c++)
+                    if (c == cl) {
+#pragma unroll
+                        for (int a = 0; a < NA; a++) u += acc[c][j][q][a];
+                    }
+                if (cf == 1) v += u;
+                else if (cf == 2) v -= u;
+            }
+            lad[(int64_t)rows[r] * nhh + cc] = pp_on ? v : 0.0;
+        }
+    }
+}
+
+template <int ND, int NK>
+__device__ __forceinline__ void nm_ladpp_ng(const NmDev& d, const NmLadD& L, const NmChanD& C, int cur, int r0,
+                                            int ct, bool pp_on, double* lutS, double* tks, int4 (*cvi)[kNmKP],
+                                            int (*cvj)[kNmKP], int4* prs) {
+    const int ng = min(4, (min(16, C.nhh - 16 * ct) + 3) >> 2);
+    switch (ng) {
+        case 1: nm_ladpp_item<1, ND, NK>(d, L, C, cur, r0, ct, pp_on, lutS, tks, cvi, cvj, prs); break;
+        case 2: nm_ladpp_item<2, ND, NK>(d, L, C, cur, r0, ct, pp_on, lutS, tks, cvi, cvj, prs); break;
+        case 3: nm_ladpp_item<3, ND, NK>(d, L, C, cur, r0, ct, pp_on, lutS, tks, cvi, cvj, prs); break;
+        default: nm_ladpp_item<4, ND, NK>(d, L, C, cur, r0, ct, pp_on, lutS, tks, cvi, cvj, prs); break;
+    }
+}
+
+// one work item (channel, 64 row momentum pairs, 16 columns) per workgroup
+// iteration; the four class tables are staged once per workgroup
+__global__ void __launch_bounds__(256, 2) k_nm_ladpp(NmDev d, int cur, uint32_t mask, int n_items) {
+    __shared__ double lutS[4 * (4 * kNmMaxNmax2 + 1)];
+    __shared__ __attribute__((aligned(16))) double tks[2 * kNmKP * 16];
+    __shared__ int4 cvi[2][kNmKP];
+    __shared__ int cvj[2][kNmKP];
+    __shared__ int4 prs[kNmLadRows];
+    for (int k = threadIdx.x; k < 4 * d.nlut; k += 256) lutS[k] = d.u[k];
+    const bool pp = (mask & CCD_T_PP) != 0;
+    for (int bi = blockIdx.x; bi < n_items; bi += gridDim.x) {
+        const NmLadItem it = d.ladit[bi];
+        const NmLadD& L = d.ladd[it.lad];
+        const NmChanD C = d.ch[L.chan];
+        const int r0 = it.start & 0xfffff, ct = it.start >> 20;
+        if (L.nd == 2 && L.nk == 2) nm_ladpp_ng<2, 2>(d, L, C, cur, r0, ct, pp, lutS, tks, cvi, cvj, prs);
+        else if (L.nd == 2 && L.nk == 1) nm_ladpp_ng<2, 1>(d, L, C, cur, r0, ct, pp, lutS, tks, cvi, cvj, prs);
+        else if (L.nd == 1 && L.nk == 2) nm_ladpp_ng<1, 2>(d, L, C, cur, r0, ct, pp, lutS, tks, cvi, cvj, prs);
+        else if (L.nd == 1) nm_ladpp_ng<1, 1>(d, L, C, cur, r0, ct, pp, lutS, tks, cvi, cvj, prs);
+        else nm_ladpp_ng<1, 1>(d, L, C, cur, r0, ct, false, lutS, tks, cvi, cvj, prs);  // no element: zeros
     }
 }
 
@@ -508,8 +775,9 @@ inline size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
 }  // namespace
 
 // kernel families of a sweep, for per-launch timing
-enum { NF_GATHER = 0, NF_ROWCOL, NF_DCHI, NF_GEMM1, NF_GEMM2, NF_UPDATE, NF_ENERGY, NF_NUM };
-const char* const kNmFamily[NF_NUM] = {"gather", "rowcol", "dchi", "gemm_chi", "gemm_ladder_ring", "update", "energy"};
+enum { NF_GATHER = 0, NF_ROWCOL, NF_DCHI, NF_GEMM1, NF_GEMM2, NF_UPDATE, NF_ENERGY, NF_LADPP, NF_NUM };
+const char* const kNmFamily[NF_NUM] = {"gather", "rowcol", "dchi", "gemm_chi", "gemm_ladder_ring", "update", "energy",
+                                       "ladder_pp"};
 
 struct ccd_nm_ctx {
     ccd_nm_problem par;
@@ -534,6 +802,10 @@ struct ccd_nm_ctx {
     int64_t n_amp = 0, n_chh = 0, n_tq = 0, n_cp = 0;
     int n_rows = 0, n_cols = 0, max_hh = 0, max_pp = 0, max_ph = 0;
     double flops = 0.0, flops_a = 0.0;  // all products; those of the first launch
+    double flops_lad = 0.0;             // the pp ladder over momentum pairs
+    std::vector<NmLadD> ladd;           // its channels, momentum pairs and work items
+    std::vector<int32_t> ladlp;
+    std::vector<NmLadItem> ladit;
     // workspace
     char* ws = nullptr;
     size_t ws_bytes = 0;
@@ -550,6 +822,143 @@ double nm_vas_host(const ccd_nm_ctx* c, int p, int q, int r, int s) {
         c->nz[p] + c->nz[q] != c->nz[r] + c->nz[s])
         return 0.0;
     return nm_vas(c->u.data(), c->nlut, c->st[p], c->st[q], c->st[r], c->st[s]);
+}
+
+// The pp ladder of channel k over its momentum pairs (k_nm_ladpp): the pairs
+// of its rows (keyed by the momentum of the first state), the pairing of its
+// label pairs into differences and each label's combination of the products.
+// False when the channel's elements do not take that form; its ladder then
+// stays a product over label pairs.  Every row's elements against a sample of
+// columns are checked against the element itself.
+bool nm_ladpp_channel(const ccd_nm_ctx* c, int k, NmLadD& L, std::vector<int32_t>& lp) {
+    const HChan& h = c->ch[k];
+    const int npp = (int)h.pp.size();
+    if (npp >= 0xffff) return false;
+    std::vector<int> labs;
+    std::map<std::tuple<int, int, int>, int> pidx;
+    std::vector<std::vector<std::pair<int, int>>> prl;  // per momentum pair: (label pair, row)
+    std::vector<std::array<int, 2>> pst;                // per momentum pair: its first row's states
+    for (int r = 0; r < npp; r++) {
+        const int a = pr_a(h.pp[r]), b = pr_b(h.pp[r]);
+        const int lab = nm_st(c->st[a]) | (nm_st(c->st[b]) << 2);
+        if (std::find(labs.begin(), labs.end(), lab) == labs.end()) labs.push_back(lab);
+        auto ins = pidx.insert({{c->nx[a], c->ny[a], c->nz[a]}, (int)prl.size()});
+        if (ins.second) {
+            prl.emplace_back();
+            pst.push_back({a, b});
+        }
+        prl[ins.first->second].push_back({lab, r});
+    }
+    const int nl = (int)labs.size();
+    if (nl > 4) return false;
+    std::sort(labs.begin(), labs.end());
+    int tk[4][4] = {}, sg[4][4] = {};
+    bool any = false;
+    for (int x = 0; x < nl; x++)
+        for (int y = 0; y < nl; y++) {
+            int kk = 0;
+            bool neg = false;
+            if (nm_class(labs[x] & 3, labs[x] >> 2, labs[y] & 3, labs[y] >> 2, kk, neg)) {
+                tk[x][y] = kk;
+                sg[x][y] = neg ? -1 : 1;
+                any = true;
+            }
+        }
+    int slot_of[4] = {0, 1, 2, 3};
+    std::memset(&L, 0, sizeof(L));
+    L.chan = k;
+    L.kx = h.Kx; L.ky = h.Ky; L.kz = h.Kz;
+    std::vector<int> cls;
+    if (any) {
+        std::vector<int> X, Y;
+        bool used[4] = {false, false, false, false};
+        for (int x = 0; x < nl; x++) {
+            if (used[x]) continue;
+            int y = -1;
+            for (int z = x + 1; z < nl && y < 0; z++) {
+                if (used[z]) continue;
+                bool ok = true;
+                for (int r = 0; r < nl && ok; r++) {
+                    if (sg[r][x] == 0 && sg[r][z] == 0) continue;
+                    ok = sg[r][x] != 0 && sg[r][z] == -sg[r][x] && tk[r][x] == tk[r][z];
+                }
+                if (ok) y = z;
+            }
+            if (y < 0) return false;
+            used[x] = used[y] = true;
+            X.push_back(x);
+            Y.push_back(y);
+        }
+        if (X.size() > 2) return false;
+        for (int r = 0; r < nl; r++)
+            for (size_t j = 0; j < X.size(); j++)
+                if (sg[r][X[j]] != 0 && std::find(cls.begin(), cls.end(), tk[r][X[j]]) == cls.end())
+                    cls.push_back(tk[r][X[j]]);
+        if (cls.empty() || cls.size() > 2) return false;
+        L.nd = (int)X.size();
+        L.nk = (int)cls.size();
+        for (int q = 0; q < L.nk; q++) L.tab[q] = cls[q];
+        for (size_t j = 0; j < X.size(); j++) {
+            slot_of[X[j]] = 2 * (int)j;
+            slot_of[Y[j]] = 2 * (int)j + 1;
+        }
+        for (int r = 0; r < nl; r++) {
+            int rc = 0;
+            for (size_t j = 0; j < X.size(); j++) {
+                const int sgn = sg[r][X[j]];
+                if (sgn == 0) continue;
+                const int ci = (int)(std::find(cls.begin(), cls.end(), tk[r][X[j]]) - cls.begin());
+                rc |= ((sgn > 0 ? 1 : 2) | (ci << 2)) << (3 * j);
+            }
+            L.rec[slot_of[r]] = rc;
+        }
+    }
+    // the rows' elements against a sample of columns, from the recipe
+    const int step = std::max(1, npp / 16);
+    for (int r = 0; r < npp; r++) {
+        const int a = pr_a(h.pp[r]), b = pr_b(h.pp[r]);
+        const int lr = (int)(std::find(labs.begin(), labs.end(), nm_st(c->st[a]) | (nm_st(c->st[b]) << 2)) -
+                             labs.begin());
+        for (int q = 0; q < npp; q += step) {
+            const int cc = pr_a(h.pp[q]), dd = pr_b(h.pp[q]);
+            const int lq = (int)(std::find(labs.begin(), labs.end(), nm_st(c->st[cc]) | (nm_st(c->st[dd]) << 2)) -
+                                 labs.begin());
+            double want = 0.0;
+            if (L.nd > 0) {
+                const int sl = slot_of[lq], j = sl >> 1, rc = (L.rec[slot_of[lr]] >> (3 * j)) & 7;
+                const int cf = rc & 3;
+                if (cf != 0) {
+                    const int kk = L.tab[(rc >> 2) & 1];
+                    const auto d2 = [&](int x, int y) {
+                        const int dx = c->nx[x] - c->nx[y], dy = c->ny[x] - c->ny[y], dz = c->nz[x] - c->nz[y];
+                        return dx * dx + dy * dy + dz * dz;
+                    };
+                    const double m = c->u[kk * c->nlut + d2(a, cc)] + c->u[kk * c->nlut + d2(a, dd)];
+                    want = ((cf == 1) == ((sl & 1) == 0)) ? m : -m;
+                }
+            }
+            const double got = nm_vas_host(c, a, b, cc, dd);
+            if (std::fabs(got - want) > 1e-12 * (std::fabs(got) + 1e-300) && got != want) return false;
+        }
+    }
+    // momentum pairs: (p packed, |p|^2 | |q|^2 << 10, slot rows 0 and 1), (slot rows 2 and 3, 0, 0)
+    L.lp_off = (int)(lp.size() / 8);
+    L.n_lp = (int)prl.size();
+    for (size_t P = 0; P < prl.size(); P++) {
+        const int a = pst[P][0], b = pst[P][1];
+        int rows[4] = {-1, -1, -1, -1};
+        for (auto& e : prl[P]) {
+            const int li = (int)(std::find(labs.begin(), labs.end(), e.first) - labs.begin());
+            rows[slot_of[li]] = e.second;
+        }
+        const int p2 = c->nx[a] * c->nx[a] + c->ny[a] * c->ny[a] + c->nz[a] * c->nz[a];
+        const int q2 = c->nx[b] * c->nx[b] + c->ny[b] * c->ny[b] + c->nz[b] * c->nz[b];
+        const int32_t pk = (int32_t)((uint32_t)(uint8_t)(int8_t)c->nx[a] | ((uint32_t)(uint8_t)(int8_t)c->ny[a] << 8) |
+                                     ((uint32_t)(uint8_t)(int8_t)c->nz[a] << 16));
+        const int32_t e[8] = {pk, p2 | (q2 << 10), rows[0], rows[1], rows[2], rows[3], 0, 0};
+        lp.insert(lp.end(), e, e + 8);
+    }
+    return true;
 }
 
 ccd_status nm_plan(ccd_nm_ctx* c) {
@@ -827,18 +1236,44 @@ ccd_status nm_plan(ccd_nm_ctx* c) {
     }
     c->tiles_a = (int)c->tiles.size();
     c->flops_a = c->flops;
-    for (size_t k = 0; k < c->ch.size(); k++) {  // ladders
+    // the pp ladder over momentum pairs where the channel's elements allow it
+    std::vector<std::pair<int, NmLadItem>> lit;
+    std::vector<bool> by_pairs(c->ch.size(), false);
+    std::vector<int32_t> lpall;
+    for (size_t k = 0; k < c->ch.size(); k++) {
+        NmLadD L;
+        const size_t lp0 = lpall.size();
+        if (!nm_ladpp_channel(c, (int)k, L, lpall)) {
+            lpall.resize(lp0);
+            continue;
+        }
+        by_pairs[k] = true;
+        const int li = (int)c->ladd.size();
+        c->ladd.push_back(L);
+        const NmChanD& C = c->chd[k];
+        for (int r0 = 0; r0 < L.n_lp; r0 += kNmLadRows)
+            for (int ct = 0; ct < (C.nhh + 15) / 16; ct++) lit.push_back({L.n_lp, NmLadItem{li, r0 | (ct << 20)}});
+        c->flops_lad += 2.0 * L.nd * L.nk * (double)L.n_lp * L.n_lp * C.nhh;
+    }
+    // the longest items (K extent n_lp) first, so that they do not start last
+    std::stable_sort(lit.begin(), lit.end(), [](const std::pair<int, NmLadItem>& x,
+                                               const std::pair<int, NmLadItem>& y) { return x.first > y.first; });
+    for (auto& e : lit) c->ladit.push_back(e.second);
+    c->ladlp = std::move(lpall);
+    for (size_t k = 0; k < c->ch.size(); k++) {  // ladders (the pp part here only without the pairs form)
         const NmChanD& C = c->chd[k];
         NmJob J = blank();
         J.M = C.npp; J.N = C.nhh; J.nseg = 2;
         J.seg[0].K = C.npp; J.seg[0].amode = AM_GPAIR; J.seg[0].a_rows = C.pp_off; J.seg[0].a_cols = C.pp_off;
-        J.seg[0].b_arr = ARR_T; J.seg[0].b_off = C.t_off; J.seg[0].ldb = C.nhh; J.seg[0].term = CCD_T_PP;
+        J.seg[0].b_arr = ARR_T; J.seg[0].b_off = C.t_off; J.seg[0].ldb = C.nhh;
+        J.seg[0].term = by_pairs[k] ? 0 : CCD_T_PP;
         J.seg[1].K = C.nhh; J.seg[1].amode = AM_ROW; J.seg[1].a_arr = ARR_T; J.seg[1].a_off = C.t_off;
         J.seg[1].lda = C.nhh; J.seg[1].b_arr = ARR_CHH; J.seg[1].b_off = C.chh_off; J.seg[1].ldb = C.nhh;
         J.seg[1].term = CCD_T_HH | CCD_T_QHH;
-        J.omode = OM_ROW; J.o_arr = ARR_LAD; J.o_off = C.t_off; J.ldo = C.nhh;
+        // with the pairs form the pp sums are already in the output (k_nm_ladpp runs first)
+        J.omode = by_pairs[k] ? OM_ROW_ADD : OM_ROW; J.o_arr = ARR_LAD; J.o_off = C.t_off; J.ldo = C.nhh;
         add_tiles(J);
-        c->flops += 2.0 * C.npp * C.npp * C.nhh + 2.0 * C.npp * C.nhh * C.nhh;
+        c->flops += (by_pairs[k] ? 0.0 : 2.0 * C.npp * C.npp * C.nhh) + 2.0 * C.npp * C.nhh * C.nhh;
     }
     {
         int64_t moff = 0;
@@ -868,7 +1303,7 @@ ccd_status nm_plan(ccd_nm_ctx* c) {
 // workspace regions, in order
 enum {
     R_ST, R_U, R_EPS, R_HH, R_PP, R_MEM, R_PMAP, R_CH, R_ITEMS, R_JOBS, R_TILES, R_CSRP, R_CSRI, R_RCH,
-    R_T0, R_T1, R_VT, R_CHH, R_TQ, R_CP, R_LAD, R_RING, R_ROWS, R_COLS, R_DCHI, R_EPART, R_EHIST, R_COUNT
+    R_LADD, R_LADLP, R_LADIT, R_T0, R_T1, R_VT, R_CHH, R_TQ, R_CP, R_LAD, R_RING, R_ROWS, R_COLS, R_DCHI, R_EPART, R_EHIST, R_COUNT
 };
 
 void nm_layout(ccd_nm_ctx* c) {
@@ -877,6 +1312,7 @@ void nm_layout(ccd_nm_ctx* c) {
         4 * c->mem_all.size(), 4 * std::max<size_t>(1, c->pmap.size()), sizeof(NmChanD) * c->chd.size(),
         sizeof(NmItem) * c->items.size(), sizeof(NmJob) * c->jobs.size(), sizeof(NmTile) * c->tiles.size(),
         4 * c->csr_ptr.size(), 4 * std::max<size_t>(1, c->csr_idx.size()), 4 * c->row_chan.size(),
+        sizeof(NmLadD) * c->ladd.size(), 4 * c->ladlp.size(), sizeof(NmLadItem) * c->ladit.size(),
         8 * (size_t)c->n_amp, 8 * (size_t)c->n_amp, 8 * (size_t)c->n_amp, 8 * (size_t)std::max<int64_t>(1, c->n_chh),
         8 * (size_t)std::max<int64_t>(1, c->n_tq), 8 * (size_t)std::max<int64_t>(1, c->n_cp), 8 * (size_t)c->n_amp,
         32 * (size_t)c->n_amp, 8 * (size_t)c->n_rows, 8 * (size_t)c->n_cols, 8 * (size_t)c->ns,
@@ -938,7 +1374,7 @@ extern "C" ccd_status ccd_nm_info_get(const ccd_nm_ctx* c, ccd_nm_info* info) {
     info->max_ph = c->max_ph;
     info->n_amplitudes = c->n_amp;
     info->box_L = c->L;
-    info->flops_per_sweep = c->flops;
+    info->flops_per_sweep = c->flops + c->flops_lad;
     return CCD_OK;
 }
 
@@ -1024,6 +1460,11 @@ ccd_status nm_sweep(ccd_nm_ctx* c, double alpha, uint32_t mask, int slot) {
         NmTimed tm(c, NF_GEMM1);
         k_nm_gemm<<<std::min(c->tiles_a, 8192), 256, 0, s>>>(d, cur, mask, 0, c->tiles_a);
     }
+    if (!c->ladit.empty() && (mask & (CCD_T_PP | CCD_T_HH | CCD_T_QHH))) {
+        // the pp sums of the channels with the pairs form, before the ladder jobs add the rest
+        NmTimed tm(c, NF_LADPP);
+        k_nm_ladpp<<<std::min<int>((int)c->ladit.size(), 4096), 256, 0, s>>>(d, cur, mask, (int)c->ladit.size());
+    }
     if (c->tiles_b > 0) {
         NmTimed tm(c, NF_GEMM2);
         k_nm_gemm<<<std::min(c->tiles_b, 8192), 256, 0, s>>>(d, cur, mask, c->tiles_a, c->tiles_b);
@@ -1075,6 +1516,9 @@ extern "C" ccd_status ccd_nm_bind_workspace(ccd_nm_ctx* c, void* ptr, size_t byt
     NM_TRY(up(R_CSRP, c->csr_ptr.data()));
     if (!c->csr_idx.empty()) NM_TRY(up(R_CSRI, c->csr_idx.data()));
     NM_TRY(up(R_RCH, c->row_chan.data()));
+    if (!c->ladd.empty()) NM_TRY(up(R_LADD, c->ladd.data()));
+    if (!c->ladlp.empty()) NM_TRY(up(R_LADLP, c->ladlp.data()));
+    if (!c->ladit.empty()) NM_TRY(up(R_LADIT, c->ladit.data()));
     NmDev& d = c->dev;
     d.st = (const int32_t*)at(R_ST);
     d.u = (const double*)at(R_U);
@@ -1090,6 +1534,9 @@ extern "C" ccd_status ccd_nm_bind_workspace(ccd_nm_ctx* c, void* ptr, size_t byt
     d.csr_ptr = (const int32_t*)at(R_CSRP);
     d.csr_idx = (const int32_t*)at(R_CSRI);
     d.row_chan = (const int32_t*)at(R_RCH);
+    d.ladd = (const NmLadD*)at(R_LADD);
+    d.ladlp = (const int4*)at(R_LADLP);
+    d.ladit = (const NmLadItem*)at(R_LADIT);
     d.t[0] = (double*)at(R_T0);
     d.t[1] = (double*)at(R_T1);
     d.vt = (double*)at(R_VT);
@@ -1302,7 +1749,10 @@ extern "C" ccd_status ccd_nm_kernel_times(ccd_nm_ctx* c, double* ms, int64_t* la
     for (int f = 0; f < NF_NUM; f++) {
         if (ms) ms[f] = c->fam_ms[f];
         if (launches) launches[f] = c->fam_n[f];
-        if (flops) flops[f] = f == NF_GEMM1 ? c->flops_a : (f == NF_GEMM2 ? c->flops - c->flops_a : 0.0);
+        if (flops)
+            flops[f] = f == NF_GEMM1 ? c->flops_a
+                     : f == NF_GEMM2 ? c->flops - c->flops_a
+                     : f == NF_LADPP ? c->flops_lad : 0.0;
         if (reset) { c->fam_ms[f] = 0.0; c->fam_n[f] = 0; }
     }
     return CCD_OK;

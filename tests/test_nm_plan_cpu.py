@@ -71,3 +71,52 @@ def test_not_closed_shell_refused():
     for A in (2, 8, 30):
         with pytest.raises(ccd.CCDError):
             ccd.NMContext(ccd.nm_problem(A, 4, 0.16))
+
+
+def test_kernel_families():
+    """The timing families in the order the header documents them."""
+    lib = ccd._lib
+    names = [lib.ccd_nm_kernel_name(f).decode() for f in range(8)]
+    assert names == ["gather", "rowcol", "dchi", "gemm_chi", "gemm_ladder_ring", "update", "energy", "ladder_pp"]
+    assert lib.ccd_nm_kernel_name(8) == b"" and lib.ccd_nm_kernel_name(-1) == b""
+
+
+@pytest.mark.parametrize("n2,rho", [(4, 0.16), (20, 0.16), (36, 0.08)])
+def test_neutron_ladder_over_momentum_pairs_matches_the_neutron_path(n2, rho):
+    """With neutrons only the isospin path's pp ladder over momentum pairs
+    (its grouping of each block's rows by the first state's momentum, the
+    pairing of its label pairs and the classes the plan derives) must come to
+    exactly the momentum-pair products of the neutron path: the same pair
+    counts in every block give the same flops, counted independently."""
+    c = ccd.NMContext(ccd.nm_problem(66 if n2 >= 20 else 14, n2, rho, species=1))
+    flops = {k: v[2] for k, v in c.kernel_times().items()}
+    p = ccd.Context([ccd.problem(66 if n2 >= 20 else 14, n2, rho)])
+    assert flops["ladder_pp"] == p.info(0)["flops_pp"]
+    assert flops["ladder_pp"] > 0
+
+
+@pytest.mark.parametrize("A,n2", [(28, 4), (76, 9), (108, 20)])
+def test_every_isospin_block_takes_the_momentum_pair_form(A, n2):
+    """Symmetric matter: every block's pp ladder goes over its momentum pairs,
+    counted here from the exported pair lists: the distinct momenta of the
+    pairs' first states, times the products the block's kind needs (one
+    difference and one element class for S_z = 0 pairs of like particles and
+    |S_z| = 1 pairs of unlike ones, two of each for S_z = T_z = 0, none for
+    |S_z| = |T_z| = 1, where the element vanishes).  A block left to the product
+    over label pairs would be missing from the sum."""
+    c = ccd.NMContext(ccd.nm_problem(A, n2, 0.16))
+    info = c.info()
+    kt = c.kernel_times()
+    blocks = c.export_map(ccd.CCD_NM_MAP_CHANNELS).reshape(info["n_channels"], 7)
+    pp = c.export_map(ccd.CCD_NM_MAP_PP).reshape(-1, 2)
+    st = c.export_map(ccd.CCD_NM_MAP_STATES).reshape(-1, 5)
+    want, row = 0.0, 0
+    for kx, ky, kz, sz2, tz2, nhh, npp in blocks:
+        firsts = {tuple(st[a, :3]) for a in pp[row:row + npp, 0]}
+        row += npp
+        prods = 4 if (sz2, tz2) == (0, 0) else (1 if (sz2 == 0) != (tz2 == 0) else 0)
+        want += 2.0 * prods * len(firsts) ** 2 * nhh
+    assert row == len(pp)
+    assert kt["ladder_pp"][2] == pytest.approx(want, rel=1e-15) and want > 0
+    assert info["flops_per_sweep"] == pytest.approx(kt["gemm_chi"][2] + kt["gemm_ladder_ring"][2] +
+                                                    kt["ladder_pp"][2], rel=1e-15)
