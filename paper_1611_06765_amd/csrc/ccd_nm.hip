@@ -490,9 +490,10 @@ __global__ void __launch_bounds__(256) k_nm_gemm(NmDev d, int cur, uint32_t mask
 //   u_(k, j)(p') = sum_P M_k[p'][P] delta_j(P),  M_k[p'][P] = U_k(|p' - p|^2) + U_k(|p' - q|^2),
 //   delta_j(P) = t(P, X_j) - t(P, Y_j),
 // a square product over the momentum pairs per (class, difference): one for
-// the S_z = 0 blocks of like particles and the |S_z| = 1 blocks of unlike ones,
-// four for the S_z = T_z = 0 blocks, against 4 x 4 and 16 x 16 times the
-// flops of the product over label pairs.  M_k is generated per lane with the
+// the S_z = 0 blocks of like particles and the |S_z| = 1 blocks of unlike ones
+// (n_lp^2 n_hh multiply-adds against the 4 n_lp^2 n_hh of the product over
+// label pairs), four for the S_z = T_z = 0 blocks (against 16 n_lp^2 n_hh),
+// none for |S_z| = |T_z| = 1, where the element vanishes.  M_k is generated per lane with the
 // offsets of the neutron ladder (one sdot4 and three integer ops), the
 // differences are formed when a chunk of kNmKP pairs is staged, and each row
 // takes its combination of the products.  A wave holds one 16-row tile; the
