@@ -4,7 +4,8 @@
 // One Jacobi sweep of eq. ccd3 in the intermediates form (sec. "Developing a
 // CCD code for infinite matter"), every term from the current amplitudes t:
 //   k_nm_gather   T~_Q[(a,i)][(c,k)] = t_ik^ac for every cross channel Q
-//   k_nm_rowcol   row and column sums of t <ab||ij> per direct channel
+//   k_nm_rowcol   row and column sums of t <ab||ij> per direct channel, from
+//   k_nm_colsum   chunks of whole rows (column parts added in chunk order)
 //   k_nm_gemm     (launch 1) chi_klij = <kl||ij> + sum_{c<d} <kl||cd> t_ij^cd per
 //                 direct channel; C_P = <kb||cj>_P + 1/2 Vbar T~_Q per cross
 //                 channel (chi_kbcj of the ring of Q, P = -Q)
@@ -117,6 +118,13 @@ struct NmItem {
 struct NmChanD {
     int64_t t_off;
     int32_t nhh, npp, hh_off, pp_off, chh_off;
+    int32_t rc_lo, rc_n;   // its row-chunk items of the row and column sums
+};
+
+// a chunk of whole rows of a block for the row and column sums; its column
+// parts (n_hh of them) start at poff
+struct NmRcItem {
+    int32_t chan, r0, nr, poff;
 };
 
 // arrays a product reads or writes
@@ -175,6 +183,8 @@ struct NmDev {
     const int32_t* pmap;    // ring position maps
     const NmChanD* ch;
     const NmItem* items;
+    const NmRcItem* rcit;   // row chunks of the row and column sums
+    double* cpart;          // their column parts
     const NmJob* jobs;
     const NmTile* tiles;
     const NmLadD* ladd;     // pp ladder over momentum pairs: channels,
@@ -293,32 +303,50 @@ __global__ void __launch_bounds__(256) k_nm_gather(NmDev d, int cur) {
     }
 }
 
-// row sums (one thread per row) and column sums (one wave per column) of t vt
-__global__ void __launch_bounds__(256) k_nm_rowcol(NmDev d, int cur, int n_chan, int n_rows, int n_cols) {
+// row and column sums of t <ab||ij> per block, from chunks of whole rows (at
+// most kNmChunk amplitudes) loaded with coalesced reads: the products in LDS,
+// then each row's sum in column order and each column's part over the chunk's
+// rows in row order; k_nm_colsum adds a column's parts in chunk order.
+__global__ void __launch_bounds__(256) k_nm_rowcol(NmDev d, int cur, int n_items) {
+    __shared__ double ps[kNmChunk];
     const double* t = d.t[cur];
-    // rows: a grid-stride loop over global rows; row_chan maps rows then columns
-    for (int r = blockIdx.x * 256 + threadIdx.x; r < n_rows; r += gridDim.x * 256) {
-        const int c = d.row_chan[r];
-        const NmChanD C = d.ch[c];
-        const int lr = r - C.pp_off;
-        const int64_t o = C.t_off + (int64_t)lr * C.nhh;
-        double s = 0.0;
-        for (int x = 0; x < C.nhh; x++) s += t[o + x] * d.vt[o + x];
-        d.rowsum[r] = s;
+    for (int bi = blockIdx.x; bi < n_items; bi += gridDim.x) {
+        const NmRcItem it = d.rcit[bi];
+        const NmChanD C = d.ch[it.chan];
+        const int nhh = C.nhh, ne = it.nr * nhh;
+        const int64_t o = C.t_off + (int64_t)it.r0 * nhh;
+        if (ne > kNmChunk) {  // one row longer than the buffer (nr = 1): straight from memory
+            for (int q = threadIdx.x; q < nhh; q += 256) d.cpart[it.poff + q] = t[o + q] * d.vt[o + q];
+            if (threadIdx.x == 0) {
+                double s = 0.0;
+                for (int x = 0; x < nhh; x++) s += t[o + x] * d.vt[o + x];
+                d.rowsum[C.pp_off + it.r0] = s;
+            }
+            continue;
+        }
+        __syncthreads();  // the previous item's reads of ps are done
+        for (int x = threadIdx.x; x < ne; x += 256) ps[x] = t[o + x] * d.vt[o + x];
+        __syncthreads();
+        for (int r = threadIdx.x; r < it.nr; r += 256) {
+            double s = 0.0;
+            for (int x = 0; x < nhh; x++) s += ps[r * nhh + x];
+            d.rowsum[C.pp_off + it.r0 + r] = s;
+        }
+        for (int q = threadIdx.x; q < nhh; q += 256) {
+            double s = 0.0;
+            for (int r = 0; r < it.nr; r++) s += ps[r * nhh + q];
+            d.cpart[it.poff + q] = s;
+        }
     }
-    const int lane = threadIdx.x & 63;
-    const int wid = (blockIdx.x * 256 + threadIdx.x) >> 6, nw = (gridDim.x * 256) >> 6;
-    for (int q = wid; q < n_cols; q += nw) {
-        const int c = d.row_chan[n_rows + q];
-        const NmChanD C = d.ch[c];
+}
+
+__global__ void __launch_bounds__(256) k_nm_colsum(NmDev d, int n_rows, int n_cols) {
+    for (int q = blockIdx.x * 256 + threadIdx.x; q < n_cols; q += gridDim.x * 256) {
+        const NmChanD C = d.ch[d.row_chan[n_rows + q]];
         const int lc = q - C.hh_off;
         double s = 0.0;
-        for (int r = lane; r < C.npp; r += 64) {
-            const int64_t o = C.t_off + (int64_t)r * C.nhh + lc;
-            s += t[o] * d.vt[o];
-        }
-        s = nm_wave_sum(s);
-        if (lane == 0) d.colsum[q] = s;
+        for (int i = 0; i < C.rc_n; i++) s += d.cpart[d.rcit[C.rc_lo + i].poff + lc];
+        d.colsum[q] = s;
     }
 }
 
@@ -797,6 +825,8 @@ struct ccd_nm_ctx {
     std::vector<int32_t> hh_all, pp_all, mem_all, pmap, csr_ptr, csr_idx, row_chan;
     std::vector<NmChanD> chd;
     std::vector<NmItem> items;
+    std::vector<NmRcItem> rcit;
+    int64_t n_cpart = 0;
     std::vector<NmJob> jobs;
     std::vector<NmTile> tiles;
     int tiles_a = 0, tiles_b = 0;  // tiles of the first launch, then of the second
@@ -1102,6 +1132,16 @@ ccd_status nm_plan(ccd_nm_ctx* c) {
         d.hh_off = h.hh_off;
         d.pp_off = h.pp_off;
         d.chh_off = (int32_t)h.chh_off;
+        d.rc_lo = (int32_t)c->rcit.size();
+        {
+            const int R = std::max(1, kNmChunk / d.nhh);
+            for (int r0 = 0; r0 < d.npp; r0 += R) {
+                const int nr = std::min(R, d.npp - r0);
+                c->rcit.push_back({(int32_t)k, r0, nr, (int32_t)c->n_cpart});
+                c->n_cpart += d.nhh;
+            }
+        }
+        d.rc_n = (int32_t)c->rcit.size() - d.rc_lo;
         c->chd.push_back(d);
         for (int64_t s0 = 0; s0 < (int64_t)d.nhh * d.npp; s0 += kNmChunk) c->items.push_back({(int32_t)k, (int32_t)s0});
     }
@@ -1304,7 +1344,8 @@ ccd_status nm_plan(ccd_nm_ctx* c) {
 // workspace regions, in order
 enum {
     R_ST, R_U, R_EPS, R_HH, R_PP, R_MEM, R_PMAP, R_CH, R_ITEMS, R_JOBS, R_TILES, R_CSRP, R_CSRI, R_RCH,
-    R_LADD, R_LADLP, R_LADIT, R_T0, R_T1, R_VT, R_CHH, R_TQ, R_CP, R_LAD, R_RING, R_ROWS, R_COLS, R_DCHI, R_EPART, R_EHIST, R_COUNT
+    R_LADD, R_LADLP, R_LADIT, R_RCIT, R_T0, R_T1, R_VT, R_CHH, R_TQ, R_CP, R_LAD, R_RING, R_ROWS, R_COLS, R_CPART,
+    R_DCHI, R_EPART, R_EHIST, R_COUNT
 };
 
 void nm_layout(ccd_nm_ctx* c) {
@@ -1314,9 +1355,11 @@ void nm_layout(ccd_nm_ctx* c) {
         sizeof(NmItem) * c->items.size(), sizeof(NmJob) * c->jobs.size(), sizeof(NmTile) * c->tiles.size(),
         4 * c->csr_ptr.size(), 4 * std::max<size_t>(1, c->csr_idx.size()), 4 * c->row_chan.size(),
         sizeof(NmLadD) * c->ladd.size(), 4 * c->ladlp.size(), sizeof(NmLadItem) * c->ladit.size(),
+        sizeof(NmRcItem) * c->rcit.size(),
         8 * (size_t)c->n_amp, 8 * (size_t)c->n_amp, 8 * (size_t)c->n_amp, 8 * (size_t)std::max<int64_t>(1, c->n_chh),
         8 * (size_t)std::max<int64_t>(1, c->n_tq), 8 * (size_t)std::max<int64_t>(1, c->n_cp), 8 * (size_t)c->n_amp,
-        32 * (size_t)c->n_amp, 8 * (size_t)c->n_rows, 8 * (size_t)c->n_cols, 8 * (size_t)c->ns,
+        32 * (size_t)c->n_amp, 8 * (size_t)c->n_rows, 8 * (size_t)c->n_cols, 8 * (size_t)std::max<int64_t>(1, c->n_cpart),
+        8 * (size_t)c->ns,
         8 * c->items.size(), 8 * (size_t)kNmHist};
     c->region.clear();
     size_t off = 0;
@@ -1450,8 +1493,8 @@ ccd_status nm_sweep(ccd_nm_ctx* c, double alpha, uint32_t mask, int slot) {
     }
     {
         NmTimed tm(c, NF_ROWCOL);
-        k_nm_rowcol<<<nm_grid(std::max(c->n_rows, c->n_cols * 64), 256), 256, 0, s>>>(d, cur, (int)c->ch.size(),
-                                                                                      c->n_rows, c->n_cols);
+        k_nm_rowcol<<<std::min<int>((int)c->rcit.size(), 8192), 256, 0, s>>>(d, cur, (int)c->rcit.size());
+        k_nm_colsum<<<nm_grid(c->n_cols, 256), 256, 0, s>>>(d, c->n_rows, c->n_cols);
     }
     {
         NmTimed tm(c, NF_DCHI);
@@ -1520,6 +1563,7 @@ extern "C" ccd_status ccd_nm_bind_workspace(ccd_nm_ctx* c, void* ptr, size_t byt
     if (!c->ladd.empty()) NM_TRY(up(R_LADD, c->ladd.data()));
     if (!c->ladlp.empty()) NM_TRY(up(R_LADLP, c->ladlp.data()));
     if (!c->ladit.empty()) NM_TRY(up(R_LADIT, c->ladit.data()));
+    NM_TRY(up(R_RCIT, c->rcit.data()));
     NmDev& d = c->dev;
     d.st = (const int32_t*)at(R_ST);
     d.u = (const double*)at(R_U);
@@ -1538,6 +1582,8 @@ extern "C" ccd_status ccd_nm_bind_workspace(ccd_nm_ctx* c, void* ptr, size_t byt
     d.ladd = (const NmLadD*)at(R_LADD);
     d.ladlp = (const int4*)at(R_LADLP);
     d.ladit = (const NmLadItem*)at(R_LADIT);
+    d.rcit = (const NmRcItem*)at(R_RCIT);
+    d.cpart = (double*)at(R_CPART);
     d.t[0] = (double*)at(R_T0);
     d.t[1] = (double*)at(R_T1);
     d.vt = (double*)at(R_VT);
