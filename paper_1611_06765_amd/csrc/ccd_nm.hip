@@ -340,12 +340,24 @@ __global__ void __launch_bounds__(256) k_nm_rowcol(NmDev d, int cur, int n_items
     }
 }
 
+// a block's chunks are consecutive and each holds n_hh parts, so the parts of
+// column lc are n_hh apart from the first chunk's; eight loads are issued
+// before they are added in chunk order
 __global__ void __launch_bounds__(256) k_nm_colsum(NmDev d, int n_rows, int n_cols) {
     for (int q = blockIdx.x * 256 + threadIdx.x; q < n_cols; q += gridDim.x * 256) {
         const NmChanD C = d.ch[d.row_chan[n_rows + q]];
-        const int lc = q - C.hh_off;
+        const double* pc = d.cpart + d.rcit[C.rc_lo].poff + (q - C.hh_off);
+        const int n = C.rc_n, step = C.nhh;
         double s = 0.0;
-        for (int i = 0; i < C.rc_n; i++) s += d.cpart[d.rcit[C.rc_lo + i].poff + lc];
+        int i = 0;
+        for (; i + 8 <= n; i += 8) {
+            double v[8];
+#pragma unroll
+            for (int k = 0; k < 8; k++) v[k] = pc[(int64_t)(i + k) * step];
+#pragma unroll
+            for (int k = 0; k < 8; k++) s += v[k];
+        }
+        for (; i < n; i++) s += pc[(int64_t)i * step];
         d.colsum[q] = s;
     }
 }
