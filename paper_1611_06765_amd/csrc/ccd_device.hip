@@ -2638,8 +2638,9 @@ static ccd_status run_phase(ccd_ctx* c, const ccd_solver_opts* o, int prec, doub
                         // rule 1 stops after two sweeps with |dE| r / (1 - r) < thr
                         const double target = rule == 1 ? thr * (1.0 - rate) / rate : thr;
                         const int extra = rule == 1 ? 2 : 1;
-                        need = de < target ? extra
-                                           : (int)std::floor(std::log(target / de) / std::log(rate)) + extra;
+                        // (clamped before the cast: a rate near 1 gives a huge count)
+                        const double k = de < target ? 0.0 : std::floor(std::log(target / de) / std::log(rate));
+                        need = k >= (double)every ? every : (int)k + extra;
                     }
                     next = std::max(next, std::min(std::max(need, 1), every));
                     d_then[sl] = de;
