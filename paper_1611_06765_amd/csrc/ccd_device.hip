@@ -2618,7 +2618,9 @@ static ccd_status run_phase(ccd_ctx* c, const ccd_solver_opts* o, int prec, doub
                         e_hist[(size_t)p * o->max_iter + k] = hb[(size_t)sl * kHistCap + k % kHistCap];
                 if (act[sl]) all_done = false;
             }
-            if (stops && used + 1 >= min_sweeps) {
+            // (with graph replay every chunk length is a graph of its own to
+            // capture, so the chunks keep the one length there)
+            if (stops && !graph && used + 1 >= min_sweeps) {
                 next = 0;
                 for (int sl = 0; sl < P; sl++) {
                     if (!act[sl]) continue;
