@@ -74,6 +74,28 @@ def test_check_every_does_not_change_convergence():
         assert a.energy(p) == b.energy(p)
 
 
+@pytest.mark.parametrize("precision,mixed_tol,rule", [(0, 0.0, 0), (0, 0.0, 1), (2, 1e-2, 1)])
+def test_chunk_lengths_do_not_change_the_solve(precision, mixed_tol, rule):
+    """The host shortens a chunk of sweeps to the sweeps it predicts the
+    slowest live problem still needs (no graph replay); the device alone
+    decides when each problem stops, so reading its flags after every sweep,
+    every 8 sweeps with that prediction, or once per 64 gives the same sweep
+    counts, energy histories and energies, in FP64 and in a BF16 phase with
+    FP64 refinement (two phases, each with its own prediction)."""
+    probs = [ccd.problem(*x) for x in MIXED_SET[:3]]
+    out = []
+    for every in (1, 8, 64):
+        c = _ctx(probs)
+        r = c.iterate(mixing=0.5, tol=0.0, tol_rel=1e-9, stop_rule=rule, max_iter=300, history=True,
+                      check_every=every, precision=precision, mixed_tol=mixed_tol, refine_sweeps=2)
+        assert r["status"] == ccd.CCD_OK
+        out.append((r, [c.energy(p) for p in range(len(probs))]))
+    for r, e in out[1:]:
+        assert np.array_equal(out[0][0]["sweeps"], r["sweeps"])
+        assert np.array_equal(out[0][0]["history"], r["history"], equal_nan=True)
+        assert out[0][1] == e
+
+
 TABLES = [
     [1, 1, 1, 1, 1, 1, 0, 0, 0, 0],
     [2, 2, 2, 2, 2, 2, 1, 1, 1, 1],
