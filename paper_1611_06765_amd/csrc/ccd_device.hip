@@ -1825,8 +1825,11 @@ static std::vector<Item> xcd_order(std::vector<std::pair<int, Item>> v, int u = 
 
 // The same for items of uneven cost: the eight pieces are cut at equal shares
 // of the total cost (still contiguous in problem order), and inside a piece the
-// costliest items come first, so long items do not start last.
-static std::vector<Item> xcd_order_cost(const std::vector<std::pair<int, Item>>& v, const std::vector<double>& cost) {
+// costliest items come first, so long items do not start last (with
+// per_problem, costliest first within each problem's run of the piece, so
+// the piece still works through one problem's data at a time).
+static std::vector<Item> xcd_order_cost(const std::vector<std::pair<int, Item>>& v, const std::vector<double>& cost,
+                                        bool per_problem = false) {
     std::vector<size_t> idx(v.size());
     for (size_t k = 0; k < idx.size(); k++) idx[k] = k;
     std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return v[a].first < v[b].first; });
@@ -1841,7 +1844,10 @@ static std::vector<Item> xcd_order_cost(const std::vector<std::pair<int, Item>>&
     }
     size_t per = 0;
     for (auto& pc : piece) {
-        std::stable_sort(pc.begin(), pc.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
+        std::stable_sort(pc.begin(), pc.end(), [&](size_t a, size_t b) {
+            if (per_problem && v[a].first != v[b].first) return v[a].first < v[b].first;
+            return cost[a] > cost[b];
+        });
         per = std::max(per, pc.size());
     }
     std::vector<Item> out(per * 8, Item{-1, 0});
@@ -1867,7 +1873,7 @@ static ccd_status assemble(ccd_ctx* c) {
     c->prob_t0.assign(P, 0);
     c->slot_of.assign(P, 0);
     std::vector<std::pair<int, Item>> lg, ue, dir, dsum, rs, rb[4];
-    std::vector<double> lg_cost, dir_cost;
+    std::vector<double> lg_cost, dir_cost, rb_cost[4];
     int64_t t_base = 0;
     int gi = 0, slot0 = 0;
     for (auto& kv : by_structure) {
@@ -2049,7 +2055,12 @@ static ccd_status assemble(ccd_ctx* c) {
                 const int nb = std::max(h.n, dp.m);  // the pair's padded order
                 for (int g = 0; g < D.G; g++) {
                     if (nb <= 16) rs.push_back({slot0 + g, Item{pid, g}});
-                    else rb[((nb + 15) >> 4) - 2].push_back({slot0 + g, Item{pid, g}});
+                    else {
+                        // an item's gather grows with n m, its products with n m (n + m)
+                        const int k = ((nb + 15) >> 4) - 2;
+                        rb[k].push_back({slot0 + g, Item{pid, g}});
+                        rb_cost[k].push_back((double)h.n * dp.m * (h.n + dp.m + 16));
+                    }
                 }
             }
             c->dph.push_back(dp);
@@ -2078,7 +2089,12 @@ static ccd_status assemble(ccd_ctx* c) {
     c->it_ring_s = xcd_order(rs, 4);
     c->it_ring_b.clear();
     for (int k = 0; k < 4; k++) {
-        std::vector<Item> o = xcd_order(rb[k]);
+        // a bucket that fits one round of two blocks per compute unit ends with
+        // its longest item: its pieces are cut at equal cost, costliest first;
+        // over several rounds the problem and pair order keeps the L2 working set
+        // of a piece smaller (10 problems at N=66, n^2<=20: ring32 46 -> 50 us
+        // in cost order)
+        std::vector<Item> o = rb[k].size() <= 512 ? xcd_order_cost(rb[k], rb_cost[k], true) : xcd_order(rb[k]);
         c->ring_lo[k] = (int)c->it_ring_b.size();
         c->ring_n[k] = (int)o.size();
         c->it_ring_b.insert(c->it_ring_b.end(), o.begin(), o.end());
