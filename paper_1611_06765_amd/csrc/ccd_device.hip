@@ -1530,7 +1530,7 @@ __global__ void __launch_bounds__(256, 3) k_ladder64(DevPtrs d, int cur, uint32_
 }
 
 // the update of every amplitude per (elementwise item, problem):
-// R = <ab||ij> + ladder sums (S_z = 0) + ring slots + one-body terms,
+// R = <ab||ij> (S_z = 0) + ladder sums (S_z = 0) + ring slots + one-body terms,
 // t_new = R / eps_ij^ab, mixing, and the energy partial of the item
 __global__ void __launch_bounds__(256) k_update(DevPtrs d, int cur, double alpha, uint32_t mask, int n_items) {
     __shared__ double sh[4];
@@ -1556,7 +1556,9 @@ __global__ void __launch_bounds__(256) k_update(DevPtrs d, int cur, double alpha
             const int e = it.start + threadIdx.x + 256 * k;
             if (e < nel && e < it.start + kElemChunk) {
                 const int64_t E = T0 + e;
-                const double tc = d.t[cur][E], v = d.vt[E];
+                // <ab||ij> = 0 in S_z = +-1 blocks (two neutrons interact only
+                // in the spin singlet), so only S_z = 0 blocks read it
+                const double tc = d.t[cur][E], v = c.sz == 0 ? d.vt[E] : 0.0;
                 double tm = tc;
                 if (act) {
                     const int r = e / c.nhh, col = e - r * c.nhh;
