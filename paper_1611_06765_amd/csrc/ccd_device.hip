@@ -18,7 +18,8 @@
 //             (k_ladder64 in FP64)
 //   k_update  every amplitude: <ab||ij> + ladder sums + ring slots + one-body
 //             terms, t_new = R / eps_ij^ab, linear mixing, energy partial sums
-//   k_energy  deterministic per-problem energy and convergence flag
+//   k_energy  deterministic per-problem energy and convergence flag (inside a
+//             run of sweeps: the last blocks of the next sweep's k_direct)
 // Problems with the same (N, nmax2, twist) form a group that shares the integer
 // tables (states, pair lists, position maps, work lists); the sweep kernels'
 // work items are (item, problem) pairs over them, and the work lists are cut
@@ -404,6 +405,41 @@ __global__ void __launch_bounds__(256, 3) k_warm(DevPtrs d, int cur, const float
 // --------------------------------------------------------------------------
 // sweep kernels
 // --------------------------------------------------------------------------
+// per-problem energy after a sweep, convergence test, divergence flag (block p
+// of k_energy, or the last blocks of the next sweep's k_direct launch)
+// rule 0: stop when |dE_n| < tol + tol_rel |E_n| (the paper's test); rule 1:
+// the geometric-tail estimate |dE_n| r / (1 - r), r = |dE_n / dE_(n-1)|, of the
+// remaining change must also be below the same threshold (r < 1), in two
+// consecutive sweeps (a turning point of E_n makes one |dE| small)
+__device__ __forceinline__ void energy_of(const DevPtrs& d, int p, double tol, double tol_rel, int rule, double* sh) {
+    const DevGroup G = d.groups[d.pgrp[p]];
+    const int g = d.pgi[p], n = G.elem_hi - G.elem_lo;
+    const double* part = d.epart_elem + G.eelem_base + g * n;
+    double s = 0.0;
+    for (int x = threadIdx.x; x < n; x += 256) s += part[x];
+    double e = block_sum256(s, sh);
+    if (threadIdx.x == 0 && d.active[p]) {
+        double old = d.ecorr[p];
+        d.eprev[p] = old;
+        d.ecorr[p] = e;
+        d.ehist[(size_t)p * kHistCap + d.sweeps[p] % kHistCap] = e;
+        d.sweeps[p] += 1;
+        if (!isfinite(e)) d.active[p] = 0;
+        else if (tol > 0.0 || tol_rel > 0.0) {
+            const double de = fabs(e - old), thr = tol + tol_rel * fabs(e), dp = d.dprev[p];
+            bool stop = de < thr;
+            if (rule == 1) {
+                const double r = dp > 0.0 ? de / dp : 1.0;
+                const bool pass = stop && r < 1.0 && de * r < thr * (1.0 - r);
+                d.streak[p] = pass ? d.streak[p] + 1 : 0;
+                stop = d.streak[p] >= 2;
+            }
+            if (stop) d.active[p] = 0;
+        }
+        d.dprev[p] = fabs(e - old);
+    }
+}
+
 
 // per (item of kDirSplit particle-pair rows of an S_z = 0 channel, problem):
 // row sums of t v, the item's part of 1/2 sum_cd <kl||cd> t_ij^cd on MFMA over
@@ -418,21 +454,35 @@ __global__ void __launch_bounds__(256, 3) k_warm(DevPtrs d, int cur, const float
 // tiles w, w+4, ...  k_dsum adds the items' parts in item order.
 constexpr int kDirBuf = 2048;  // doubles per staged operand
 template <int P>
-__global__ void __launch_bounds__(256) k_direct(DevPtrs d, int cur, uint32_t mask, int n_items) {
+__global__ void __launch_bounds__(256) k_direct(DevPtrs d, int cur, uint32_t mask, int n_items, int nd, int energy,
+                                                double tol, double tol_rel, int rule) {
     using E = double;
     using AT = typename std::conditional<P == P_F64, d4, f4>::type;
     constexpr int PM = P == P_F64 ? P_F64 : P_F32;   // contraction precision used here
     __shared__ __attribute__((aligned(16))) E vs[kDirBuf];
     __shared__ __attribute__((aligned(16))) E ts[kDirBuf];
     __shared__ AT red[3][64];  // partial tiles of waves 1..3
-    for (int bi = blockIdx.x; bi < n_items; bi += gridDim.x) {
+    __shared__ int live_s;
+    // blocks nd .. nd + P - 1 (energy set): the previous sweep's energy step,
+    // one problem each; it only reads the previous update's partial sums
+    if (energy && (int)blockIdx.x >= nd) {
+        energy_of(d, blockIdx.x - nd, tol, tol_rel, rule, vs);
+        return;
+    }
+    for (int bi = blockIdx.x; bi < n_items; bi += nd) {
     const Item it = d.it_direct[bi];
     if (it.chan < 0) continue;
     const Item sub = d.it_dsub[it.chan];
     const DevChan c = d.chans[sub.chan];
     const DevGroup G = d.groups[c.group];
     const int g = it.start;
-    if (!d.active[G.p0 + g]) continue;
+    // the problem's flag, read once for the block: an energy block of this
+    // launch may clear it meanwhile, and waves that read it at different
+    // times would otherwise take different paths through the barriers below
+    __syncthreads();  // the previous item's readers of live_s are done
+    if (threadIdx.x == 0) live_s = d.active[G.p0 + g];
+    __syncthreads();
+    if (!live_s) continue;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int nhh = c.nhh, npp = c.npp, nt = (nhh + 15) >> 4, ntt = nt * nt;
     const int ld = nt * 16 + 1;                    // staging row stride
@@ -1577,40 +1627,9 @@ __global__ void __launch_bounds__(256) k_update(DevPtrs d, int cur, double alpha
     }
 }
 
-// per-problem energy after a sweep, convergence test, divergence flag
-// rule 0: stop when |dE_n| < tol + tol_rel |E_n| (the paper's test); rule 1:
-// the geometric-tail estimate |dE_n| r / (1 - r), r = |dE_n / dE_(n-1)|, of the
-// remaining change must also be below the same threshold (r < 1), in two
-// consecutive sweeps (a turning point of E_n makes one |dE| small)
 __global__ void __launch_bounds__(256) k_energy(DevPtrs d, double tol, double tol_rel, int rule) {
     __shared__ double sh[4];
-    const int p = blockIdx.x;
-    const DevGroup G = d.groups[d.pgrp[p]];
-    const int g = d.pgi[p], n = G.elem_hi - G.elem_lo;
-    const double* part = d.epart_elem + G.eelem_base + g * n;
-    double s = 0.0;
-    for (int x = threadIdx.x; x < n; x += 256) s += part[x];
-    double e = block_sum256(s, sh);
-    if (threadIdx.x == 0 && d.active[p]) {
-        double old = d.ecorr[p];
-        d.eprev[p] = old;
-        d.ecorr[p] = e;
-        d.ehist[(size_t)p * kHistCap + d.sweeps[p] % kHistCap] = e;
-        d.sweeps[p] += 1;
-        if (!isfinite(e)) d.active[p] = 0;
-        else if (tol > 0.0 || tol_rel > 0.0) {
-            const double de = fabs(e - old), thr = tol + tol_rel * fabs(e), dp = d.dprev[p];
-            bool stop = de < thr;
-            if (rule == 1) {
-                const double r = dp > 0.0 ? de / dp : 1.0;
-                const bool pass = stop && r < 1.0 && de * r < thr * (1.0 - r);
-                d.streak[p] = pass ? d.streak[p] + 1 : 0;
-                stop = d.streak[p] >= 2;
-            }
-            if (stop) d.active[p] = 0;
-        }
-        d.dprev[p] = fabs(e - old);
-    }
+    energy_of(d, blockIdx.x, tol, tol_rel, rule, sh);
 }
 
 // --------------------------------------------------------------------------
@@ -1686,6 +1705,11 @@ struct ccd_ctx {
     hipStream_t aux[3] = {nullptr, nullptr, nullptr};
     hipEvent_t ev_fork = nullptr, ev_mid = nullptr, ev_join[3] = {nullptr, nullptr, nullptr};
     bool aux_ok = false;
+    // inside run_sweeps (kernel timing off) a sweep's energy step is left to
+    // the next sweep's k_direct launch, or to the end of the run
+    bool defer_energy = false, energy_pending = false;
+    double pend_tol = 0.0, pend_tol_rel = 0.0;
+    int pend_rule = 0;
     std::vector<GraphEntry> graphs;
 };
 
@@ -2180,11 +2204,28 @@ static int grid_for(const ccd_ctx* c, int slot, int nb) {
     return std::min(nb, m * 256);
 }
 
+// the energy step left over from the previous sweep, as its own launch
+static ccd_status flush_energy(ccd_ctx* c, const DevPtrs& d) {
+    if (!c->energy_pending) return CCD_OK;
+    c->energy_pending = false;
+    LAUNCH(F_ENERGY, k_energy, (int)c->probs.size(), 256, 0, d, c->pend_tol, c->pend_tol_rel, c->pend_rule);
+    return CCD_OK;
+}
+
 template <int P>
 static ccd_status L_direct(ccd_ctx* c, const DevPtrs& d, int cur, uint32_t mask) {
     const int n = (int)c->it_direct.size(), ns = (int)c->it_dsum.size();
-    if (mask & (CCD_T_QHH | CCD_T_QHOLE | CCD_T_QPART))
-        LAUNCH(F_DIRECT, k_direct<P>, grid_for(c, CCD_TUNE_DIRECT, n), 256, 0, d, cur, mask, n);
+    if (mask & (CCD_T_QHH | CCD_T_QHOLE | CCD_T_QPART)) {
+        const int nd = grid_for(c, CCD_TUNE_DIRECT, n);
+        if (c->energy_pending && nd > 0) {
+            // the previous sweep's energy step rides on this launch (its last blocks)
+            c->energy_pending = false;
+            LAUNCH(F_DIRECT, k_direct<P>, nd + (int)c->probs.size(), 256, 0, d, cur, mask, n, nd, 1, c->pend_tol,
+                   c->pend_tol_rel, c->pend_rule);
+        } else {
+            LAUNCH(F_DIRECT, k_direct<P>, nd, 256, 0, d, cur, mask, n, nd, 0, 0.0, 0.0, 0);
+        }
+    }
     if (mask & (CCD_T_HH | CCD_T_QHH | CCD_T_QHOLE))
         LAUNCH(F_DSUM, k_dsum, ns, 256, 0, d, mask, ns);
     return CCD_OK;
@@ -2274,6 +2315,12 @@ template <int P>
 static ccd_status launch_contractions(ccd_ctx* c, const DevPtrs& d, int cur, uint32_t mask) {
     const bool fork = c->aux_ok && !c->timing;
     ccd_status s = CCD_OK;
+    // a pending energy step that no k_direct launch of this sweep can carry
+    // runs first, on its own
+    if (c->energy_pending && !((mask & (CCD_T_QHH | CCD_T_QHOLE | CCD_T_QPART)) && !c->it_direct.empty())) {
+        s = flush_energy(c, d);
+        if (s != CCD_OK) return s;
+    }
     if (fork) {
         HIP_TRY(hipEventRecord(c->ev_fork, c->stream));
         for (int k = 0; k < 2; k++) HIP_TRY(hipStreamWaitEvent(c->aux[k], c->ev_fork, 0));
@@ -2348,7 +2395,19 @@ static ccd_status sweep(ccd_ctx* c, double alpha, double tol, double tol_rel, in
     if (s != CCD_OK) return s;
     s = L_update(c, d, cur, alpha, mask);
     if (s != CCD_OK) return s;
-    LAUNCH(F_ENERGY, k_energy, (int)c->probs.size(), 256, 0, d, tol, tol_rel, rule);
+    s = flush_energy(c, d);  // not left by a k_direct launch of this sweep (none)
+    if (s != CCD_OK) return s;
+    if (c->defer_energy && !c->timing) {
+        // the energy step of this sweep rides on the next sweep's k_direct launch
+        // (or runs at the end of the run), so that nothing sits between this
+        // update and the next sweep's fork
+        c->energy_pending = true;
+        c->pend_tol = tol;
+        c->pend_tol_rel = tol_rel;
+        c->pend_rule = rule;
+    } else {
+        LAUNCH(F_ENERGY, k_energy, (int)c->probs.size(), 256, 0, d, tol, tol_rel, rule);
+    }
     c->cur ^= 1;
     return CCD_OK;
 }
@@ -2356,14 +2415,22 @@ static ccd_status sweep(ccd_ctx* c, double alpha, double tol, double tol_rel, in
 // n sweeps: launched one by one, or (graph) as one replay of a captured graph
 // of the same n sweeps; kernel timing disables the graph
 static constexpr size_t kMaxGraphs = 4;
+// the energy steps of a run's sweeps are deferred (see sweep) and the last one
+// is launched before the run returns
+struct DeferEnergy {
+    ccd_ctx* c;
+    explicit DeferEnergy(ccd_ctx* cc) : c(cc) { c->defer_energy = true; c->energy_pending = false; }
+    ~DeferEnergy() { c->defer_energy = false; c->energy_pending = false; }
+};
 static ccd_status run_sweeps(ccd_ctx* c, int n, double alpha, double tol, double tol_rel, int rule, uint32_t mask,
                              int prec, bool graph) {
+    DeferEnergy de(c);
     if (!graph || c->timing) {
         for (int k = 0; k < n; k++) {
             ccd_status s = sweep(c, alpha, tol, tol_rel, rule, mask, prec);
             if (s != CCD_OK) return s;
         }
-        return CCD_OK;
+        return flush_energy(c, make_ptrs(c));
     }
     GraphEntry* ge = nullptr;
     for (GraphEntry& g : c->graphs)
@@ -2378,6 +2445,8 @@ static ccd_status run_sweeps(ccd_ctx* c, int n, double alpha, double tol, double
         c->stream = c->cap_stream;
         ccd_status s = CCD_OK;
         for (int k = 0; k < n && s == CCD_OK; k++) s = sweep(c, alpha, tol, tol_rel, rule, mask, prec);
+        if (s == CCD_OK) s = flush_energy(c, make_ptrs(c));  // inside the captured graph
+        c->energy_pending = false;
         hipGraph_t gr = nullptr;
         const hipError_t ec = hipStreamEndCapture(c->cap_stream, &gr);
         c->stream = user;

@@ -123,6 +123,35 @@ def test_launch_shapes_bit_identical(prec):
             assert np.array_equal(x, y), tab
 
 
+def test_problems_stopping_at_different_sweeps_under_every_launch_shape():
+    """Inside a run the energy step of a sweep (which clears the flag of a
+    problem that has converged) runs as extra blocks of the next sweep's
+    chi_klij launch, beside that launch's own items and the rings.  With
+    problems stopping at different sweeps, persistent grids (workgroups that
+    take several items) and flags read every sweep or every 8 sweeps, every
+    sweep count, energy history and energy equals that of the default shapes
+    with the flags read after every sweep."""
+    probs = [ccd.problem(n, n2, rho) for n, n2 in ((14, 8), (38, 12), (54, 16), (66, 20))
+             for rho in (0.05, 0.1, 0.2)]
+
+    def solve(tab, every, graph=False):
+        c = _ctx(probs)
+        c.set_tuning(tab)
+        r = c.iterate(mixing=0.5, tol=0.0, tol_rel=1e-9, stop_rule=1, max_iter=300, history=True,
+                      check_every=every, graph=graph)
+        assert r["status"] == ccd.CCD_OK
+        return r, [c.energy(p) for p in range(len(probs))]
+
+    ref, e_ref = solve([0] * ccd.CCD_TUNE_LEN, 1)
+    assert len(set(ref["sweeps"].tolist())) > 3  # the problems stop at different sweeps
+    for tab in [[0] * ccd.CCD_TUNE_LEN] + TABLES:
+        for every, graph in ((1, False), (8, False), (8, True)):
+            r, e = solve(tab, every, graph)
+            assert np.array_equal(ref["sweeps"], r["sweeps"]), (tab, every, graph)
+            assert np.array_equal(ref["history"], r["history"], equal_nan=True), (tab, every, graph)
+            assert e_ref == e, (tab, every, graph)
+
+
 def test_autotune_keeps_the_iteration():
     probs = [ccd.problem(*x) for x in MIXED_SET]
     ref = _ctx(probs)
